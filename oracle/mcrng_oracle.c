@@ -1,0 +1,620 @@
+/*
+ * CPU oracle for hash- vs stride-seeded LCG streams driving a 1-D slab
+ * Monte Carlo transport loop (Cuneo & Variansyah, "An Alternative to
+ * Stride-Based RNG for Monte Carlo Transport", arXiv 2403.06362).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
+ * statement of what the GPU library computes.  Only the test suite, the smoke
+ * check and the CPU-baseline leg of the benchmark load it.  It shares no code,
+ * header, table or constant with the HIP library, and the library never
+ * calls it.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fno-fast-math -fPIC -shared
+ * (no FMA contraction, IEEE double and single arithmetic, round-to-nearest).
+ *
+ * Sections of the paper each function follows:
+ *   lcg step ............ Sec. "Linear Congruential Generator", eq. (1)
+ *   skip-ahead .......... Sec. "Parallel LCG with Seed Striding", eq. (2)
+ *   stride allocation ... same section: unit u_k starts at X_{Qk}
+ *   hash(k, s) .......... Sec. "Parallel LCG with Seed Hashing", Listing 1
+ *   seed splitting ...... Sec. "Seed Splitting", eq. (3): S_k = hash(k, s)
+ *   hierarchical seeds .. Sec. "Hierarchical Seed Splitting", eq. (4)
+ * The transport loop, the uniform mapping, the logarithm and the fixed-point
+ * tally are readings of points the paper leaves open; each is stated where
+ * it is implemented.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stddef.h>
+#include <string.h>
+#include <stdlib.h>
+
+typedef unsigned __int128 u128;
+
+/* ------------------------------------------------------------------ */
+/* LCG, eq. (1): X_{n+1} = (g X_n + c) mod 2^m; the new state is also the
+ * generator's output. */
+/* ------------------------------------------------------------------ */
+
+static uint64_t mask_of(uint32_t m)
+{
+    return (m >= 64) ? ~(uint64_t)0 : (((uint64_t)1 << m) - 1);
+}
+
+uint64_t orc_lcg_next(uint64_t x, uint64_t g, uint64_t c, uint32_t m)
+{
+    /* exact product in 128 bits, then reduce modulo 2^m */
+    u128 full = (u128)g * (u128)x + (u128)c;
+    return (uint64_t)full & mask_of(m);
+}
+
+/* ------------------------------------------------------------------ */
+/* Skip-ahead, eq. (2).  X_k = G_k X_0 + C_k (mod 2^m) with
+ *   G_k = prod_j (g^{2^j})^{k_(j)},   C_k = c (1 + g + ... + g^{k-1}),
+ * where k_(j) is bit j of k.  Both factors are built in O(m) steps by
+ * walking the bits of k with the 2^j-step map (g^{2^j}, c(1+...+g^{2^j-1})),
+ * which doubles as  g_{2h} = g_h^2,  c_{2h} = c_h (1 + g_h).
+ * (As printed, eq. (2) omits X_0 from the first term; it is the X_0 = 1
+ * case of the affine form used here.) */
+/* ------------------------------------------------------------------ */
+
+void orc_skip_coeffs(uint64_t k, uint64_t g, uint64_t c, uint32_t m,
+                     uint64_t *G_out, uint64_t *C_out)
+{
+    const uint64_t msk = mask_of(m);
+    uint64_t G = 1 & msk, C = 0;     /* map for the bits of k consumed so far */
+    uint64_t gj = g & msk, cj = c & msk;  /* map for 2^j steps */
+    for (int j = 0; j < 64; ++j) {
+        if ((k >> j) & 1) {
+            /* X -> gj (G X + C) + cj */
+            G = (uint64_t)((u128)gj * G) & msk;
+            C = (uint64_t)((u128)gj * C + cj) & msk;
+        }
+        cj = (uint64_t)((u128)cj * (u128)(gj + 1)) & msk;
+        gj = (uint64_t)((u128)gj * gj) & msk;
+    }
+    *G_out = G;
+    *C_out = C;
+}
+
+uint64_t orc_skip(uint64_t x0, uint64_t k, uint64_t g, uint64_t c, uint32_t m)
+{
+    uint64_t G, C;
+    orc_skip_coeffs(k, g, c, m, &G, &C);
+    return (uint64_t)((u128)G * x0 + C) & mask_of(m);
+}
+
+/* ------------------------------------------------------------------ */
+/* Listing 1: the modified 64-bit MurmurHash with one 64-bit key and one
+ * 64-bit seed; all arithmetic is modulo 2^64 (wrapping multiplies). */
+/* ------------------------------------------------------------------ */
+
+static const uint64_t MURMUR_M = 0xC6A4A7935BD1E995ull;
+
+uint64_t orc_subhash(uint64_t x)
+{
+    uint64_t y = x * MURMUR_M;
+    return y ^ (y >> 47);
+}
+
+uint64_t orc_hash(uint64_t k, uint64_t s)
+{
+    uint64_t seed_hash = orc_subhash(s ^ (8 * MURMUR_M));
+    return orc_subhash(seed_hash ^ (orc_subhash(k) * MURMUR_M));
+}
+
+/* ------------------------------------------------------------------ */
+/* Stream start states.
+ *  stride: unit with global 0-based index i starts at X_{Q i}
+ *          (Sec. "Parallel LCG with Seed Striding"; X_0 is the base seed).
+ *  hash:   S_k = hash(k, s) with the 1-based key k = i + 1 (eq. 3); with a
+ *          group key p, the parent is hash(p, s) first (eq. 4, the group id
+ *          is hashed first).  The 64-bit hash is reduced modulo 2^m to give
+ *          an LCG state (the paper seeds an m-bit generator with a 64-bit
+ *          hash without saying how; reduction modulo 2^m is the reading). */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    uint64_t g, c;
+    uint32_t m;
+    uint32_t pad_;
+} orc_lcg;
+
+enum { ORC_SEED_STRIDE = 0, ORC_SEED_HASH = 1 };
+
+typedef struct {
+    uint32_t kind;       /* ORC_SEED_STRIDE or ORC_SEED_HASH */
+    uint32_t hier;       /* hash only: 1 => parent = hash(group_key, base) */
+    uint64_t base;       /* stride: X_0; hash: global seed s */
+    uint64_t stride;     /* stride only: Q */
+    uint64_t first_index;/* global 0-based index of this set's stream 0 */
+    uint64_t group_key;  /* hash with hier = 1: the group (problem/batch) id */
+} orc_seeding;
+
+uint64_t orc_stream_start(const orc_lcg *L, const orc_seeding *S, uint64_t i)
+{
+    const uint64_t idx = S->first_index + i;
+    if (S->kind == ORC_SEED_STRIDE) {
+        /* k = Q * idx; the cycle length 2^m divides 2^64, so the product
+         * may wrap modulo 2^64 without changing X_k */
+        return orc_skip(S->base & mask_of(L->m), S->stride * idx, L->g, L->c, L->m);
+    }
+    uint64_t parent = S->hier ? orc_hash(S->group_key, S->base) : S->base;
+    return orc_hash(idx + 1, parent) & mask_of(L->m);
+}
+
+void orc_init_streams(const orc_lcg *L, const orc_seeding *S, uint64_t n, uint64_t *out)
+{
+    for (uint64_t i = 0; i < n; ++i)
+        out[i] = orc_stream_start(L, S, i);
+}
+
+/* Draw microbenchmark: stream i takes count[i] LCG steps from its start
+ * state; its checksum is the sum of the outputs X_1..X_count modulo 2^64.
+ * With S == NULL the start states are read from state_inout instead.  The
+ * final states go back to state_inout when it is not NULL. */
+void orc_seed_and_draw(const orc_lcg *L, const orc_seeding *S, uint64_t n,
+                       const uint32_t *count, uint64_t *state_inout,
+                       uint64_t *checksum)
+{
+    for (uint64_t i = 0; i < n; ++i) {
+        uint64_t x = S ? orc_stream_start(L, S, i) : state_inout[i];
+        uint64_t sum = 0;
+        for (uint32_t d = 0; d < count[i]; ++d) {
+            x = orc_lcg_next(x, L->g, L->c, L->m);
+            sum += x;
+        }
+        checksum[i] = sum;
+        if (state_inout)
+            state_inout[i] = x;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Uniform from a state (reading; the paper does not give the mapping):
+ * the top 53 of the m state bits, plus one, times 2^-53.  The result is an
+ * exact double in (0, 1], so -ln(u) is always finite.  Requires m >= 53. */
+/* ------------------------------------------------------------------ */
+
+double orc_uniform(uint64_t x, uint32_t m)
+{
+    uint64_t top = x >> (m - 53);
+    return (double)(top + 1) * 0x1p-53;
+}
+
+/* ------------------------------------------------------------------ */
+/* Natural logarithm with a fixed operation sequence (reading; the paper
+ * does not fix the flight-sampling arithmetic, and bit-exact tallies need
+ * the same rounded result on every device).  Textbook route:
+ *   u = f 2^e with f in [1,2); if f >= 3/2 then f <- f/2, e <- e+1, so that
+ *   f = 1 + a with a in [-1/4, 1/2);  s = a/(2+a);  ln(1+a) = 2 atanh(s)
+ *   = 2s + sum_{k>=1} 2 s^{2k+1}/(2k+1)   (Taylor series of atanh),
+ *   and 2s = a - a s, so  ln(1+a) = a - s (a - h),  h = sum_{k>=1} 2 s^{2k}/(2k+1);
+ *   ln u = e ln2 + ln(1+a), with ln 2 split as LN2_HI + LN2_LO where
+ *   LN2_HI holds ln 2 truncated to 40 fraction bits (so e LN2_HI is exact)
+ *   and LN2_LO is the double nearest to ln 2 - LN2_HI.
+ * Every step is one IEEE double operation rounded to nearest, in this order,
+ * with no fused multiply-add:
+ *   a = f - 1;  b = 2 + a;  s = a / b;  w = s * s;
+ *   p = 2/(2K+1);  for k = K-1 .. 1:  p = p * w;  p = p + 2/(2k+1);
+ *   h = w * p;  t = a - h;  c = s * t;  l = a - c;
+ *   r = l + (double)e * LN2_LO;   result = (double)e * LN2_HI + r
+ * with K = 11; the series coefficients are the correctly rounded quotients
+ * 2/(2k+1). */
+/* ------------------------------------------------------------------ */
+
+#define ORC_LN_K 11
+
+double orc_ln(double u)
+{
+    const double LN2_HI = 0x1.62e42fefa2000p-1;
+    const double LN2_LO = 0x1.9ef35793c7673p-41;
+    int ex;
+    double fr = frexp(u, &ex);      /* u = fr 2^ex, fr in [1/2, 1) */
+    double f = fr * 2.0;            /* exact */
+    int e = ex - 1;
+    if (f >= 1.5) {
+        f = f * 0.5;                /* exact */
+        e = e + 1;
+    }
+    double a = f - 1.0;             /* exact */
+    double b = 2.0 + a;
+    double s = a / b;
+    double w = s * s;
+    double p = 2.0 / (double)(2 * ORC_LN_K + 1);
+    for (int k = ORC_LN_K - 1; k >= 1; --k) {
+        p = p * w;
+        p = p + 2.0 / (double)(2 * k + 1);
+    }
+    double h = w * p;
+    double t = a - h;
+    double c = s * t;
+    double l = a - c;
+    double r = l + (double)e * LN2_LO;
+    return (double)e * LN2_HI + r;
+}
+
+/* ------------------------------------------------------------------ */
+/* Fixed-source 1-D slab transport.
+ *
+ * Geometry: cells are the intervals between the merged, increasing edges
+ * of material regions and tally bins; each cell has one total cross
+ * section sigma_t, one scattering ratio c and one space tally bin.  With
+ * n_time_bins > 0 the problem is time dependent at particle speed 1; the
+ * last time edge is the census time.
+ *
+ * One history (readings of points the paper leaves open):
+ *   start at the left face, x = E[0], mu = +1, t = T[0], cell 0;
+ *   tau = -ln(u) remaining optical depth to the next collision.
+ *   step:  s_col  = tau / sigma_t[cell]
+ *          s_edge = (E[cell+1]-x)/mu (mu>0), (E[cell]-x)/mu (mu<0), inf (mu=0)
+ *          s_time = T[tb+1] - t                     (time dependent only)
+ *          the smallest wins; on equal distances collision beats edge and
+ *          edge beats time (strict-less updates in that order);
+ *   score  track length s into (batch, time bin, space bin);
+ *   t += s (clamped to T[tb+1]);  tau -= sigma_t s (clamped at 0);
+ *   edge:  move onto the crossed edge; leaving E[0] or E[last] leaks;
+ *   time:  x += mu s (clamped into the cell); t = T[tb+1]; next time bin;
+ *          passing the last time edge ends the history at census;
+ *   collision: x += mu s (clamped into the cell); draw u1: scatter if
+ *          u1 < c[cell], else absorbed; on scatter draw u2 -> mu = 2 u2 - 1
+ *          (isotropic in the slab), draw u3 -> tau = -ln(u3).
+ *
+ * Tally (reading: bit-reproducible track-length sums).  Each track length
+ * s is quantised once to q = round-half-even(s 2^56) (an integer, exact
+ * because s < 2^7 is enforced by the caller) and summed exactly as a
+ * 128-bit integer.  The flux of a bin is (sum q) 2^-56 / (N dx [dt]).
+ *
+ * FP32 flight mode: tau is computed in double by orc_ln and rounded once
+ * to float; mu = 2 u2 - 1 is computed in double (exact) and rounded once
+ * to float; s, x, mu, t, sigma_t and the edges are floats (edges and
+ * sigma_t rounded once from the double inputs); every distance, position
+ * and time operation is one IEEE single operation.  The absorption test
+ * u1 < c stays in double; q is computed from (double)s.
+ */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t n_cells;
+    int32_t n_space_bins;
+    int32_t n_time_bins;      /* 0 => steady state */
+    uint32_t n_batches;       /* >= 1 */
+    const double *edges;      /* n_cells + 1 */
+    const double *sigma_t;    /* n_cells */
+    const double *scatter;    /* n_cells */
+    const int32_t *bin;       /* n_cells: space bin of each cell */
+    const double *t_edges;    /* n_time_bins + 1, or NULL */
+    uint64_t n_histories;     /* N of the whole problem (sets batch size) */
+    orc_lcg lcg;
+    orc_seeding seeding;
+} orc_problem;
+
+enum {
+    ORC_D_HISTORIES = 0, ORC_D_LEAK_LEFT, ORC_D_LEAK_RIGHT, ORC_D_ABSORBED,
+    ORC_D_CENSUS, ORC_D_EVENTS, ORC_D_COLLISIONS, ORC_D_DRAWS,
+    ORC_D_MAX_DRAWS, ORC_D_OVER_STRIDE, ORC_NDIAG
+};
+
+enum { EV_COLL = 0, EV_EDGE = 1, EV_TIME = 2 };
+
+typedef struct {
+    int32_t type;    /* EV_COLL, EV_EDGE or EV_TIME */
+    int32_t cell;    /* cell the step was taken in */
+    int32_t tbin;
+    int32_t pad_;
+    double s;        /* track length of the step */
+} orc_event;
+
+typedef struct {
+    uint64_t x;              /* LCG state */
+    const orc_lcg *lcg;
+    const double *script;    /* when not NULL: uniforms are read from here */
+    uint64_t n_script, pos;
+    uint64_t draws;
+    int exhausted;
+} orc_rng;
+
+static double rng_draw(orc_rng *R)
+{
+    R->draws++;
+    if (R->script) {
+        if (R->pos >= R->n_script) {
+            R->exhausted = 1;
+            return 0.5;
+        }
+        return R->script[R->pos++];
+    }
+    R->x = orc_lcg_next(R->x, R->lcg->g, R->lcg->c, R->lcg->m);
+    return orc_uniform(R->x, R->lcg->m);
+}
+
+static u128 quantise(double s)
+{
+    double v = rint(s * 0x1p56);   /* s * 2^56 is exact; rint rounds half-even */
+    return (u128)(uint64_t)v;
+}
+
+typedef struct {
+    orc_event *log;
+    uint64_t cap, n;
+} orc_log;
+
+static void log_event(orc_log *lg, int type, int cell, int tb, double s)
+{
+    if (!lg || !lg->log) return;
+    if (lg->n < lg->cap) {
+        orc_event *e = &lg->log[lg->n];
+        e->type = type; e->cell = cell; e->tbin = tb; e->pad_ = 0; e->s = s;
+    }
+    lg->n++;
+}
+
+static void history_f64(const orc_problem *P, orc_rng *R, u128 *T, uint64_t *d, orc_log *lg)
+{
+    const int nc = P->n_cells, nt = P->n_time_bins, nsb = P->n_space_bins;
+    const int timed = nt > 0;
+    double x = P->edges[0], mu = 1.0, t = timed ? P->t_edges[0] : 0.0;
+    int cell = 0, tb = 0;
+    double tau = -orc_ln(rng_draw(R));
+    for (;;) {
+        const double sig = P->sigma_t[cell];
+        double s = tau / sig;
+        int ev = EV_COLL;
+        double se;
+        if (mu > 0.0)
+            se = (P->edges[cell + 1] - x) / mu;
+        else if (mu < 0.0)
+            se = (P->edges[cell] - x) / mu;
+        else
+            se = INFINITY;
+        if (se < s) { s = se; ev = EV_EDGE; }
+        if (timed) {
+            double st = P->t_edges[tb + 1] - t;
+            if (st < s) { s = st; ev = EV_TIME; }
+        }
+        T[(size_t)tb * nsb + P->bin[cell]] += quantise(s);
+        d[ORC_D_EVENTS]++;
+        log_event(lg, ev, cell, tb, s);
+        if (timed) {
+            t = t + s;
+            if (t > P->t_edges[tb + 1]) t = P->t_edges[tb + 1];
+        }
+        double dtau = sig * s;
+        tau = tau - dtau;
+        if (tau < 0.0) tau = 0.0;
+        if (ev == EV_EDGE) {
+            if (mu > 0.0) {
+                cell = cell + 1;
+                if (cell == nc) { d[ORC_D_LEAK_RIGHT]++; break; }
+                x = P->edges[cell];
+            } else {
+                x = P->edges[cell];
+                cell = cell - 1;
+                if (cell < 0) { d[ORC_D_LEAK_LEFT]++; break; }
+            }
+            continue;
+        }
+        double step = mu * s;
+        double nx = x + step;
+        if (nx < P->edges[cell]) nx = P->edges[cell];
+        if (nx > P->edges[cell + 1]) nx = P->edges[cell + 1];
+        x = nx;
+        if (ev == EV_TIME) {
+            tb = tb + 1;
+            t = P->t_edges[tb];
+            if (tb == nt) { d[ORC_D_CENSUS]++; break; }
+            continue;
+        }
+        d[ORC_D_COLLISIONS]++;
+        double u1 = rng_draw(R);
+        if (!(u1 < P->scatter[cell])) { d[ORC_D_ABSORBED]++; break; }
+        double u2 = rng_draw(R);
+        mu = 2.0 * u2 - 1.0;
+        double u3 = rng_draw(R);
+        tau = -orc_ln(u3);
+    }
+}
+
+static void history_f32(const orc_problem *P, const float *E, const float *SG, const float *TE,
+                        orc_rng *R, u128 *T, uint64_t *d, orc_log *lg)
+{
+    const int nc = P->n_cells, nt = P->n_time_bins, nsb = P->n_space_bins;
+    const int timed = nt > 0;
+    float x = E[0], mu = 1.0f, t = timed ? TE[0] : 0.0f;
+    int cell = 0, tb = 0;
+    float tau = (float)(-orc_ln(rng_draw(R)));
+    for (;;) {
+        const float sig = SG[cell];
+        float s = tau / sig;
+        int ev = EV_COLL;
+        float se;
+        if (mu > 0.0f)
+            se = (E[cell + 1] - x) / mu;
+        else if (mu < 0.0f)
+            se = (E[cell] - x) / mu;
+        else
+            se = INFINITY;
+        if (se < s) { s = se; ev = EV_EDGE; }
+        if (timed) {
+            float st = TE[tb + 1] - t;
+            if (st < s) { s = st; ev = EV_TIME; }
+        }
+        T[(size_t)tb * nsb + P->bin[cell]] += quantise((double)s);
+        d[ORC_D_EVENTS]++;
+        log_event(lg, ev, cell, tb, (double)s);
+        if (timed) {
+            t = t + s;
+            if (t > TE[tb + 1]) t = TE[tb + 1];
+        }
+        float dtau = sig * s;
+        tau = tau - dtau;
+        if (tau < 0.0f) tau = 0.0f;
+        if (ev == EV_EDGE) {
+            if (mu > 0.0f) {
+                cell = cell + 1;
+                if (cell == nc) { d[ORC_D_LEAK_RIGHT]++; break; }
+                x = E[cell];
+            } else {
+                x = E[cell];
+                cell = cell - 1;
+                if (cell < 0) { d[ORC_D_LEAK_LEFT]++; break; }
+            }
+            continue;
+        }
+        float step = mu * s;
+        float nx = x + step;
+        if (nx < E[cell]) nx = E[cell];
+        if (nx > E[cell + 1]) nx = E[cell + 1];
+        x = nx;
+        if (ev == EV_TIME) {
+            tb = tb + 1;
+            t = TE[tb];
+            if (tb == nt) { d[ORC_D_CENSUS]++; break; }
+            continue;
+        }
+        d[ORC_D_COLLISIONS]++;
+        double u1 = rng_draw(R);
+        if (!(u1 < P->scatter[cell])) { d[ORC_D_ABSORBED]++; break; }
+        double u2 = rng_draw(R);
+        mu = (float)(2.0 * u2 - 1.0);
+        double u3 = rng_draw(R);
+        tau = (float)(-orc_ln(u3));
+    }
+}
+
+/* Tally slice sizes: per batch, n_time_bins' x n_space_bins, with
+ * n_time_bins' = max(n_time_bins, 1). */
+static size_t slice_bins(const orc_problem *P)
+{
+    size_t ntb = P->n_time_bins > 0 ? (size_t)P->n_time_bins : 1;
+    return ntb * (size_t)P->n_space_bins;
+}
+
+/* History j (0-based within the problem) belongs to batch
+ * floor(j / ceil(N / n_batches)). */
+static uint64_t batch_of(const orc_problem *P, uint64_t j)
+{
+    uint64_t nb = P->n_batches ? P->n_batches : 1;
+    uint64_t bs = (P->n_histories + nb - 1) / nb;
+    if (bs == 0) bs = 1;
+    return j / bs;
+}
+
+static void update_diag_history(const orc_problem *P, uint64_t *d, uint64_t draws)
+{
+    d[ORC_D_HISTORIES]++;
+    d[ORC_D_DRAWS] += draws;
+    if (draws > d[ORC_D_MAX_DRAWS]) d[ORC_D_MAX_DRAWS] = draws;
+    if (P->seeding.kind == ORC_SEED_STRIDE && draws > P->seeding.stride)
+        d[ORC_D_OVER_STRIDE]++;
+}
+
+/* Runs histories j0 .. j1-1 of the problem and ADDS their tallies into
+ * tally_lo/tally_hi (each 128-bit bin sum split in two 64-bit words; the
+ * arrays hold n_batches x slice_bins entries) and their counts into diag
+ * (ORC_NDIAG words; ORC_D_MAX_DRAWS is a maximum).  float_mode selects the
+ * FP32 flight arithmetic.  Returns 0, or -1 on a bad argument. */
+int orc_transport(const orc_problem *P, int float_mode, uint64_t j0, uint64_t j1,
+                  uint64_t *tally_lo, uint64_t *tally_hi, uint64_t *diag)
+{
+    if (!P || !tally_lo || !tally_hi || !diag) return -1;
+    if (P->n_cells < 1 || P->n_space_bins < 1 || P->n_time_bins < 0) return -1;
+    if (P->lcg.m < 53 || P->lcg.m > 64) return -1;
+    const size_t sb = slice_bins(P);
+    const size_t nb = P->n_batches ? P->n_batches : 1;
+    const int nc = P->n_cells, nt = P->n_time_bins;
+    const size_t need = sb * nb;
+    /* 128-bit accumulators for this call, added into the caller's words at the end */
+    u128 *acc = (u128 *)calloc(need, sizeof(u128));
+    float *f32 = (float *)calloc((size_t)(2 * nc + nt + 3), sizeof(float));
+    if (!acc || !f32) { free(acc); free(f32); return -1; }
+    /* FP32 mode copies: edges (nc+1), sigma_t (nc), time edges (nt+1) */
+    float *E32 = f32, *SG32 = f32 + nc + 1, *TE32 = f32 + 2 * nc + 1;
+    for (int i = 0; i <= nc; ++i) E32[i] = (float)P->edges[i];
+    for (int i = 0; i < nc; ++i) SG32[i] = (float)P->sigma_t[i];
+    for (int i = 0; nt > 0 && i <= nt; ++i) TE32[i] = (float)P->t_edges[i];
+    for (uint64_t j = j0; j < j1; ++j) {
+        orc_rng R;
+        memset(&R, 0, sizeof R);
+        R.lcg = &P->lcg;
+        R.x = orc_stream_start(&P->lcg, &P->seeding, j);
+        u128 *T = acc + (size_t)batch_of(P, j) * sb;
+        if (float_mode)
+            history_f32(P, E32, SG32, TE32, &R, T, diag, NULL);
+        else
+            history_f64(P, &R, T, diag, NULL);
+        update_diag_history(P, diag, R.draws);
+    }
+    for (size_t i = 0; i < need; ++i) {
+        u128 cur = ((u128)tally_hi[i] << 64) | tally_lo[i];
+        cur += acc[i];
+        tally_lo[i] = (uint64_t)cur;
+        tally_hi[i] = (uint64_t)(cur >> 64);
+    }
+    free(acc);
+    free(f32);
+    return 0;
+}
+
+/* One history driven by a given list of uniforms instead of an LCG (for
+ * unit tests of the transport steps).  Tallies of that one history go to
+ * tally_lo/tally_hi (one slice, overwritten), its events to log (up to
+ * log_cap entries; *log_n receives the full count).  Returns the number of
+ * uniforms consumed, or -1 if the script ran out or an argument is bad. */
+int64_t orc_transport_scripted(const orc_problem *P, int float_mode,
+                               const double *u, uint64_t n_u,
+                               uint64_t *tally_lo, uint64_t *tally_hi, uint64_t *diag,
+                               orc_event *log, uint64_t log_cap, uint64_t *log_n)
+{
+    if (!P || !u || !tally_lo || !tally_hi || !diag) return -1;
+    const size_t sb = slice_bins(P);
+    const int nc = P->n_cells, nt = P->n_time_bins;
+    u128 T[4096];
+    if (sb > 4096) return -1;
+    memset(T, 0, sizeof T);
+    orc_rng R;
+    memset(&R, 0, sizeof R);
+    R.lcg = &P->lcg;
+    R.script = u;
+    R.n_script = n_u;
+    orc_log lg = { log, log_cap, 0 };
+    if (float_mode) {
+        float *f32 = (float *)calloc((size_t)(2 * nc + nt + 3), sizeof(float));
+        if (!f32) return -1;
+        float *E32 = f32, *SG32 = f32 + nc + 1, *TE32 = f32 + 2 * nc + 1;
+        for (int i = 0; i <= nc; ++i) E32[i] = (float)P->edges[i];
+        for (int i = 0; i < nc; ++i) SG32[i] = (float)P->sigma_t[i];
+        for (int i = 0; nt > 0 && i <= nt; ++i) TE32[i] = (float)P->t_edges[i];
+        history_f32(P, E32, SG32, TE32, &R, T, diag, &lg);
+        free(f32);
+    } else {
+        history_f64(P, &R, T, diag, &lg);
+    }
+    update_diag_history(P, diag, R.draws);
+    for (size_t i = 0; i < sb; ++i) {
+        tally_lo[i] = (uint64_t)T[i];
+        tally_hi[i] = (uint64_t)(T[i] >> 64);
+    }
+    if (log_n) *log_n = lg.n;
+    if (R.exhausted) return -1;
+    return (int64_t)R.pos;
+}
+
+/* 128-bit unsigned integer to double, rounded to nearest, ties to even:
+ * the plain definition is "the double nearest to the integer"; long double
+ * is not used so that the rounding is explicit. */
+double orc_u128_to_f64(uint64_t lo, uint64_t hi)
+{
+    u128 v = ((u128)hi << 64) | lo;
+    if (v == 0) return 0.0;
+    int nbits = 128;
+    while (!((v >> (nbits - 1)) & 1)) --nbits;   /* bit length */
+    if (nbits <= 53) return (double)(uint64_t)v;
+    int sh = nbits - 53;
+    u128 mant = v >> sh;
+    u128 rem = v - (mant << sh);
+    u128 half = (u128)1 << (sh - 1);
+    if (rem > half || (rem == half && (mant & 1))) mant += 1;
+    /* mant may have become 2^53: ldexp handles it exactly */
+    return ldexp((double)(uint64_t)mant, sh);
+}
