@@ -1,0 +1,228 @@
+/*
+ * mcrng.h - C ABI of the MI355X (gfx950) library for hash- and
+ * stride-seeded LCG random-number streams driving a fixed-source 1-D slab
+ * Monte Carlo transport loop.
+ *
+ * Method: Cuneo & Variansyah, "An Alternative to Stride-Based RNG for Monte
+ * Carlo Transport" (arXiv 2403.06362).
+ *
+ * Conventions for every entry point:
+ *   - Pointers named d_* are device pointers (HIP device memory on the
+ *     current device); every other pointer is a host pointer.  The caller
+ *     owns all of them.  Host arrays are read during the call only.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Device work is enqueued on it asynchronously; the call returns once
+ *     the work is enqueued, not when it has finished.
+ *   - Return value: MCRNG_OK (0) or a positive warning on success, a
+ *     negative MCRNG_E* code on failure.  On failure nothing is enqueued
+ *     and mcrng_last_error() (thread-local) describes the cause.  No C++
+ *     exception crosses this interface.
+ *   - Unless stated otherwise, calls that use one device are not safe to run
+ *     concurrently from several threads on the same mcrng_ctx.
+ */
+#ifndef MCRNG_H
+#define MCRNG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MCRNG_ABI_VERSION 1
+
+enum {
+    MCRNG_OK = 0,
+    MCRNG_WSTRIDE_WRAP = 1,   /* success; a stride allocation wraps the cycle (N Q > 2^m) */
+    MCRNG_EINVAL = -1,        /* bad argument (null pointer, size, malformed geometry) */
+    MCRNG_ENOMEM = -2,        /* device or host allocation failed */
+    MCRNG_EDEVICE = -3,       /* HIP runtime error (no device, launch failure) */
+    MCRNG_ERANGE = -4,        /* a track length could reach 2^7, the fixed-point tally range */
+    MCRNG_ESTATE = -5         /* call order: reduce_tallies before any run_histories */
+};
+
+/* ------------------------------------------------------------------ */
+/* Generator and stream seeding                                        */
+/* ------------------------------------------------------------------ */
+
+/* LCG of Sec. "Linear Congruential Generator", eq. (1):
+ *   X_{n+1} = (g X_n + c) mod 2^m,  the new state is also the output.
+ * Requires 1 <= m <= 64 (the transport needs m >= 53: a uniform takes the
+ * top 53 state bits).  The workloads use g = 2806196910506780709, c = 1,
+ * m = 63. */
+typedef struct {
+    uint64_t g;
+    uint64_t c;
+    uint32_t m;
+    uint32_t reserved;   /* must be 0 */
+} mcrng_lcg;
+
+enum { MCRNG_SEED_STRIDE = 0, MCRNG_SEED_HASH = 1 };
+
+/* Where stream i (0-based, global index first_index + i) starts.
+ *   MCRNG_SEED_STRIDE: X_{Q (first_index + i)} with X_0 = base and Q = stride
+ *     (Sec. "Parallel LCG with Seed Striding": unit u_k is assigned X_{Qk};
+ *     the skip-ahead is eq. (2)).
+ *   MCRNG_SEED_HASH: hash(first_index + i + 1, parent) mod 2^m, with
+ *     parent = base, or parent = hash(group_key, base) when hier = 1
+ *     (Listing 1 for hash(k, s); eq. (3) seed splitting with 1-based keys;
+ *     eq. (4) hierarchical splitting, the group id hashed first). */
+typedef struct {
+    uint32_t kind;         /* MCRNG_SEED_STRIDE or MCRNG_SEED_HASH */
+    uint32_t hier;         /* hash only: 1 = hash the group key first */
+    uint64_t base;         /* stride: X_0; hash: the seed s */
+    uint64_t stride;       /* stride only: Q >= 1 */
+    uint64_t first_index;  /* global index of this set's stream 0 */
+    uint64_t group_key;    /* hash with hier = 1: the group (problem/batch) id */
+} mcrng_seeding;
+
+/* Writes the start state of streams 0..n-1 to d_state[0..n-1] (uint64,
+ * state in the low m bits).  n = 0 is a no-op.  Returns MCRNG_WSTRIDE_WRAP
+ * when a stride allocation passes 2^m states (allocations wrap around the
+ * cycle, Sec. "Parallel LCG with Seed Striding"); the states are written
+ * all the same. */
+int mcrng_init_streams(const mcrng_lcg *lcg, const mcrng_seeding *seeding, uint64_t n,
+                       uint64_t *d_state, void *stream);
+
+/* Draw microbenchmark and stream advance.  Stream i takes d_count[i] LCG
+ * steps (eq. (1)) from its start state and d_checksum[i] receives the sum
+ * of its outputs X_1 .. X_count modulo 2^64 (0 for count 0).
+ *   seeding != NULL: start states come from the seeding (fused seed + draw);
+ *                    d_state may be NULL, else it receives the final states.
+ *   seeding == NULL: start states are read from d_state, which receives the
+ *                    final states (in place).
+ * d_count: n uint32; d_checksum: n uint64.  n = 0 is a no-op. */
+int mcrng_draw(const mcrng_lcg *lcg, const mcrng_seeding *seeding, uint64_t n,
+               const uint32_t *d_count, uint64_t *d_state, uint64_t *d_checksum, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Slab transport                                                      */
+/* ------------------------------------------------------------------ */
+
+/* One fixed-source slab problem.  The source is mono-directional (mu = +1)
+ * at the left face x = region_edges[0], at t = time_edges[0] (or t = 0);
+ * both faces are vacuum.  Cells are the intervals between the merged
+ * region and bin edges.  History j (0-based) uses stream j of `seeding`
+ * and belongs to batch floor(j / ceil(n_histories / n_batches)).
+ * Host arrays:
+ *   region_edges  n_regions + 1, strictly increasing
+ *   sigma_t       n_regions, > 0 (total cross section)
+ *   scatter       n_regions, in [0, 1] (scattering ratio c)
+ *   bin_edges     n_space_bins + 1, strictly increasing, same first and
+ *                 last value as region_edges
+ *   time_edges    n_time_bins + 1, strictly increasing (the last is the
+ *                 census time), or NULL with n_time_bins = 0 (steady state) */
+typedef struct {
+    uint32_t n_regions;
+    uint32_t n_space_bins;
+    uint32_t n_time_bins;
+    uint32_t n_batches;          /* >= 1 */
+    const double *region_edges;
+    const double *sigma_t;
+    const double *scatter;
+    const double *bin_edges;
+    const double *time_edges;
+    uint64_t n_histories;
+    mcrng_seeding seeding;
+} mcrng_problem;
+
+enum { MCRNG_FP64 = 0, MCRNG_FP32 = 1 };
+enum { MCRNG_SCHED_HISTORY = 0, MCRNG_SCHED_EVENT = 1 };
+
+/* Launch options.  Zero means "default" for every field.  No option changes
+ * any result bit: tallies are exact integers, so every schedule, block
+ * size, histories-per-lane and tally tiling gives the same output.
+ *   precision       MCRNG_FP64, or MCRNG_FP32 (flight, direction, position
+ *                   and time in single precision; -ln(u) and tallies stay
+ *                   exact / double; a different, also deterministic result)
+ *   schedule        history-based persistent kernel, or event-sorted
+ *                   particle bank (one event per particle per launch)
+ *   block           threads per block: 64, 128, 256, 512 or 1024
+ *   hist_per_lane   histories each lane carries at once: 1, 2 or 4
+ *   unit_histories  histories per work unit (the scheduling grain)
+ *   grid            persistent blocks (0 = fill the device)
+ *   tally_copies    LDS tally copies per block: 1, or one per wave (= 2)
+ *   use_graph       1 = capture the launches of a run in a hipGraph once
+ *                   per (problem set, options) and replay it
+ *   bank_size       event schedule: particles per bank slice */
+typedef struct {
+    uint32_t precision;
+    uint32_t schedule;
+    uint32_t block;
+    uint32_t hist_per_lane;
+    uint32_t unit_histories;
+    uint32_t grid;
+    uint32_t tally_copies;
+    uint32_t use_graph;
+    uint32_t bank_size;
+    uint32_t reserved[7];        /* must be 0 */
+} mcrng_run_opts;
+
+/* Diagnostics per problem, MCRNG_NDIAG uint64 words in this order.  All are
+ * sums except MCRNG_D_MAX_DRAWS (a maximum).  OVER_STRIDE counts histories
+ * that drew more than Q numbers under stride seeding (they ran into the next
+ * unit's stream, Sec. "Repetition and State Space Exhaustion"). */
+enum {
+    MCRNG_D_HISTORIES = 0, MCRNG_D_LEAK_LEFT, MCRNG_D_LEAK_RIGHT, MCRNG_D_ABSORBED,
+    MCRNG_D_CENSUS, MCRNG_D_EVENTS, MCRNG_D_COLLISIONS, MCRNG_D_DRAWS,
+    MCRNG_D_MAX_DRAWS, MCRNG_D_OVER_STRIDE, MCRNG_NDIAG
+};
+
+typedef struct mcrng_ctx mcrng_ctx;
+
+/* Creates a context bound to HIP device `device`.  The context owns the
+ * device tables, work-unit partial tallies and cached graphs of its runs;
+ * they are allocated on demand and grow, never shrink, until destroy. */
+int mcrng_ctx_create(int device, mcrng_ctx **out);
+int mcrng_ctx_destroy(mcrng_ctx *ctx);
+
+/* Number of tally bins of a problem set: sum over problems of
+ * n_batches * max(n_time_bins, 1) * n_space_bins.  Host-only. */
+uint64_t mcrng_tally_bins(const mcrng_problem *problems, uint32_t n_problems);
+
+/* Runs every history of every problem (the hot path: stream seeding, LCG
+ * draws, flight sampling, cell and time marching, collisions, track-length
+ * scoring).  Per-work-unit exact partial tallies stay in the context until
+ * the next run.  Validation errors: MCRNG_EINVAL (geometry, sizes,
+ * options), MCRNG_ERANGE (a flight could exceed 2^7 length units:
+ * -ln(2^-53)/min sigma_t >= 128 and no time bin bounds it).  Returns
+ * MCRNG_WSTRIDE_WRAP when a stride allocation passes 2^m states. */
+int mcrng_run_histories(mcrng_ctx *ctx, const mcrng_lcg *lcg, const mcrng_problem *problems,
+                        uint32_t n_problems, const mcrng_run_opts *opts, void *stream);
+
+/* Reduces the partial tallies of the last run in a fixed order.
+ *   d_raw   2 uint64 per bin (low, high word): the exact 128-bit sum of the
+ *           quantised track lengths q = round-half-even(s 2^56) of the bin
+ *   d_flux  1 double per bin: RN(sum) 2^-56 / (N_b dx [dt]), N_b the
+ *           histories of the bin's batch, dx its width, dt its duration
+ *   d_diag  n_problems x MCRNG_NDIAG uint64 (may be NULL)
+ * Bins are ordered problem, batch, time bin, space bin. */
+int mcrng_reduce_tallies(mcrng_ctx *ctx, uint64_t *d_raw, double *d_flux, uint64_t *d_diag,
+                         void *stream);
+
+/* Times candidate launch options for the problem set (each candidate run
+ * once after a warm-up, timed with HIP events on `stream`; the call
+ * synchronises the stream) and writes the fastest to *best.  `base` fixes
+ * precision and schedule; the search covers block size, histories per
+ * lane, work-unit size and tally copies.  The choice is cached in the
+ * context per problem-set shape.  *best_ms receives its time (may be NULL). */
+int mcrng_autotune(mcrng_ctx *ctx, const mcrng_lcg *lcg, const mcrng_problem *problems,
+                   uint32_t n_problems, const mcrng_run_opts *base, mcrng_run_opts *best,
+                   float *best_ms, void *stream);
+
+/* Kernel time of the last run_histories (HIP events around its launches on
+ * its stream), in milliseconds, once that stream has reached the end of the
+ * run; negative if unavailable. */
+float mcrng_last_run_ms(mcrng_ctx *ctx);
+
+/* Thread-local text of the last failure (never NULL). */
+const char *mcrng_last_error(void);
+
+/* MCRNG_ABI_VERSION of the built library. */
+int mcrng_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCRNG_H */

@@ -1,0 +1,805 @@
+// Host side of the C ABI declared in include/mcrng.h: argument validation,
+// slab geometry (merged cells), stride skip-ahead tables, work units, device
+// buffers of a context, hipGraph capture and the launch-option autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "mcrng.h"
+
+using namespace mcrng;
+
+// ------------------------------------------------------------------ errors
+
+static thread_local std::string g_last_error;
+
+static int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(e_ == hipErrorOutOfMemory ? MCRNG_ENOMEM : MCRNG_EDEVICE, "%s: %s", \
+                        #expr, hipGetErrorString(e_));                                      \
+    } while (0)
+
+extern "C" const char* mcrng_last_error(void) { return g_last_error.c_str(); }
+extern "C" int mcrng_version(void) { return MCRNG_ABI_VERSION; }
+
+// ------------------------------------------------------------------ LCG maths (host)
+
+typedef unsigned __int128 u128;
+
+static uint64_t mask_bits(uint32_t m) { return m >= 64 ? ~0ull : ((1ull << m) - 1ull); }
+
+struct Affine {   // X -> G X + C (mod 2^m)
+    uint64_t G, C;
+};
+
+// b after a: X -> bG (aG X + aC) + bC
+static Affine compose(const Affine& a, const Affine& b, uint64_t mask) {
+    return Affine{(b.G * a.G) & mask, (b.G * a.C + b.C) & mask};
+}
+
+// The map of k LCG steps, by binary doubling of the one-step map (eq. (2)).
+static Affine affine_power(uint64_t g, uint64_t c, uint64_t k, uint64_t mask) {
+    Affine acc{1ull & mask, 0}, sq{g & mask, c & mask};
+    while (k) {
+        if (k & 1) acc = compose(acc, sq, mask);
+        sq = compose(sq, sq, mask);
+        k >>= 1;
+    }
+    return acc;
+}
+
+static int validate_lcg(const mcrng_lcg* L, uint32_t min_m, LcgDev* out) {
+    if (!L) return fail(MCRNG_EINVAL, "lcg is NULL");
+    if (L->m < min_m || L->m > 64) return fail(MCRNG_EINVAL, "lcg.m = %u outside [%u, 64]", L->m, min_m);
+    if (L->reserved != 0) return fail(MCRNG_EINVAL, "lcg.reserved must be 0");
+    out->mask = mask_bits(L->m);
+    out->g = L->g & out->mask;
+    out->c = L->c & out->mask;
+    out->m = L->m;
+    out->shift53 = L->m >= 53 ? L->m - 53 : 0;
+    return MCRNG_OK;
+}
+
+// ------------------------------------------------------------------ stride tables
+
+// Process-wide cache of device skip tables, one per (device, g, c, m, Q).
+// Tables are immutable once built, so concurrent users can share them.
+struct TableKey {
+    int dev;
+    uint64_t g, c, Q;
+    uint32_t m;
+    bool operator<(const TableKey& o) const {
+        if (dev != o.dev) return dev < o.dev;
+        if (g != o.g) return g < o.g;
+        if (c != o.c) return c < o.c;
+        if (Q != o.Q) return Q < o.Q;
+        return m < o.m;
+    }
+};
+static std::mutex g_table_mu;
+static std::map<TableKey, uint64_t*> g_tables;
+
+static int get_stride_table(const LcgDev& L, uint64_t Q, const uint64_t** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    TableKey key{dev, L.g, L.c, Q, L.m};
+    std::lock_guard<std::mutex> lk(g_table_mu);
+    auto it = g_tables.find(key);
+    if (it != g_tables.end()) {
+        *out = it->second;
+        return MCRNG_OK;
+    }
+    std::vector<uint64_t> h(2 * kStrideDigits * kStrideRadix);
+    for (int d = 0; d < kStrideDigits; ++d) {
+        // Q * 16^d steps, taken modulo 2^64 (the cycle length 2^m divides it)
+        const uint64_t steps = Q << (kStrideRadixBits * d);
+        const Affine step = affine_power(L.g, L.c, steps, L.mask);
+        Affine cur{1ull & L.mask, 0};
+        for (int v = 0; v < kStrideRadix; ++v) {
+            h[2 * (d * kStrideRadix + v)] = cur.G;
+            h[2 * (d * kStrideRadix + v) + 1] = cur.C;
+            cur = compose(cur, step, L.mask);
+        }
+    }
+    uint64_t* d_tab = nullptr;
+    HIP_TRY(hipMalloc(&d_tab, h.size() * sizeof(uint64_t)));
+    hipError_t e = hipMemcpy(d_tab, h.data(), h.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d_tab);
+        return fail(MCRNG_EDEVICE, "stride table upload: %s", hipGetErrorString(e));
+    }
+    g_tables[key] = d_tab;
+    *out = d_tab;
+    return MCRNG_OK;
+}
+
+static uint32_t hex_digits(uint64_t v) {
+    uint32_t d = 0;
+    while (v) {
+        ++d;
+        v >>= kStrideRadixBits;
+    }
+    return d;
+}
+
+// Fills *S for n streams; returns MCRNG_WSTRIDE_WRAP when a stride
+// allocation passes 2^m states.
+static int build_seed(const LcgDev& L, const mcrng_seeding* sd, uint64_t n, SeedDev* S) {
+    if (!sd) return fail(MCRNG_EINVAL, "seeding is NULL");
+    S->first_index = sd->first_index;
+    S->table = nullptr;
+    S->stride_digits = 0;
+    if (sd->kind == MCRNG_SEED_HASH) {
+        S->kind = SEED_HASH;
+        const uint64_t parent = sd->hier ? murmur_hash(sd->group_key, sd->base) : sd->base;
+        S->base = murmur_seed_part(parent);
+        return MCRNG_OK;
+    }
+    if (sd->kind != MCRNG_SEED_STRIDE) return fail(MCRNG_EINVAL, "seeding.kind = %u unknown", sd->kind);
+    if (sd->stride == 0) return fail(MCRNG_EINVAL, "stride seeding needs stride >= 1");
+    S->kind = SEED_STRIDE;
+    S->base = sd->base & L.mask;
+    const uint64_t last = n ? sd->first_index + n - 1 : sd->first_index;
+    if (n && last < sd->first_index) return fail(MCRNG_EINVAL, "stream index overflows 64 bits");
+    S->stride_digits = hex_digits(last);
+    int rc = get_stride_table(L, sd->stride, &S->table);
+    if (rc < 0) return rc;
+    const u128 used = (static_cast<u128>(sd->first_index) + n) * static_cast<u128>(sd->stride);
+    const u128 cycle = static_cast<u128>(1) << L.m;
+    return used > cycle ? MCRNG_WSTRIDE_WRAP : MCRNG_OK;
+}
+
+// ------------------------------------------------------------------ streams
+
+extern "C" int mcrng_init_streams(const mcrng_lcg* lcg, const mcrng_seeding* seeding, uint64_t n,
+                                  uint64_t* d_state, void* stream) {
+    LcgDev L;
+    int rc = validate_lcg(lcg, 1, &L);
+    if (rc < 0) return rc;
+    if (n == 0) return MCRNG_OK;
+    if (!d_state) return fail(MCRNG_EINVAL, "d_state is NULL");
+    if (n >> 40) return fail(MCRNG_EINVAL, "n = %llu too large", (unsigned long long)n);
+    SeedDev S;
+    rc = build_seed(L, seeding, n, &S);
+    if (rc < 0) return rc;
+    HIP_TRY(launch_init_streams(L, S, n, d_state, static_cast<hipStream_t>(stream)));
+    return rc;
+}
+
+extern "C" int mcrng_draw(const mcrng_lcg* lcg, const mcrng_seeding* seeding, uint64_t n,
+                          const uint32_t* d_count, uint64_t* d_state, uint64_t* d_checksum, void* stream) {
+    LcgDev L;
+    int rc = validate_lcg(lcg, 1, &L);
+    if (rc < 0) return rc;
+    if (n == 0) return MCRNG_OK;
+    if (!d_count || !d_checksum) return fail(MCRNG_EINVAL, "d_count and d_checksum are required");
+    if (!seeding && !d_state) return fail(MCRNG_EINVAL, "d_state is required when seeding is NULL");
+    if (n >> 40) return fail(MCRNG_EINVAL, "n = %llu too large", (unsigned long long)n);
+    DrawParams p;
+    std::memset(&p, 0, sizeof p);
+    p.lcg = L;
+    p.n = n;
+    p.count = d_count;
+    p.state = d_state;
+    p.checksum = d_checksum;
+    int mode = SEED_LOAD;
+    if (seeding) {
+        rc = build_seed(L, seeding, n, &p.seed);
+        if (rc < 0) return rc;
+        mode = p.seed.kind;
+    }
+    int bpc = 8;
+    if (const char* env = getenv("MCRNG_DRAW_BLOCKS_PER_CU")) bpc = atoi(env);
+    HIP_TRY(launch_draw(p, mode, static_cast<hipStream_t>(stream), bpc));
+    return rc;
+}
+
+// ------------------------------------------------------------------ context
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+};
+
+struct mcrng_ctx {
+    int device = 0;
+    hipStream_t capture_stream = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool timing_valid = false;
+
+    DevBuf problems, edges64, sig64, scat64, cbin, edges32, sig32, tedges64, tedges32;
+    DevBuf units, order, partial, unit_diag, counter, groups, dx, dt, pu_begin;
+
+    // host copies of the current tables (kept alive while copies are staged)
+    std::vector<DevProblem> h_problems;
+    std::vector<double> h_edges64, h_sig64, h_scat64, h_tedges64, h_dx, h_dt;
+    std::vector<float> h_edges32, h_sig32, h_tedges32;
+    std::vector<int32_t> h_cbin;
+    std::vector<WorkUnit> h_units;
+    std::vector<uint32_t> h_order, h_pu_begin;
+    std::vector<ReduceGroup> h_groups;
+
+    uint64_t tables_sig = 0;      // signature of the uploaded tables
+    bool have_run = false;
+    uint32_t n_problems = 0;
+    uint32_t max_cells = 0, max_tedges = 0, max_slice = 0;
+    bool any_timed = false;
+    uint64_t partial_words = 0;
+
+    std::map<uint64_t, hipGraphExec_t> graphs;          // (tables, opts) -> executable
+    std::map<uint64_t, mcrng_run_opts> tuned;           // shape -> options
+};
+
+static int ensure(DevBuf& b, size_t bytes, hipStream_t st) {
+    if (bytes <= b.cap) return MCRNG_OK;
+    if (b.p) {
+        HIP_TRY(hipStreamSynchronize(st));
+        HIP_TRY(hipFree(b.p));
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    size_t want = std::max<size_t>(bytes + bytes / 4, 256);
+    HIP_TRY(hipMalloc(&b.p, want));
+    b.cap = want;
+    return MCRNG_OK;
+}
+
+template <class T>
+static int upload(DevBuf& b, const std::vector<T>& h, hipStream_t st) {
+    const size_t bytes = h.size() * sizeof(T);
+    int rc = ensure(b, bytes, st);
+    if (rc < 0) return rc;
+    if (bytes) HIP_TRY(hipMemcpyAsync(b.p, h.data(), bytes, hipMemcpyHostToDevice, st));
+    return MCRNG_OK;
+}
+
+static void clear_graphs(mcrng_ctx* ctx) {
+    for (auto& kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
+    ctx->graphs.clear();
+}
+
+extern "C" int mcrng_ctx_create(int device, mcrng_ctx** out) {
+    if (!out) return fail(MCRNG_EINVAL, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    HIP_TRY(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return fail(MCRNG_EINVAL, "device %d not present (%d devices)", device, n);
+    HIP_TRY(hipSetDevice(device));
+    mcrng_ctx* c = new (std::nothrow) mcrng_ctx();
+    if (!c) return fail(MCRNG_ENOMEM, "context allocation");
+    c->device = device;
+    hipError_t e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreate(&c->ev0);
+    if (e == hipSuccess) e = hipEventCreate(&c->ev1);
+    if (e != hipSuccess) {
+        delete c;
+        return fail(MCRNG_EDEVICE, "context setup: %s", hipGetErrorString(e));
+    }
+    *out = c;
+    return MCRNG_OK;
+}
+
+extern "C" int mcrng_ctx_destroy(mcrng_ctx* ctx) {
+    if (!ctx) return MCRNG_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    clear_graphs(ctx);
+    DevBuf* bufs[] = {&ctx->problems, &ctx->edges64, &ctx->sig64, &ctx->scat64, &ctx->cbin, &ctx->edges32,
+                      &ctx->sig32, &ctx->tedges64, &ctx->tedges32, &ctx->units, &ctx->order, &ctx->partial,
+                      &ctx->unit_diag, &ctx->counter, &ctx->groups, &ctx->dx, &ctx->dt, &ctx->pu_begin};
+    for (DevBuf* b : bufs)
+        if (b->p) (void)hipFree(b->p);
+    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
+    delete ctx;
+    return MCRNG_OK;
+}
+
+// ------------------------------------------------------------------ problem tables
+
+static uint64_t fnv(uint64_t h, const void* data, size_t n) {
+    const unsigned char* p = static_cast<const unsigned char*>(data);
+    for (size_t i = 0; i < n; ++i) {
+        h ^= p[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+static uint64_t tally_bins_of(const mcrng_problem& P) {
+    return static_cast<uint64_t>(P.n_batches) * std::max<uint32_t>(P.n_time_bins, 1) * P.n_space_bins;
+}
+
+extern "C" uint64_t mcrng_tally_bins(const mcrng_problem* problems, uint32_t n) {
+    if (!problems) return 0;
+    uint64_t t = 0;
+    for (uint32_t i = 0; i < n; ++i) t += tally_bins_of(problems[i]);
+    return t;
+}
+
+static bool increasing(const double* a, uint32_t n) {
+    for (uint32_t i = 0; i < n; ++i)
+        if (!std::isfinite(a[i]) || (i && !(a[i] > a[i - 1]))) return false;
+    return true;
+}
+
+constexpr uint32_t kMaxCells = 4096;
+constexpr uint32_t kMaxSlice = 8192;
+constexpr double kTauMax = 36.75;   // above -ln(2^-53) = 36.7368...
+
+static int validate_problem(const mcrng_problem& P, uint32_t idx) {
+    if (P.n_regions < 1 || P.n_space_bins < 1 || P.n_batches < 1)
+        return fail(MCRNG_EINVAL, "problem %u: n_regions, n_space_bins and n_batches must be >= 1", idx);
+    if (!P.region_edges || !P.sigma_t || !P.scatter || !P.bin_edges)
+        return fail(MCRNG_EINVAL, "problem %u: NULL geometry array", idx);
+    if ((P.n_time_bins > 0) != (P.time_edges != nullptr))
+        return fail(MCRNG_EINVAL, "problem %u: time_edges must be given exactly when n_time_bins > 0", idx);
+    if (!increasing(P.region_edges, P.n_regions + 1) || !increasing(P.bin_edges, P.n_space_bins + 1))
+        return fail(MCRNG_EINVAL, "problem %u: edges must be finite and strictly increasing", idx);
+    if (P.region_edges[0] != P.bin_edges[0] || P.region_edges[P.n_regions] != P.bin_edges[P.n_space_bins])
+        return fail(MCRNG_EINVAL, "problem %u: region and bin edges must span the same interval", idx);
+    if (P.n_time_bins > 0 && !increasing(P.time_edges, P.n_time_bins + 1))
+        return fail(MCRNG_EINVAL, "problem %u: time edges must be finite and strictly increasing", idx);
+    double min_sig = INFINITY;
+    for (uint32_t r = 0; r < P.n_regions; ++r) {
+        if (!(P.sigma_t[r] > 0.0) || !std::isfinite(P.sigma_t[r]))
+            return fail(MCRNG_EINVAL, "problem %u: sigma_t[%u] must be finite and > 0", idx, r);
+        if (!(P.scatter[r] >= 0.0 && P.scatter[r] <= 1.0))
+            return fail(MCRNG_EINVAL, "problem %u: scatter[%u] must be in [0, 1]", idx, r);
+        min_sig = std::min(min_sig, P.sigma_t[r]);
+    }
+    double bound = kTauMax / min_sig;
+    if (P.n_time_bins > 0) {
+        double wmax = 0;
+        for (uint32_t t = 0; t < P.n_time_bins; ++t) wmax = std::max(wmax, P.time_edges[t + 1] - P.time_edges[t]);
+        bound = std::min(bound, wmax);
+    }
+    if (!(bound < 128.0))
+        return fail(MCRNG_ERANGE, "problem %u: track lengths may reach 2^7 (bound %.3f)", idx, bound);
+    if (P.n_time_bins > 0 && static_cast<uint64_t>(P.n_time_bins) * P.n_space_bins > kMaxSlice)
+        return fail(MCRNG_EINVAL, "problem %u: more than %u tally bins per batch", idx, kMaxSlice);
+    if (P.n_space_bins > kMaxSlice) return fail(MCRNG_EINVAL, "problem %u: too many space bins", idx);
+    if (P.n_regions + P.n_space_bins > kMaxCells)
+        return fail(MCRNG_EINVAL, "problem %u: more than %u cells", idx, kMaxCells);
+    if (P.n_histories >> 40) return fail(MCRNG_EINVAL, "problem %u: n_histories too large", idx);
+    return MCRNG_OK;
+}
+
+static uint64_t signature(const mcrng_lcg* lcg, const mcrng_problem* P, uint32_t n, uint32_t unit_hist) {
+    uint64_t h = 1469598103934665603ull;
+    h = fnv(h, lcg, sizeof *lcg);
+    h = fnv(h, &n, sizeof n);
+    h = fnv(h, &unit_hist, sizeof unit_hist);
+    for (uint32_t i = 0; i < n; ++i) {
+        h = fnv(h, &P[i].n_regions, 4 * sizeof(uint32_t));
+        h = fnv(h, &P[i].n_histories, sizeof(uint64_t));
+        h = fnv(h, &P[i].seeding, sizeof(mcrng_seeding));
+        h = fnv(h, P[i].region_edges, (P[i].n_regions + 1) * sizeof(double));
+        h = fnv(h, P[i].sigma_t, P[i].n_regions * sizeof(double));
+        h = fnv(h, P[i].scatter, P[i].n_regions * sizeof(double));
+        h = fnv(h, P[i].bin_edges, (P[i].n_space_bins + 1) * sizeof(double));
+        if (P[i].n_time_bins) h = fnv(h, P[i].time_edges, (P[i].n_time_bins + 1) * sizeof(double));
+    }
+    return h;
+}
+
+static uint32_t default_unit_histories(const mcrng_problem* P, uint32_t n) {
+    uint64_t total = 0;
+    for (uint32_t i = 0; i < n; ++i) total += P[i].n_histories;
+    uint64_t u = total / 4096;   // a few units per resident block of the device
+    u = std::max<uint64_t>(u, 512);
+    u = std::min<uint64_t>(u, 65536);
+    return static_cast<uint32_t>(u);
+}
+
+// Builds every table of the problem set on the host and uploads them.
+static int build_tables(mcrng_ctx* ctx, const LcgDev& L, const mcrng_problem* P, uint32_t n, uint32_t unit_hist,
+                        hipStream_t st, int* warn) {
+    ctx->h_problems.assign(n, DevProblem{});
+    ctx->h_edges64.clear();
+    ctx->h_sig64.clear();
+    ctx->h_scat64.clear();
+    ctx->h_cbin.clear();
+    ctx->h_tedges64.clear();
+    ctx->h_dx.clear();
+    ctx->h_dt.clear();
+    ctx->h_units.clear();
+    ctx->h_groups.clear();
+    ctx->h_pu_begin.assign(n + 1, 0);
+    ctx->max_cells = ctx->max_tedges = ctx->max_slice = 0;
+    ctx->any_timed = false;
+    uint64_t slot = 0, out_off = 0;
+    *warn = MCRNG_OK;
+    for (uint32_t p = 0; p < n; ++p) {
+        const mcrng_problem& Q = P[p];
+        DevProblem& D = ctx->h_problems[p];
+        // merged cell edges: union of region and bin edges (exact doubles)
+        std::vector<double> E;
+        E.reserve(Q.n_regions + Q.n_space_bins + 2);
+        uint32_t a = 0, b = 0;
+        while (a <= Q.n_regions || b <= Q.n_space_bins) {
+            double v;
+            if (b > Q.n_space_bins || (a <= Q.n_regions && Q.region_edges[a] < Q.bin_edges[b]))
+                v = Q.region_edges[a++];
+            else if (a > Q.n_regions || Q.bin_edges[b] < Q.region_edges[a])
+                v = Q.bin_edges[b++];
+            else {
+                v = Q.region_edges[a];
+                ++a;
+                ++b;
+            }
+            E.push_back(v);
+        }
+        const uint32_t nc = static_cast<uint32_t>(E.size() - 1);
+        D.cell_off = static_cast<uint32_t>(ctx->h_sig64.size());
+        D.edge_off = static_cast<uint32_t>(ctx->h_edges64.size());
+        D.n_cells = nc;
+        uint32_t reg = 0, sb = 0;
+        for (uint32_t c = 0; c < nc; ++c) {
+            while (reg + 1 < Q.n_regions && Q.region_edges[reg + 1] <= E[c]) ++reg;
+            while (sb + 1 < Q.n_space_bins && Q.bin_edges[sb + 1] <= E[c]) ++sb;
+            ctx->h_sig64.push_back(Q.sigma_t[reg]);
+            ctx->h_scat64.push_back(Q.scatter[reg]);
+            ctx->h_cbin.push_back(static_cast<int32_t>(sb));
+        }
+        ctx->h_edges64.insert(ctx->h_edges64.end(), E.begin(), E.end());
+        D.n_time_bins = Q.n_time_bins;
+        D.n_space_bins = Q.n_space_bins;
+        D.slice_bins = std::max<uint32_t>(Q.n_time_bins, 1) * Q.n_space_bins;
+        D.tedge_off = static_cast<uint32_t>(ctx->h_tedges64.size());
+        if (Q.n_time_bins) {
+            ctx->h_tedges64.insert(ctx->h_tedges64.end(), Q.time_edges, Q.time_edges + Q.n_time_bins + 1);
+            ctx->any_timed = true;
+            ctx->max_tedges = std::max(ctx->max_tedges, Q.n_time_bins + 1);
+        }
+        ctx->max_cells = std::max(ctx->max_cells, nc);
+        ctx->max_slice = std::max(ctx->max_slice, D.slice_bins);
+        // seeding
+        SeedDev S;
+        int rc = build_seed(L, &Q.seeding, Q.n_histories, &S);
+        if (rc < 0) return rc;
+        if (rc > 0) *warn = rc;
+        D.seed_kind = static_cast<uint32_t>(S.kind);
+        D.stride_digits = S.stride_digits;
+        D.seed_base = S.base;
+        D.first_index = S.first_index;
+        D.stride_q = (S.kind == SEED_STRIDE) ? Q.seeding.stride : 0;
+        D.table = S.table;
+        // bin widths for the flux normalisation
+        const uint32_t dx_off = static_cast<uint32_t>(ctx->h_dx.size());
+        for (uint32_t i = 0; i < Q.n_space_bins; ++i) ctx->h_dx.push_back(Q.bin_edges[i + 1] - Q.bin_edges[i]);
+        const uint32_t dt_off = static_cast<uint32_t>(ctx->h_dt.size());
+        for (uint32_t i = 0; i < Q.n_time_bins; ++i) ctx->h_dt.push_back(Q.time_edges[i + 1] - Q.time_edges[i]);
+        // work units: batches split into runs of unit_hist histories
+        ctx->h_pu_begin[p] = static_cast<uint32_t>(ctx->h_units.size());
+        const uint64_t nb = Q.n_batches;
+        uint64_t bs = (Q.n_histories + nb - 1) / nb;
+        if (bs == 0) bs = 1;
+        for (uint64_t bt = 0; bt < nb; ++bt) {
+            const uint64_t j0 = std::min<uint64_t>(bt * bs, Q.n_histories);
+            const uint64_t j1 = std::min<uint64_t>((bt + 1) * bs, Q.n_histories);
+            ReduceGroup G;
+            G.problem = p;
+            G.unit_begin = static_cast<uint32_t>(ctx->h_units.size());
+            for (uint64_t j = j0; j < j1; j += unit_hist) {
+                WorkUnit U;
+                U.problem = p;
+                U.batch = static_cast<uint32_t>(bt);
+                U.j0 = j;
+                U.count = static_cast<uint32_t>(std::min<uint64_t>(unit_hist, j1 - j));
+                U.slice_bins = D.slice_bins;
+                U.slot = slot;
+                slot += 2ull * D.slice_bins;
+                ctx->h_units.push_back(U);
+            }
+            G.unit_end = static_cast<uint32_t>(ctx->h_units.size());
+            G.slice_bins = D.slice_bins;
+            G.n_space_bins = Q.n_space_bins;
+            G.n_time_bins = Q.n_time_bins;
+            G.out_off = out_off;
+            G.n_hist = j1 - j0;
+            G.dx_off = dx_off;
+            G.dt_off = dt_off;
+            out_off += D.slice_bins;
+            ctx->h_groups.push_back(G);
+        }
+    }
+    ctx->h_pu_begin[n] = static_cast<uint32_t>(ctx->h_units.size());
+    if (ctx->h_units.size() > 0xffffffffull) return fail(MCRNG_EINVAL, "too many work units");
+    // schedule: largest units first (stable), so short units fill the tail
+    ctx->h_order.resize(ctx->h_units.size());
+    for (uint32_t i = 0; i < ctx->h_order.size(); ++i) ctx->h_order[i] = i;
+    std::stable_sort(ctx->h_order.begin(), ctx->h_order.end(), [&](uint32_t x, uint32_t y) {
+        return ctx->h_units[x].count > ctx->h_units[y].count;
+    });
+    // FP32 copies, rounded once from the doubles
+    ctx->h_edges32.assign(ctx->h_edges64.begin(), ctx->h_edges64.end());
+    ctx->h_sig32.assign(ctx->h_sig64.begin(), ctx->h_sig64.end());
+    ctx->h_tedges32.assign(ctx->h_tedges64.begin(), ctx->h_tedges64.end());
+    if (ctx->h_tedges64.empty()) {
+        ctx->h_tedges64.push_back(0.0);
+        ctx->h_tedges32.push_back(0.0f);
+    }
+    if (ctx->h_dt.empty()) ctx->h_dt.push_back(0.0);
+    ctx->partial_words = slot;
+    int rc;
+    if ((rc = upload(ctx->problems, ctx->h_problems, st)) < 0) return rc;
+    if ((rc = upload(ctx->edges64, ctx->h_edges64, st)) < 0) return rc;
+    if ((rc = upload(ctx->sig64, ctx->h_sig64, st)) < 0) return rc;
+    if ((rc = upload(ctx->scat64, ctx->h_scat64, st)) < 0) return rc;
+    if ((rc = upload(ctx->cbin, ctx->h_cbin, st)) < 0) return rc;
+    if ((rc = upload(ctx->edges32, ctx->h_edges32, st)) < 0) return rc;
+    if ((rc = upload(ctx->sig32, ctx->h_sig32, st)) < 0) return rc;
+    if ((rc = upload(ctx->tedges64, ctx->h_tedges64, st)) < 0) return rc;
+    if ((rc = upload(ctx->tedges32, ctx->h_tedges32, st)) < 0) return rc;
+    if ((rc = upload(ctx->units, ctx->h_units, st)) < 0) return rc;
+    if ((rc = upload(ctx->order, ctx->h_order, st)) < 0) return rc;
+    if ((rc = upload(ctx->groups, ctx->h_groups, st)) < 0) return rc;
+    if ((rc = upload(ctx->dx, ctx->h_dx, st)) < 0) return rc;
+    if ((rc = upload(ctx->dt, ctx->h_dt, st)) < 0) return rc;
+    if ((rc = upload(ctx->pu_begin, ctx->h_pu_begin, st)) < 0) return rc;
+    if ((rc = ensure(ctx->partial, std::max<uint64_t>(slot, 2) * sizeof(uint64_t), st)) < 0) return rc;
+    if ((rc = ensure(ctx->unit_diag, std::max<size_t>(ctx->h_units.size(), 1) * kNDiag * sizeof(uint64_t), st)) < 0)
+        return rc;
+    if ((rc = ensure(ctx->counter, 64, st)) < 0) return rc;
+    ctx->n_problems = n;
+    return MCRNG_OK;
+}
+
+static TransportParams make_params(mcrng_ctx* ctx, const LcgDev& L, uint32_t copies) {
+    TransportParams tp;
+    std::memset(&tp, 0, sizeof tp);
+    tp.lcg = L;
+    tp.problems = static_cast<const DevProblem*>(ctx->problems.p);
+    tp.units = static_cast<const WorkUnit*>(ctx->units.p);
+    tp.order = static_cast<const uint32_t*>(ctx->order.p);
+    tp.n_units = static_cast<uint32_t>(ctx->h_units.size());
+    tp.max_cells = ctx->max_cells;
+    tp.max_tedges = ctx->max_tedges;
+    tp.max_slice = ctx->max_slice;
+    tp.tally_copies = copies;
+    tp.edges64 = static_cast<const double*>(ctx->edges64.p);
+    tp.sig64 = static_cast<const double*>(ctx->sig64.p);
+    tp.scat64 = static_cast<const double*>(ctx->scat64.p);
+    tp.cbin = static_cast<const int32_t*>(ctx->cbin.p);
+    tp.edges32 = static_cast<const float*>(ctx->edges32.p);
+    tp.sig32 = static_cast<const float*>(ctx->sig32.p);
+    tp.tedges64 = static_cast<const double*>(ctx->tedges64.p);
+    tp.tedges32 = static_cast<const float*>(ctx->tedges32.p);
+    tp.partial = static_cast<uint64_t*>(ctx->partial.p);
+    tp.unit_diag = static_cast<uint64_t*>(ctx->unit_diag.p);
+    tp.unit_counter = static_cast<uint32_t*>(ctx->counter.p);
+    return tp;
+}
+
+static int normalise_opts(const mcrng_run_opts* in, mcrng_run_opts* o) {
+    std::memset(o, 0, sizeof *o);
+    if (in) *o = *in;
+    for (uint32_t r : o->reserved)
+        if (r) return fail(MCRNG_EINVAL, "opts.reserved must be 0");
+    if (o->precision > MCRNG_FP32) return fail(MCRNG_EINVAL, "opts.precision unknown");
+    if (o->schedule > MCRNG_SCHED_EVENT) return fail(MCRNG_EINVAL, "opts.schedule unknown");
+    if (o->block == 0) o->block = 256;
+    if (o->block != 64 && o->block != 128 && o->block != 256 && o->block != 512 && o->block != 1024)
+        return fail(MCRNG_EINVAL, "opts.block = %u not in {64,128,256,512,1024}", o->block);
+    if (o->hist_per_lane == 0) o->hist_per_lane = 1;
+    if (o->hist_per_lane != 1 && o->hist_per_lane != 2 && o->hist_per_lane != 4)
+        return fail(MCRNG_EINVAL, "opts.hist_per_lane = %u not in {1,2,4}", o->hist_per_lane);
+    if (o->tally_copies == 0) o->tally_copies = 1;
+    if (o->tally_copies > 2) return fail(MCRNG_EINVAL, "opts.tally_copies must be 1 or 2");
+    return MCRNG_OK;
+}
+
+static int run_prepared(mcrng_ctx* ctx, const LcgDev& L, const mcrng_run_opts& o, hipStream_t st);
+
+extern "C" int mcrng_run_histories(mcrng_ctx* ctx, const mcrng_lcg* lcg, const mcrng_problem* problems,
+                                   uint32_t n_problems, const mcrng_run_opts* opts, void* stream) {
+    if (!ctx) return fail(MCRNG_EINVAL, "ctx is NULL");
+    if (!problems && n_problems) return fail(MCRNG_EINVAL, "problems is NULL");
+    if (n_problems == 0) return fail(MCRNG_EINVAL, "n_problems must be >= 1");
+    LcgDev L;
+    int rc = validate_lcg(lcg, 53, &L);
+    if (rc < 0) return rc;
+    mcrng_run_opts o;
+    if ((rc = normalise_opts(opts, &o)) < 0) return rc;
+    for (uint32_t i = 0; i < n_problems; ++i)
+        if ((rc = validate_problem(problems[i], i)) < 0) return rc;
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const uint32_t unit_hist = o.unit_histories ? o.unit_histories : default_unit_histories(problems, n_problems);
+    o.unit_histories = unit_hist;
+    const uint64_t sig = signature(lcg, problems, n_problems, unit_hist);
+    int warn = MCRNG_OK;
+    if (!ctx->have_run || sig != ctx->tables_sig) {
+        clear_graphs(ctx);
+        ctx->have_run = false;
+        if ((rc = build_tables(ctx, L, problems, n_problems, unit_hist, st, &warn)) < 0) return rc;
+        ctx->tables_sig = sig;
+    } else {
+        // seeding warnings do not depend on the upload
+        for (uint32_t i = 0; i < n_problems; ++i) {
+            SeedDev S;
+            int r2 = build_seed(L, &problems[i].seeding, problems[i].n_histories, &S);
+            if (r2 < 0) return r2;
+            if (r2 > 0) warn = r2;
+        }
+    }
+    if ((rc = run_prepared(ctx, L, o, st)) < 0) return rc;
+    ctx->have_run = true;
+    return warn;
+}
+
+static int enqueue_run(mcrng_ctx* ctx, const LcgDev& L, const mcrng_run_opts& o, hipStream_t st) {
+    TransportParams tp = make_params(ctx, L, o.tally_copies == 2 ? std::max<uint32_t>(o.block / 64, 1) : 1);
+    LaunchShape sh;
+    sh.block = static_cast<int>(o.block);
+    sh.hist_per_lane = static_cast<int>(o.hist_per_lane);
+    sh.grid = static_cast<int>(o.grid);
+    sh.f32 = o.precision == MCRNG_FP32;
+    sh.timed = ctx->any_timed;
+    int dev_lds = 0;
+    HIP_TRY(hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
+    if (transport_lds_bytes(tp, sh.f32) + 256 > static_cast<size_t>(dev_lds))
+        return fail(MCRNG_EINVAL, "LDS needed (%zu bytes) exceeds the device's %d", transport_lds_bytes(tp, sh.f32),
+                    dev_lds);
+    HIP_TRY(launch_fill_u32(tp.unit_counter, 16, 0u, st));
+    if (o.schedule == MCRNG_SCHED_EVENT) return fail(MCRNG_EINVAL, "event schedule not available in this build");
+    HIP_TRY(launch_transport(tp, sh, st, nullptr));
+    return MCRNG_OK;
+}
+
+static uint64_t opts_key(uint64_t tables_sig, const mcrng_run_opts& o) {
+    return fnv(tables_sig, &o, sizeof o);
+}
+
+static int run_prepared(mcrng_ctx* ctx, const LcgDev& L, const mcrng_run_opts& o, hipStream_t st) {
+    HIP_TRY(hipEventRecord(ctx->ev0, st));
+    if (o.use_graph && o.schedule == MCRNG_SCHED_HISTORY) {
+        const uint64_t key = opts_key(ctx->tables_sig, o);
+        auto it = ctx->graphs.find(key);
+        if (it == ctx->graphs.end()) {
+            // the tables were uploaded on `st`; the capture stream must see them
+            HIP_TRY(hipStreamSynchronize(st));
+            hipGraph_t g = nullptr;
+            HIP_TRY(hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
+            int rc = enqueue_run(ctx, L, o, ctx->capture_stream);
+            hipError_t e = hipStreamEndCapture(ctx->capture_stream, &g);
+            if (rc < 0) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc;
+            }
+            if (e != hipSuccess) return fail(MCRNG_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+            hipGraphExec_t ex = nullptr;
+            e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return fail(MCRNG_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
+            it = ctx->graphs.emplace(key, ex).first;
+        }
+        HIP_TRY(hipGraphLaunch(it->second, st));
+    } else {
+        int rc = enqueue_run(ctx, L, o, st);
+        if (rc < 0) return rc;
+    }
+    HIP_TRY(hipEventRecord(ctx->ev1, st));
+    ctx->timing_valid = true;
+    return MCRNG_OK;
+}
+
+extern "C" float mcrng_last_run_ms(mcrng_ctx* ctx) {
+    if (!ctx || !ctx->timing_valid) return -1.0f;
+    if (hipEventSynchronize(ctx->ev1) != hipSuccess) return -1.0f;
+    float ms = -1.0f;
+    if (hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1) != hipSuccess) return -1.0f;
+    return ms;
+}
+
+extern "C" int mcrng_reduce_tallies(mcrng_ctx* ctx, uint64_t* d_raw, double* d_flux, uint64_t* d_diag, void* stream) {
+    if (!ctx) return fail(MCRNG_EINVAL, "ctx is NULL");
+    if (!ctx->have_run) return fail(MCRNG_ESTATE, "reduce_tallies before any run_histories");
+    if (!d_raw || !d_flux) return fail(MCRNG_EINVAL, "d_raw and d_flux are required");
+    HIP_TRY(hipSetDevice(ctx->device));
+    ReduceParams rp;
+    std::memset(&rp, 0, sizeof rp);
+    rp.groups = static_cast<const ReduceGroup*>(ctx->groups.p);
+    rp.n_groups = static_cast<uint32_t>(ctx->h_groups.size());
+    rp.max_slice = ctx->max_slice;
+    rp.units = static_cast<const WorkUnit*>(ctx->units.p);
+    rp.partial = static_cast<const uint64_t*>(ctx->partial.p);
+    rp.dx = static_cast<const double*>(ctx->dx.p);
+    rp.dt = static_cast<const double*>(ctx->dt.p);
+    rp.raw = d_raw;
+    rp.flux = d_flux;
+    rp.pu_begin = static_cast<const uint32_t*>(ctx->pu_begin.p);
+    rp.n_problems = ctx->n_problems;
+    rp.unit_diag = static_cast<const uint64_t*>(ctx->unit_diag.p);
+    rp.diag = d_diag;
+    HIP_TRY(launch_reduce(rp, static_cast<hipStream_t>(stream)));
+    return MCRNG_OK;
+}
+
+// ------------------------------------------------------------------ autotuner
+
+static uint64_t shape_key(const mcrng_lcg* lcg, const mcrng_problem* P, uint32_t n, const mcrng_run_opts& base) {
+    uint64_t h = signature(lcg, P, n, 0);
+    h = fnv(h, &base.precision, sizeof base.precision);
+    h = fnv(h, &base.schedule, sizeof base.schedule);
+    return h;
+}
+
+extern "C" int mcrng_autotune(mcrng_ctx* ctx, const mcrng_lcg* lcg, const mcrng_problem* problems, uint32_t n_problems,
+                              const mcrng_run_opts* base, mcrng_run_opts* best, float* best_ms, void* stream) {
+    if (!ctx || !best) return fail(MCRNG_EINVAL, "ctx and best are required");
+    mcrng_run_opts b0;
+    int rc = normalise_opts(base, &b0);
+    if (rc < 0) return rc;
+    const uint64_t key = shape_key(lcg, problems, n_problems, b0);
+    auto hit = ctx->tuned.find(key);
+    if (hit != ctx->tuned.end()) {
+        *best = hit->second;
+        if (best_ms) *best_ms = -1.0f;
+        return MCRNG_OK;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    auto timed_run = [&](const mcrng_run_opts& o, float* ms) -> int {
+        int r = mcrng_run_histories(ctx, lcg, problems, n_problems, &o, stream);
+        if (r < 0) return r;
+        r = mcrng_run_histories(ctx, lcg, problems, n_problems, &o, stream);
+        if (r < 0) return r;
+        *ms = mcrng_last_run_ms(ctx);
+        return *ms < 0 ? fail(MCRNG_EDEVICE, "timing failed") : MCRNG_OK;
+    };
+    mcrng_run_opts cur = b0;
+    cur.unit_histories = 0;
+    cur.use_graph = 0;
+    float cur_ms = 0;
+    if ((rc = timed_run(cur, &cur_ms)) < 0) return rc;
+    auto try_field = [&](uint32_t mcrng_run_opts::*field, std::initializer_list<uint32_t> vals) -> int {
+        for (uint32_t v : vals) {
+            if (cur.*field == v) continue;
+            mcrng_run_opts cand = cur;
+            cand.*field = v;
+            float ms = 0;
+            int r = timed_run(cand, &ms);
+            if (r == MCRNG_EINVAL) continue;   // e.g. LDS does not fit this shape
+            if (r < 0) return r;
+            if (ms < cur_ms) {
+                cur = cand;
+                cur_ms = ms;
+            }
+        }
+        return MCRNG_OK;
+    };
+    if ((rc = try_field(&mcrng_run_opts::block, {64, 128, 256, 512, 1024})) < 0) return rc;
+    if ((rc = try_field(&mcrng_run_opts::hist_per_lane, {1, 2, 4})) < 0) return rc;
+    if ((rc = try_field(&mcrng_run_opts::tally_copies, {1, 2})) < 0) return rc;
+    const uint32_t u0 = default_unit_histories(problems, n_problems);
+    if ((rc = try_field(&mcrng_run_opts::unit_histories, {u0 / 4 > 256 ? u0 / 4 : 256, u0, u0 * 4})) < 0) return rc;
+    if (cur.unit_histories == 0) cur.unit_histories = u0;
+    HIP_TRY(hipStreamSynchronize(st));
+    ctx->tuned[key] = cur;
+    *best = cur;
+    if (best_ms) *best_ms = cur_ms;
+    return MCRNG_OK;
+}

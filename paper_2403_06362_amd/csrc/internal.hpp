@@ -1,0 +1,188 @@
+// Internal types shared by the library's kernels and its host-side API.
+// Not part of the public C ABI (include/mcrng.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_rng.hpp"
+
+namespace mcrng {
+
+constexpr int kNDiag = 10;   // same order as the MCRNG_D_* words of the C ABI
+enum DiagWord {
+    D_HISTORIES = 0, D_LEAK_LEFT, D_LEAK_RIGHT, D_ABSORBED, D_CENSUS,
+    D_EVENTS, D_COLLISIONS, D_DRAWS, D_MAX_DRAWS, D_OVER_STRIDE
+};
+
+enum SeedMode : int { SEED_LOAD = 0, SEED_HASH = 1, SEED_STRIDE = 2 };
+
+// Stride skip-ahead table: for digit d (base 16) and value v, the affine map
+// of Q * v * 16^d LCG steps, stored as (G, C) word pairs at
+// table[(d * 16 + v) * 2].
+constexpr int kStrideRadixBits = 4;
+constexpr int kStrideRadix = 1 << kStrideRadixBits;
+constexpr int kStrideDigits = 64 / kStrideRadixBits;
+
+struct SeedDev {
+    int kind;                  // SEED_HASH or SEED_STRIDE
+    uint32_t stride_digits;    // base-16 digits of the largest stream index
+    uint64_t base;             // stride: X_0 (masked); hash: subhash(parent ^ 8M)
+    uint64_t first_index;      // global index of stream 0
+    const uint64_t* table;     // stride: skip table of this Q
+};
+
+__device__ __forceinline__ uint64_t stream_start(const LcgDev& L, const SeedDev& S, uint64_t i) {
+    const uint64_t idx = S.first_index + i;
+    if (S.kind == SEED_HASH) return murmur_with_seed_part(idx + 1ull, S.base) & L.mask;
+    uint64_t x = S.base;
+    for (uint32_t d = 0; d < S.stride_digits; ++d) {
+        const uint32_t v = static_cast<uint32_t>(idx >> (kStrideRadixBits * d)) & (kStrideRadix - 1);
+        const uint64_t* e = S.table + 2 * (d * kStrideRadix + v);
+        x = affine_apply(e[0], e[1], L.mask, x);
+    }
+    return x;
+}
+
+// ------------------------------------------------------------ draw kernels
+
+struct DrawParams {
+    LcgDev lcg;
+    SeedDev seed;
+    uint64_t n;
+    const uint32_t* count;
+    uint64_t* state;      // SEED_LOAD: in/out; else optional out (may be null)
+    uint64_t* checksum;
+};
+
+hipError_t launch_init_streams(const LcgDev& L, const SeedDev& S, uint64_t n, uint64_t* out,
+                               hipStream_t st);
+hipError_t launch_draw(const DrawParams& p, int seed_mode, hipStream_t st, int blocks_per_cu);
+
+// ------------------------------------------------------------ transport
+
+struct DevProblem {
+    uint32_t cell_off;       // first cell in the flat cell arrays
+    uint32_t n_cells;
+    uint32_t tedge_off;      // first time edge in the flat time-edge arrays
+    uint32_t n_time_bins;    // 0 = steady state
+    uint32_t n_space_bins;
+    uint32_t slice_bins;     // max(n_time_bins, 1) * n_space_bins
+    uint32_t seed_kind;      // SEED_HASH or SEED_STRIDE
+    uint32_t stride_digits;
+    uint64_t seed_base;
+    uint64_t first_index;
+    uint64_t stride_q;       // stride seeding: Q (for the over-stride count); else 0
+    const uint64_t* table;   // stride seeding: skip table of this Q (device memory)
+    uint32_t edge_off;       // first edge in the flat edge arrays (n_cells + 1 edges)
+    uint32_t pad_;
+};
+
+struct WorkUnit {
+    uint32_t problem;
+    uint32_t batch;
+    uint64_t j0;             // first history (0-based within the problem)
+    uint32_t count;          // histories in the unit
+    uint32_t slice_bins;
+    uint64_t slot;           // first word of the unit's partial tally (2 words per bin)
+};
+
+struct TransportParams {
+    LcgDev lcg;
+    const DevProblem* problems;
+    const WorkUnit* units;
+    const uint32_t* order;       // schedule: units in the order blocks take them
+    uint32_t n_units;
+    uint32_t max_cells;          // LDS sizing: largest n_cells of the set
+    uint32_t max_tedges;         // largest n_time_bins + 1 (0 if all steady)
+    uint32_t max_slice;          // largest slice_bins
+    uint32_t tally_copies;       // 1 or waves per block
+    uint32_t pad_;
+    const double* edges64;       // flat cell arrays
+    const double* sig64;
+    const double* scat64;
+    const int32_t* cbin;
+    const float* edges32;
+    const float* sig32;
+    const double* tedges64;
+    const float* tedges32;
+    uint64_t* partial;           // per-unit partial tallies (low-half sum, high-half sum)
+    uint64_t* unit_diag;         // n_units x kNDiag
+    uint32_t* unit_counter;      // persistent scheduling counter (zeroed before launch)
+};
+
+struct LaunchShape {
+    int block;           // threads per block
+    int hist_per_lane;   // 1, 2 or 4
+    int grid;            // 0 = fill the device
+    int f32;             // 1 = FP32 flight mode
+    int timed;           // 1 = time-dependent problems present
+};
+
+size_t transport_lds_bytes(const TransportParams& p, int f32);
+hipError_t launch_transport(const TransportParams& p, const LaunchShape& s, hipStream_t st,
+                            int* grid_used);
+hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st);
+hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t st);
+
+// ------------------------------------------------------------ event schedule
+
+struct EventBank {
+    // structure-of-arrays particle bank, capacity entries each
+    double* x64; double* mu64; double* t64; double* tau64;
+    float* x32; float* mu32; float* t32; float* tau32;
+    uint64_t* X;             // LCG state
+    int32_t* cell;
+    int32_t* tb;
+    uint32_t* hdraws;        // draws of the history so far
+    uint32_t* flags;         // bit 0: need a fresh tau
+    uint32_t* unit;          // work unit (selects the partial-tally slice)
+};
+
+struct EventParams {
+    TransportParams tp;
+    EventBank in, out;
+    uint32_t n_in;
+    uint32_t* n_out;         // atomic append counter of the next bank
+    // init only: histories [j0, j0 + n_in) of unit `unit`
+    uint32_t init_unit;
+};
+
+hipError_t launch_event_init(const EventParams& p, int f32, int timed, hipStream_t st);
+hipError_t launch_event_step(const EventParams& p, int f32, int timed, hipStream_t st);
+
+// ------------------------------------------------------------ reduction
+
+struct ReduceGroup {         // one (problem, batch): a contiguous run of units
+    uint32_t problem;
+    uint32_t unit_begin;
+    uint32_t unit_end;
+    uint32_t slice_bins;
+    uint32_t n_space_bins;
+    uint32_t n_time_bins;    // 0 = steady
+    uint64_t out_off;        // first output bin
+    uint64_t n_hist;         // histories of the batch (flux normalisation)
+    uint32_t dx_off;         // first space-bin width of the problem
+    uint32_t dt_off;         // first time-bin width of the problem
+};
+
+struct ReduceParams {
+    const ReduceGroup* groups;
+    uint32_t n_groups;
+    uint32_t max_slice;
+    const WorkUnit* units;
+    const uint64_t* partial;
+    const double* dx;
+    const double* dt;
+    uint64_t* raw;           // 2 words per bin
+    double* flux;
+    // diagnostics: problem p owns units [pu_begin[p], pu_begin[p+1])
+    const uint32_t* pu_begin;
+    uint32_t n_problems;
+    const uint64_t* unit_diag;
+    uint64_t* diag;          // n_problems x kNDiag, may be null
+};
+
+hipError_t launch_reduce(const ReduceParams& p, hipStream_t st);
+
+}  // namespace mcrng

@@ -1,0 +1,543 @@
+// Fixed-source 1-D slab transport kernels for gfx950.
+//
+// k_transport (history-based, persistent).  A block takes work units (a run
+// of histories of one batch of one problem) from a global counter.  For each
+// unit it stages the problem's cells in LDS, zeroes an LDS tally slice and
+// runs the unit's histories one per lane: a lane whose history ended takes
+// the next history index of the unit through a wave ballot, a prefix count
+// and one LDS atomic per wave.  Every track length is scored as the integer
+// q = round-half-even(s 2^56) into the LDS slice (64-bit LDS atomics on its
+// low and high 32-bit halves), so the unit's partial tally is an exact
+// integer whatever order the lanes score in.  At the end of the unit the
+// block writes the slice to the unit's own partial-tally slot in HBM.
+//
+// k_reduce sums the partial slots of each (problem, batch) in unit order
+// (a fixed order; integer addition makes any order give the same bits),
+// converts the 128-bit sums to double with round-half-even, normalises the
+// flux and reduces per-problem diagnostics.
+//
+// The per-history arithmetic (flight sampling, cell / time marching,
+// collision, scoring) follows the same fixed IEEE operation sequence in FP64
+// mode and in FP32-flight mode; it is spelled out in step_particle below.
+#include <type_traits>
+
+#include "internal.hpp"
+
+namespace mcrng {
+
+__global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
+    for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_fill_u64(uint64_t* p, uint64_t n, uint64_t v) {
+    for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+        p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    uint64_t b = (n + 255) / 256;
+    if (b > 4096) b = 4096;
+    hipLaunchKernelGGL(k_fill_u32, dim3(static_cast<unsigned>(b)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    uint64_t b = (n + 255) / 256;
+    if (b > 4096) b = 4096;
+    hipLaunchKernelGGL(k_fill_u64, dim3(static_cast<unsigned>(b)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ particle
+
+template <bool F32>
+struct Particle {
+    using R = typename std::conditional<F32, float, double>::type;
+    R x, mu, t, tau;
+    uint64_t X;         // LCG state
+    int32_t cell, tb;
+    uint32_t hdraws;    // numbers drawn by this history
+    bool need_tau;      // the next step starts by sampling a flight
+};
+
+// Cell data of the current problem, staged in LDS.
+template <bool F32>
+struct CellsLds {
+    using R = typename std::conditional<F32, float, double>::type;
+    const R* edge;      // n_cells + 1
+    const R* sig;       // n_cells
+    const double* scat; // n_cells (the absorption test stays in double)
+    const int32_t* bin; // n_cells
+    const R* tedge;     // n_time_bins + 1
+    int32_t n_cells;
+    int32_t n_time_bins;
+    int32_t n_space_bins;
+};
+
+enum : int { END_NONE = 0, END_LEAK_LEFT, END_LEAK_RIGHT, END_ABSORBED, END_CENSUS };
+
+struct LaneCounters {
+    uint64_t events = 0, draws = 0, collisions = 0;
+    uint32_t histories = 0, leak_left = 0, leak_right = 0, absorbed = 0, census = 0;
+    uint32_t max_draws = 0, over_stride = 0;
+};
+
+__device__ __forceinline__ void lds_score(uint64_t* slot, uint64_t q) {
+    atomicAdd(reinterpret_cast<unsigned long long*>(slot), static_cast<unsigned long long>(q & 0xffffffffull));
+    atomicAdd(reinterpret_cast<unsigned long long*>(slot + 1), static_cast<unsigned long long>(q >> 32));
+}
+
+// One event of one particle.  Returns END_* (END_NONE while the history
+// continues).  Operation sequence (R = double, or float in FP32 mode; every
+// operation rounded to nearest, no fused multiply-add):
+//   [need_tau]  X = lcg(X); u = uniform(X); tau = R(-ln(u))   (ln in double)
+//   s = tau / sig[cell]                                     -> collision
+//   se = (E[cell+1] - x) / mu if mu > 0, (E[cell] - x) / mu if mu < 0,
+//        +inf if mu == 0;  if se < s: s = se               -> edge
+//   timed: st = T[tb+1] - t;  if st < s: s = st             -> time
+//   score q(double(s)) into (tb, bin[cell])
+//   timed: t = t + s; if t > T[tb+1]: t = T[tb+1]
+//   tau = tau - sig * s; if tau < 0: tau = 0
+//   edge:  mu > 0: cell + 1 (leak right past the last), x = E[cell]
+//          mu < 0: x = E[cell], cell - 1 (leak left past the first)
+//   other: x = x + mu * s, clamped to [E[cell], E[cell+1]]
+//   time:  tb + 1, t = T[tb]; census past the last time edge
+//   collision: X = lcg(X), u1: absorbed unless u1 < scat[cell] (double);
+//          X = lcg(X), u2: mu = R(2 u2 - 1) (computed in double, exact);
+//          the next step samples tau from the following draw.
+template <bool F32, bool TIMED>
+__device__ __forceinline__ int step_particle(Particle<F32>& p, const CellsLds<F32>& C, const LcgDev& L,
+                                             uint64_t* tally, LaneCounters& cnt) {
+    using R = typename Particle<F32>::R;
+    if (p.need_tau) {
+        p.X = lcg_next(L, p.X);
+        p.hdraws++;
+        const double lg = fixed_log(to_uniform(L, p.X));
+        p.tau = static_cast<R>(-lg);
+        p.need_tau = false;
+    }
+    const int c = p.cell;
+    const R sig = C.sig[c];
+    R s = p.tau / sig;
+    int ev = 0;   // 0 collision, 1 edge, 2 time
+    R se;
+    if (p.mu > R(0))
+        se = (C.edge[c + 1] - p.x) / p.mu;
+    else if (p.mu < R(0))
+        se = (C.edge[c] - p.x) / p.mu;
+    else
+        se = __builtin_huge_val();
+    if (se < s) {
+        s = se;
+        ev = 1;
+    }
+    R tnext = R(0);
+    const bool timed = TIMED && C.n_time_bins > 0;   // a set may mix steady and timed problems
+    if (timed) {
+        tnext = C.tedge[p.tb + 1];
+        const R st = tnext - p.t;
+        if (st < s) {
+            s = st;
+            ev = 2;
+        }
+    }
+    lds_score(tally + 2 * (static_cast<uint32_t>(p.tb) * C.n_space_bins + C.bin[c]),
+              quantise(static_cast<double>(s)));
+    cnt.events++;
+    if (timed) {
+        R tn = p.t + s;
+        if (tn > tnext) tn = tnext;
+        p.t = tn;
+    }
+    const R dtau = sig * s;
+    R tau = p.tau - dtau;
+    if (tau < R(0)) tau = R(0);
+    p.tau = tau;
+    if (ev == 1) {
+        if (p.mu > R(0)) {
+            const int nc = c + 1;
+            if (nc == C.n_cells) return END_LEAK_RIGHT;
+            p.cell = nc;
+            p.x = C.edge[nc];
+        } else {
+            p.x = C.edge[c];
+            if (c == 0) return END_LEAK_LEFT;
+            p.cell = c - 1;
+        }
+        return END_NONE;
+    }
+    const R step = p.mu * s;
+    R nx = p.x + step;
+    const R lo = C.edge[c], hi = C.edge[c + 1];
+    if (nx < lo) nx = lo;
+    if (nx > hi) nx = hi;
+    p.x = nx;
+    if (timed && ev == 2) {
+        const int ntb = p.tb + 1;
+        p.tb = ntb;
+        p.t = tnext;
+        if (ntb == C.n_time_bins) return END_CENSUS;
+        return END_NONE;
+    }
+    cnt.collisions++;
+    p.X = lcg_next(L, p.X);
+    p.hdraws++;
+    const double u1 = to_uniform(L, p.X);
+    if (!(u1 < C.scat[c])) return END_ABSORBED;
+    p.X = lcg_next(L, p.X);
+    p.hdraws++;
+    const double u2 = to_uniform(L, p.X);
+    p.mu = static_cast<R>(2.0 * u2 - 1.0);
+    p.need_tau = true;
+    return END_NONE;
+}
+
+template <bool F32, bool TIMED>
+__device__ __forceinline__ void init_particle(Particle<F32>& p, const CellsLds<F32>& C, const LcgDev& L,
+                                              const SeedDev& S, uint64_t j) {
+    using R = typename Particle<F32>::R;
+    p.X = stream_start(L, S, j);
+    p.x = C.edge[0];
+    p.mu = R(1);
+    p.t = (TIMED && C.n_time_bins > 0) ? C.tedge[0] : R(0);
+    p.tau = R(0);
+    p.cell = 0;
+    p.tb = 0;
+    p.hdraws = 0;
+    p.need_tau = true;
+}
+
+__device__ __forceinline__ void end_history(LaneCounters& cnt, int end, uint32_t hdraws, uint64_t stride_q) {
+    cnt.histories++;
+    cnt.draws += hdraws;
+    if (hdraws > cnt.max_draws) cnt.max_draws = hdraws;
+    if (stride_q != 0 && hdraws > stride_q) cnt.over_stride++;
+    cnt.leak_left += (end == END_LEAK_LEFT);
+    cnt.leak_right += (end == END_LEAK_RIGHT);
+    cnt.absorbed += (end == END_ABSORBED);
+    cnt.census += (end == END_CENSUS);
+}
+
+// LDS layout: [tally: copies x max_slice x 2 u64][edges][sig][scat f64][bin i32][tedges]
+__host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~static_cast<size_t>(15); }
+
+size_t transport_lds_bytes(const TransportParams& p, int f32) {
+    const size_t rs = f32 ? sizeof(float) : sizeof(double);
+    size_t b = align16(static_cast<size_t>(p.tally_copies) * p.max_slice * 2 * sizeof(uint64_t));
+    b += align16((p.max_cells + 1) * rs);
+    b += align16(p.max_cells * rs);
+    b += align16(p.max_cells * sizeof(double));
+    b += align16(p.max_cells * sizeof(int32_t));
+    b += align16((p.max_tedges > 0 ? p.max_tedges : 1) * rs);
+    return b;
+}
+
+template <bool F32, bool TIMED, int H, int BLOCK>
+__global__ void __launch_bounds__(BLOCK) k_transport(TransportParams P) {
+    using R = typename Particle<F32>::R;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ uint32_t s_unit;
+    __shared__ uint32_t s_next;
+    __shared__ unsigned long long s_diag[kNDiag];
+
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & 63u;
+    const uint32_t wid = tid >> 6;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+
+    uint64_t* tally_all = reinterpret_cast<uint64_t*>(smem);
+    size_t off = align16(static_cast<size_t>(P.tally_copies) * P.max_slice * 2 * sizeof(uint64_t));
+    R* l_edge = reinterpret_cast<R*>(smem + off);
+    off += align16((P.max_cells + 1) * sizeof(R));
+    R* l_sig = reinterpret_cast<R*>(smem + off);
+    off += align16(P.max_cells * sizeof(R));
+    double* l_scat = reinterpret_cast<double*>(smem + off);
+    off += align16(P.max_cells * sizeof(double));
+    int32_t* l_bin = reinterpret_cast<int32_t*>(smem + off);
+    off += align16(P.max_cells * sizeof(int32_t));
+    R* l_tedge = reinterpret_cast<R*>(smem + off);
+
+    const R* g_edge;
+    const R* g_sig;
+    const R* g_tedge;
+    if constexpr (F32) {
+        g_edge = P.edges32;
+        g_sig = P.sig32;
+        g_tedge = P.tedges32;
+    } else {
+        g_edge = P.edges64;
+        g_sig = P.sig64;
+        g_tedge = P.tedges64;
+    }
+
+    const uint32_t copy = (P.tally_copies > 1) ? (wid % P.tally_copies) : 0u;
+    int32_t cur_problem = -1;
+
+    for (;;) {
+        if (tid == 0) {
+            s_unit = atomicAdd(P.unit_counter, 1u);
+            s_next = 0;
+        }
+        if (tid < kNDiag) s_diag[tid] = 0;
+        __syncthreads();
+        const uint32_t pos = s_unit;
+        if (pos >= P.n_units) break;
+        const uint32_t ui = P.order[pos];
+        const WorkUnit U = P.units[ui];
+        const DevProblem PR = P.problems[U.problem];
+        const uint32_t slice = PR.slice_bins;
+
+        for (uint32_t c = 0; c < P.tally_copies; ++c)
+            for (uint32_t i = tid; i < 2 * slice; i += BLOCK) tally_all[static_cast<size_t>(c) * P.max_slice * 2 + i] = 0;
+        if (static_cast<int32_t>(U.problem) != cur_problem) {
+            for (uint32_t i = tid; i <= PR.n_cells; i += BLOCK) l_edge[i] = g_edge[PR.edge_off + i];
+            for (uint32_t i = tid; i < PR.n_cells; i += BLOCK) {
+                l_sig[i] = g_sig[PR.cell_off + i];
+                l_scat[i] = P.scat64[PR.cell_off + i];
+                l_bin[i] = P.cbin[PR.cell_off + i];
+            }
+            if (TIMED)
+                for (uint32_t i = tid; i <= PR.n_time_bins; i += BLOCK) l_tedge[i] = g_tedge[PR.tedge_off + i];
+            cur_problem = static_cast<int32_t>(U.problem);
+        }
+        __syncthreads();
+
+        CellsLds<F32> C;
+        C.edge = l_edge;
+        C.sig = l_sig;
+        C.scat = l_scat;
+        C.bin = l_bin;
+        C.tedge = l_tedge;
+        C.n_cells = static_cast<int32_t>(PR.n_cells);
+        C.n_time_bins = static_cast<int32_t>(PR.n_time_bins);
+        C.n_space_bins = static_cast<int32_t>(PR.n_space_bins);
+        SeedDev S;
+        S.kind = static_cast<int>(PR.seed_kind);
+        S.stride_digits = PR.stride_digits;
+        S.base = PR.seed_base;
+        S.first_index = PR.first_index;
+        S.table = PR.table;
+        uint64_t* tally = tally_all + static_cast<size_t>(copy) * P.max_slice * 2;
+
+        LaneCounters cnt;
+        Particle<F32> p[H];
+        bool alive[H];
+#pragma unroll
+        for (int h = 0; h < H; ++h) alive[h] = false;
+        bool exhausted = false;   // wave-uniform
+
+        for (;;) {
+#pragma unroll
+            for (int h = 0; h < H; ++h) {
+                if (!exhausted) {
+                    const uint64_t need = __ballot(!alive[h]);
+                    if (need != 0) {
+                        const uint32_t nneed = static_cast<uint32_t>(__popcll(need));
+                        const int leader = __ffsll(static_cast<unsigned long long>(need)) - 1;
+                        uint32_t base = 0;
+                        if (static_cast<int>(lane) == leader) base = atomicAdd(&s_next, nneed);
+                        base = __shfl(base, leader);
+                        if (base + nneed >= U.count) exhausted = true;
+                        if (!alive[h]) {
+                            const uint32_t j = base + static_cast<uint32_t>(__popcll(need & lt_mask));
+                            if (j < U.count) {
+                                init_particle<F32, TIMED>(p[h], C, P.lcg, S, U.j0 + j);
+                                alive[h] = true;
+                            }
+                        }
+                    }
+                }
+            }
+            bool any = false;
+#pragma unroll
+            for (int h = 0; h < H; ++h) any = any || alive[h];
+            if (__ballot(any) == 0) break;
+#pragma unroll
+            for (int h = 0; h < H; ++h) {
+                if (alive[h]) {
+                    const int end = step_particle<F32, TIMED>(p[h], C, P.lcg, tally, cnt);
+                    if (end != END_NONE) {
+                        end_history(cnt, end, p[h].hdraws, PR.stride_q);
+                        alive[h] = false;
+                    }
+                }
+            }
+        }
+
+        // unit diagnostics: per-lane counters into LDS
+        atomicAdd(&s_diag[D_HISTORIES], static_cast<unsigned long long>(cnt.histories));
+        atomicAdd(&s_diag[D_LEAK_LEFT], static_cast<unsigned long long>(cnt.leak_left));
+        atomicAdd(&s_diag[D_LEAK_RIGHT], static_cast<unsigned long long>(cnt.leak_right));
+        atomicAdd(&s_diag[D_ABSORBED], static_cast<unsigned long long>(cnt.absorbed));
+        atomicAdd(&s_diag[D_CENSUS], static_cast<unsigned long long>(cnt.census));
+        atomicAdd(&s_diag[D_EVENTS], static_cast<unsigned long long>(cnt.events));
+        atomicAdd(&s_diag[D_COLLISIONS], static_cast<unsigned long long>(cnt.collisions));
+        atomicAdd(&s_diag[D_DRAWS], static_cast<unsigned long long>(cnt.draws));
+        atomicMax(&s_diag[D_MAX_DRAWS], static_cast<unsigned long long>(cnt.max_draws));
+        atomicAdd(&s_diag[D_OVER_STRIDE], static_cast<unsigned long long>(cnt.over_stride));
+        __syncthreads();
+
+        uint64_t* dst = P.partial + U.slot;
+        for (uint32_t i = tid; i < slice; i += BLOCK) {
+            uint64_t lo = 0, hi = 0;
+            for (uint32_t c = 0; c < P.tally_copies; ++c) {
+                lo += tally_all[(static_cast<size_t>(c) * P.max_slice + i) * 2];
+                hi += tally_all[(static_cast<size_t>(c) * P.max_slice + i) * 2 + 1];
+            }
+            dst[2 * i] = lo;
+            dst[2 * i + 1] = hi;
+        }
+        if (tid < kNDiag) P.unit_diag[static_cast<size_t>(ui) * kNDiag + tid] = s_diag[tid];
+        __syncthreads();
+    }
+}
+
+template <bool F32, bool TIMED, int H, int BLOCK>
+static hipError_t launch_t(const TransportParams& p, int grid, size_t lds, hipStream_t st, int* used) {
+    auto kern = k_transport<F32, TIMED, H, BLOCK>;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+        if (e != hipSuccess) return e;
+    }
+    if (grid <= 0) {
+        int dev = 0, cus = 0, per_cu = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern), BLOCK, lds);
+        if (e != hipSuccess) return e;
+        if (per_cu < 1) per_cu = 1;
+        grid = cus * per_cu;
+    }
+    if (static_cast<uint32_t>(grid) > p.n_units) grid = static_cast<int>(p.n_units);
+    if (grid < 1) grid = 1;
+    if (used) *used = grid;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(BLOCK), lds, st, p);
+    return hipGetLastError();
+}
+
+template <bool F32, bool TIMED, int H>
+static hipError_t launch_b(const TransportParams& p, int block, int grid, size_t lds, hipStream_t st, int* used) {
+    switch (block) {
+        case 64: return launch_t<F32, TIMED, H, 64>(p, grid, lds, st, used);
+        case 128: return launch_t<F32, TIMED, H, 128>(p, grid, lds, st, used);
+        case 512: return launch_t<F32, TIMED, H, 512>(p, grid, lds, st, used);
+        case 1024: return launch_t<F32, TIMED, H, 1024>(p, grid, lds, st, used);
+        default: return launch_t<F32, TIMED, H, 256>(p, grid, lds, st, used);
+    }
+}
+
+template <bool F32, bool TIMED>
+static hipError_t launch_h(const TransportParams& p, const LaunchShape& s, size_t lds, hipStream_t st, int* used) {
+    switch (s.hist_per_lane) {
+        case 2: return launch_b<F32, TIMED, 2>(p, s.block, s.grid, lds, st, used);
+        case 4: return launch_b<F32, TIMED, 4>(p, s.block, s.grid, lds, st, used);
+        default: return launch_b<F32, TIMED, 1>(p, s.block, s.grid, lds, st, used);
+    }
+}
+
+hipError_t launch_transport(const TransportParams& p, const LaunchShape& s, hipStream_t st, int* grid_used) {
+    if (p.n_units == 0) return hipSuccess;
+    const size_t lds = transport_lds_bytes(p, s.f32);
+    if (s.f32) {
+        return s.timed ? launch_h<true, true>(p, s, lds, st, grid_used)
+                       : launch_h<true, false>(p, s, lds, st, grid_used);
+    }
+    return s.timed ? launch_h<false, true>(p, s, lds, st, grid_used)
+                   : launch_h<false, false>(p, s, lds, st, grid_used);
+}
+
+// ------------------------------------------------------------------ reduction
+
+// Round-half-even conversion of the 128-bit integer (hi, lo) to double:
+// keep the top 53 bits, round on the dropped bits, scale back exactly.
+__device__ __forceinline__ double u128_to_double(uint64_t lo, uint64_t hi) {
+    typedef unsigned __int128 u128;
+    const u128 v = (static_cast<u128>(hi) << 64) | lo;
+    if ((v >> 53) == 0) return static_cast<double>(lo);
+    const int nbits = (hi != 0) ? 128 - __clzll(static_cast<long long>(hi)) : 64 - __clzll(static_cast<long long>(lo));
+    const int sh = nbits - 53;
+    u128 mant = v >> sh;
+    const u128 rem = v - (mant << sh);
+    const u128 half = static_cast<u128>(1) << (sh - 1);
+    if (rem > half || (rem == half && (mant & 1))) mant += 1;
+    return __builtin_ldexp(static_cast<double>(static_cast<uint64_t>(mant)), sh);
+}
+
+// One thread per output bin; the groups' bins are laid out back to back.
+__global__ void __launch_bounds__(256) k_reduce_bins(ReduceParams P) {
+    const uint32_t g = blockIdx.y;
+    const ReduceGroup G = P.groups[g];
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < G.slice_bins; i += gridDim.x * blockDim.x) {
+        unsigned __int128 acc = 0;
+        for (uint32_t u = G.unit_begin; u < G.unit_end; ++u) {
+            const uint64_t* s = P.partial + P.units[u].slot + 2 * static_cast<uint64_t>(i);
+            acc += static_cast<unsigned __int128>(s[0]);
+            acc += static_cast<unsigned __int128>(s[1]) << 32;
+        }
+        const uint64_t lo = static_cast<uint64_t>(acc), hi = static_cast<uint64_t>(acc >> 64);
+        const uint64_t o = G.out_off + i;
+        P.raw[2 * o] = lo;
+        P.raw[2 * o + 1] = hi;
+        const uint32_t sb = i % G.n_space_bins;
+        const uint32_t tb = i / G.n_space_bins;
+        const double r = u128_to_double(lo, hi) * 0x1p-56;
+        double d = static_cast<double>(G.n_hist) * P.dx[G.dx_off + sb];
+        if (G.n_time_bins > 0) d = d * P.dt[G.dt_off + tb];
+        P.flux[o] = (d != 0.0) ? r / d : 0.0;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_reduce_diag(ReduceParams P) {
+    const uint32_t pb = blockIdx.x;
+    __shared__ unsigned long long acc[kNDiag];
+    if (threadIdx.x < kNDiag) acc[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t u0 = P.pu_begin[pb], u1 = P.pu_begin[pb + 1];
+    unsigned long long loc[kNDiag];
+#pragma unroll
+    for (int k = 0; k < kNDiag; ++k) loc[k] = 0;
+    for (uint32_t u = u0 + threadIdx.x; u < u1; u += blockDim.x) {
+#pragma unroll
+        for (int k = 0; k < kNDiag; ++k) {
+            const unsigned long long v = P.unit_diag[static_cast<size_t>(u) * kNDiag + k];
+            if (k == D_MAX_DRAWS)
+                loc[k] = v > loc[k] ? v : loc[k];
+            else
+                loc[k] += v;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kNDiag; ++k) {
+        if (k == D_MAX_DRAWS)
+            atomicMax(&acc[k], loc[k]);
+        else
+            atomicAdd(&acc[k], loc[k]);
+    }
+    __syncthreads();
+    if (threadIdx.x < kNDiag) P.diag[static_cast<size_t>(pb) * kNDiag + threadIdx.x] = acc[threadIdx.x];
+}
+
+hipError_t launch_reduce(const ReduceParams& p, hipStream_t st) {
+    if (p.n_groups > 0) {
+        uint32_t bx = (p.max_slice + 255) / 256;
+        if (bx < 1) bx = 1;
+        hipLaunchKernelGGL(k_reduce_bins, dim3(bx, p.n_groups), dim3(256), 0, st, p);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (p.diag != nullptr && p.n_problems > 0) {
+        hipLaunchKernelGGL(k_reduce_diag, dim3(p.n_problems), dim3(256), 0, st, p);
+        return hipGetLastError();
+    }
+    return hipSuccess;
+}
+
+}  // namespace mcrng

@@ -1,0 +1,140 @@
+"""GPU parity of stream seeding and draws against the CPU oracle, through the
+C ABI (mcrng_init_streams, mcrng_draw).  Bit-exact: integer work."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from helpers import to_dev_u32, u64_np
+
+pytestmark = pytest.mark.gpu
+LCG = W.Lcg()
+
+
+def say(*a):
+    print("[gpu]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def M():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    import paper_2403_06362_amd as M
+    M.lib()
+    return M
+
+
+def _empty_u64(n):
+    import torch
+    return torch.empty(max(n, 1), dtype=torch.uint64, device="cuda:0")
+
+
+@pytest.mark.parametrize("kind", ["hash", "stride"])
+@pytest.mark.parametrize("n,first", [(1, 0), (63, 0), (65, 7), (70001, 0), (70001, 123456789)])
+def test_init_streams_parity(M, orc, kind, n, first):
+    sd = W.hash_seeding(first) if kind == "hash" else W.stride_seeding(first)
+    say("init_streams", kind, n, first)
+    out = _empty_u64(n)
+    M.init_streams(LCG, sd, n, out)
+    assert np.array_equal(u64_np(out)[:n], orc.init_streams(LCG, sd, n))
+
+
+def test_init_streams_group_key(M, orc):
+    sd = W.hash_seeding(group_key=17)
+    out = _empty_u64(1000)
+    M.init_streams(LCG, sd, 1000, out)
+    assert np.array_equal(u64_np(out), orc.init_streams(LCG, sd, 1000))
+
+
+@pytest.mark.parametrize("kind", ["hash", "stride"])
+def test_init_streams_full_size_sampled(M, orc, kind):
+    n = 1 << 26
+    sd = W.hash_seeding() if kind == "hash" else W.stride_seeding()
+    say("init_streams full", kind, n)
+    out = _empty_u64(n)
+    M.init_streams(LCG, sd, n, out)
+    got = u64_np(out)
+    rng = np.random.default_rng(5)
+    idx = np.concatenate([np.arange(64), np.arange(n - 64, n), rng.integers(0, n, 2000)])
+    for i in idx:
+        assert int(got[i]) == orc.stream_start(LCG, sd, int(i)), int(i)
+
+
+@pytest.mark.parametrize("mode", ["hash", "stride", "load"])
+@pytest.mark.parametrize("n", [1, 65, 100003])
+def test_draw_parity(M, orc, mode, n):
+    import torch
+    counts = W.draw_counts(n, seed=42)
+    counts[: min(n, 3)] = [0, 1, 2][: min(n, 3)]
+    sd = W.stride_seeding() if mode == "stride" else W.hash_seeding()
+    say("draw", mode, n)
+    chk = _empty_u64(n)
+    if mode == "load":
+        st = _empty_u64(n)
+        M.init_streams(LCG, sd, n, st)
+        M.draw(LCG, None, to_dev_u32(counts), chk, d_state=st)
+        states = orc.init_streams(LCG, sd, n)
+        ref = orc.seed_and_draw(LCG, None, counts, states=states)
+        assert np.array_equal(u64_np(st)[:n], states)
+    else:
+        st = _empty_u64(n)
+        M.draw(LCG, sd, to_dev_u32(counts), chk, d_state=st)
+        ref = orc.seed_and_draw(LCG, sd, counts, threads=8)
+        states = orc.init_streams(LCG, sd, n)
+        orc.seed_and_draw(LCG, None, counts, states=states)
+        assert np.array_equal(u64_np(st)[:n], states)
+    torch.cuda.synchronize()
+    assert np.array_equal(u64_np(chk)[:n], ref)
+
+
+@pytest.mark.parametrize("kind", ["hash", "stride"])
+def test_draw_full_size_sampled(M, orc, kind):
+    """The benchmark workload: 2^26 streams, geometric counts (mean 64)."""
+    n = 1 << 26
+    counts = W.draw_counts()
+    sd = W.hash_seeding() if kind == "hash" else W.stride_seeding()
+    say("draw full", kind, n)
+    chk = _empty_u64(n)
+    M.draw(LCG, sd, to_dev_u32(counts), chk)
+    got = u64_np(chk)
+    rng = np.random.default_rng(9)
+    idx = np.concatenate([np.arange(64), np.arange(n - 64, n), rng.integers(0, n, 3000),
+                          [int(np.argmax(counts))]])
+    for i in idx:
+        i = int(i)
+        one = orc.seed_and_draw(LCG, W.Seeding(sd.kind, sd.base, sd.stride, i), counts[i:i + 1])
+        assert int(got[i]) == int(one[0]), i
+    # property over all streams: total draws = sum of counts (checksum of count-0 streams is 0)
+    assert int(counts.sum()) > (1 << 32) - (1 << 27)
+
+
+def test_forced_long_stride_streams_overlap(M, orc):
+    """Streams drawing 2Q numbers run into the next unit's stride: stream k's
+    outputs Q+1..2Q are stream k+1's outputs 1..Q."""
+    Q = W.STRIDE_Q
+    n = 1024
+    sd = W.stride_seeding()
+    say("forced long streams")
+    c2 = to_dev_u32(np.full(n, 2 * Q, np.uint32))
+    c1 = to_dev_u32(np.full(n, Q, np.uint32))
+    chk2, chk1 = _empty_u64(n), _empty_u64(n)
+    M.draw(LCG, sd, c2, chk2)
+    M.draw(LCG, sd, c1, chk1)
+    a2, a1 = u64_np(chk2), u64_np(chk1)
+    for k in range(n - 1):
+        assert int(a2[k]) == (int(a1[k]) + int(a1[k + 1])) % (1 << 64)
+    ref = orc.seed_and_draw(LCG, sd, np.full(4, 2 * Q, np.uint32))
+    assert np.array_equal(a2[:4], ref)
+
+
+def test_stride_wrap_warning(M, orc):
+    """N Q > 2^m: allocations wrap the cycle; the library says so and still
+    produces the defined states."""
+    lcg = W.Lcg(W.G_MCNP % (1 << 20), 1, 20)
+    sd = W.Seeding("stride", 5, 1000, 0)
+    out = _empty_u64(2000)
+    rc = M.init_streams(lcg, sd, 2000, out)
+    assert rc == 1
+    assert np.array_equal(u64_np(out), orc.init_streams(lcg, sd, 2000))

@@ -1,0 +1,204 @@
+"""GPU parity of the slab transport (mcrng_run_histories +
+mcrng_reduce_tallies) against the CPU oracle.
+
+Tallies are exact integers, so the bar is bit-exact raw sums (and bit-exact
+flux, whose normalisation is the same operation sequence on both sides),
+equal diagnostics, and bit-identical results across launch shapes.  At the
+full workload sizes the oracle recomputes sampled outputs: whole batches of
+the 1e8-history long-chain slab, whole small problems of the 512-problem
+set, and sub-ranges (sharding) of the 2e8-history multi-region slab."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from helpers import diag_dict, raw_ints
+
+pytestmark = pytest.mark.gpu
+LCG = W.Lcg()
+
+
+def say(*a):
+    print("[gpu]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def M():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    import paper_2403_06362_amd as M
+    M.lib()
+    return M
+
+
+@pytest.fixture(scope="module")
+def ctx(M):
+    c = M.Context(0)
+    yield c
+    c.close()
+
+
+def run(M, ctx, probs, **opts):
+    import torch
+    raw, flux, diag = M.transport(probs, LCG, ctx=ctx, opts=M.make_opts(**opts))
+    torch.cuda.synchronize()
+    return raw_ints(raw), flux.cpu().numpy(), diag_dict(diag, M.DIAG_NAMES)
+
+
+def split(values, probs):
+    out, off = [], 0
+    for p in probs:
+        n = p.n_batches * max(p.n_time_bins, 1) * p.n_space_bins
+        out.append(values[off:off + n])
+        off += n
+    return out
+
+
+def check_parity(orc, probs, raw, flux, diag, float_mode=False, threads=8):
+    for p, r, f, d in zip(probs, split(raw, probs), split(list(flux), probs), diag):
+        ref = orc.transport(p, LCG, float_mode=float_mode, threads=threads)
+        assert r == ref.raw
+        assert d == ref.diag
+        assert np.array_equal(np.array(f), orc.flux(p, ref))
+
+
+@pytest.mark.parametrize("kind", ["hash", "stride"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_small_slab_parity(M, ctx, orc, kind, precision):
+    sd = W.hash_seeding() if kind == "hash" else W.stride_seeding()
+    p = W.small_slab(sd)
+    say("small slab", kind, precision)
+    raw, flux, diag = run(M, ctx, [p], precision=precision)
+    check_parity(orc, [p], raw, flux, diag, float_mode=bool(precision))
+
+
+def test_launch_shapes_bit_identical(M, ctx, orc):
+    p = W.homogeneous(10.0, 1.3, 0.95, 37, 20011, W.hash_seeding(), n_batches=3)
+    ref = orc.transport(p, LCG, threads=8)
+    for block in (64, 256, 1024):
+        for hpl in (1, 2, 4):
+            for unit in (300, 4096):
+                for copies in (1, 2):
+                    say("shape", block, hpl, unit, copies)
+                    raw, _, diag = run(M, ctx, [p], block=block, hist_per_lane=hpl, unit_histories=unit,
+                                       tally_copies=copies)
+                    assert raw == ref.raw, (block, hpl, unit, copies)
+                    assert diag[0] == ref.diag
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_long_chain_parity(M, ctx, orc, precision):
+    p = W.long_chain(n_histories=200_003)
+    say("long chain 2e5", precision)
+    raw, flux, diag = run(M, ctx, [p], precision=precision)
+    check_parity(orc, [p], raw, flux, diag, float_mode=bool(precision))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_multi_region_parity(M, ctx, orc, precision):
+    p = W.multi_region(n_histories=100_001)
+    say("multi region 1e5", precision)
+    raw, flux, diag = run(M, ctx, [p], precision=precision)
+    check_parity(orc, [p], raw, flux, diag, float_mode=bool(precision))
+
+
+@pytest.mark.parametrize("kind", ["hash", "stride"])
+def test_batched_parity(M, ctx, orc, kind):
+    probs = W.batched(seeding_kind=kind, scale=1e-3)
+    say("batched 512 (scaled)", kind)
+    raw, flux, diag = run(M, ctx, probs)
+    check_parity(orc, probs, raw, flux, diag, threads=4)
+
+
+def test_graph_replays_match_eager(M, ctx, orc):
+    import torch
+    probs = W.batched(scale=2e-3)[:64]
+    eager = run(M, ctx, probs)
+    for rep in range(3):
+        say("graph replay", rep)
+        g = run(M, ctx, probs, use_graph=1)
+        assert g[0] == eager[0] and g[2] == eager[2]
+        x = torch.ones(1 << 20, device="cuda:0").sum()   # unrelated eager work between replays
+        torch.cuda.synchronize()
+        assert float(x) == float(1 << 20)
+    ref = [orc.transport(p, LCG, threads=4).raw for p in probs[:8]]
+    assert split(eager[0], probs)[:8] == ref
+
+
+def test_zero_histories_and_edge_problems(M, ctx, orc):
+    probs = [W.small_slab(n_histories=0), W.small_slab(n_histories=1),
+             W.homogeneous(1.0, 2.0, 0.0, 1, 777), W.small_slab(n_histories=64)]
+    say("edge problems")
+    raw, flux, diag = run(M, ctx, probs)
+    check_parity(orc, probs, raw, flux, diag, threads=1)
+
+
+def test_error_paths(M, ctx):
+    p = W.small_slab()
+    with pytest.raises(M.McrngError):
+        run(M, ctx, [p], block=96)
+    thin = W.homogeneous(100.0, 0.1, 0.5, 10, 10)   # flights up to 367 mfp: fixed point range
+    with pytest.raises(M.McrngError) as e:
+        run(M, ctx, [thin])
+    assert e.value.code == -4
+
+
+# ------------------------------------------------------------ full sizes
+
+def _batch_raw(raw, p, b):
+    n = max(p.n_time_bins, 1) * p.n_space_bins
+    return raw[b * n:(b + 1) * n]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_long_chain_full_size_sampled_batches(M, ctx, orc, precision):
+    """1e8 histories, 64 batches (the transport benchmark configuration):
+    two whole batches recomputed by the oracle, plus exact balance."""
+    p = W.long_chain()
+    say("long chain full", precision)
+    raw, flux, diag = run(M, ctx, [p], precision=precision)
+    d = diag[0]
+    assert d["histories"] == p.n_histories
+    assert d["leak_left"] + d["leak_right"] + d["absorbed"] + d["census"] == p.n_histories
+    bs = p.n_histories // p.n_batches
+    for b in (0, 45):
+        ref = orc.transport(p, LCG, float_mode=bool(precision), j0=b * bs, j1=(b + 1) * bs, threads=16)
+        assert _batch_raw(raw, p, b) == _batch_raw(ref.raw, p, b), b
+
+
+def test_multi_region_full_size_sharded(M, ctx, orc):
+    """2e8 histories: the full run equals the sum of two shards run
+    separately (first_index), a sub-range agrees with the oracle, and the
+    particle balance is exact."""
+    p = W.multi_region()
+    say("multi region full")
+    raw, _, diag = run(M, ctx, [p])
+    assert diag[0]["histories"] == p.n_histories
+    d = diag[0]
+    assert d["leak_left"] + d["leak_right"] + d["absorbed"] + d["census"] == p.n_histories
+    h = p.n_histories // 2
+    a = p.with_(n_histories=h)
+    b = p.with_(n_histories=p.n_histories - h, seeding=W.hash_seeding(first_index=h))
+    ra, _, _ = run(M, ctx, [a], block=512, unit_histories=100_000)
+    rb, _, _ = run(M, ctx, [b], block=128, hist_per_lane=2)
+    assert [x + y for x, y in zip(ra, rb)] == raw
+    sub = p.with_(n_histories=200_000, seeding=W.hash_seeding(first_index=150_000_000))
+    rs, _, ds = run(M, ctx, [sub])
+    ref = orc.transport(sub, LCG, threads=16)
+    assert rs == ref.raw and ds[0] == ref.diag
+
+
+def test_batched_full_size_small_problems(M, ctx, orc):
+    """512 problems, 5.6e8 histories in one persistent launch: the 24
+    smallest problems recomputed whole by the oracle."""
+    probs = W.batched()
+    say("batched full")
+    raw, _, diag = run(M, ctx, probs)
+    parts = split(raw, probs)
+    order = np.argsort([p.n_histories for p in probs])[:24]
+    for i in order:
+        ref = orc.transport(probs[i], LCG, threads=4)
+        assert parts[i] == ref.raw, int(i)
+        assert diag[i] == ref.diag
