@@ -1,0 +1,307 @@
+#!/usr/bin/env python3
+"""Benchmark: seeded LCG draws and slab transport on one MI355X.
+
+Step (timed, the headline `value`): one pass of the seed + draw hot path over
+the stream microbenchmark workload -- 2^26 streams, per-stream draw counts
+geometric with mean 64 (NumPy seed 42), hash seeding with global seed 1,
+LCG X <- (g X + 1) mod 2^63.  Every stream is seeded in registers, advanced
+count[i] times and its checksum (sum of outputs mod 2^64) written to HBM.
+value = RNG draws per second (the draws of the whole step / step time).
+
+Also reported, each timed separately after the headline loop:
+  stride        the same workload with stride seeding (X_0 = 1, Q = 152917)
+  transport     the 1e8-history long-chain slab (50 mfp, c = 0.99, 200 bins,
+                64 batches): histories/s, draws/s, events/s for hash FP64,
+                hash FP32-flight and stride FP64 (kernel time, HIP events)
+  roofline      of the draw kernel: integer VALU lane-ops per launch over the
+                average kernel duration (HIP events on the launch stream)
+  cpu_baseline  the CPU oracle on the host cores, same workload
+With --full, the 512-problem batched set (persistent + graph, FP64 and
+FP32, against one launch per problem) and the 2e8-history multi-region
+slab are added.
+
+Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--full]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle histories/sec and RNG draws/sec (hash vs stride seeding), % int-VALU peak"
+
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz = one full-rate 32-bit
+# VALU lane-operation per lane per clock.
+INT_VALU_PEAK = 256 * 4 * 16 * 2.4e9
+# Algorithmic integer lane-ops: a draw is the 63-bit multiply-add on 32-bit
+# halves (64-bit low product with the increment, two cross products, one
+# three-way add, the mask) plus the 64-bit checksum add = 6; a hash seed is
+# Listing 1 on a 64-bit key = 16; a stride seed is 6 per base-16 digit of
+# the stream index (digit extraction 2, 64-bit multiply-add 4).
+OPS_PER_DRAW = 6
+OPS_PER_HASH_SEED = 16
+OPS_PER_STRIDE_DIGIT = 6
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def draw_workload(M, W, torch, dev, kind, steps, warmup, d_count, n, total_draws, lcg):
+    sd = W.hash_seeding() if kind == "hash" else W.stride_seeding()
+    chk = torch.empty(n, dtype=torch.uint64, device=dev)
+    for _ in range(warmup):
+        M.draw(lcg, sd, d_count, chk)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        M.draw(lcg, sd, d_count, chk, stream=stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / steps
+    kern_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    return {"ms_per_step": ms_step, "kernel_ms": kern_ms, "draws_per_s": total_draws / (ms_step * 1e-3),
+            "chk": chk}
+
+
+def spot_check(oracle, W, lcg, kind, counts, chk_np, k=256):
+    sd = W.hash_seeding() if kind == "hash" else W.stride_seeding()
+    rng = np.random.default_rng(123)
+    for i in rng.integers(0, counts.size, k):
+        i = int(i)
+        one = oracle.seed_and_draw(lcg, W.Seeding(sd.kind, sd.base, sd.stride, i), counts[i:i + 1])
+        if int(one[0]) != int(chk_np[i]):
+            return False
+    return True
+
+
+def traffic_from_profiles(kernel_src_sha):
+    """HBM bytes per launch measured with rocprofv3 --pmc (FETCH_SIZE, then
+    WRITE_SIZE), scaled by a copy kernel of known size; None if absent or
+    taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "k_draw_hash_2p26_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != kernel_src_sha:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def transport_leg(M, W, torch, lcg, ctx, prob, opts, reps=2):
+    import paper_2403_06362_amd as P
+    nb = P.tally_bins([prob])
+    raw = torch.empty((nb, 2), dtype=torch.uint64, device="cuda:0")
+    flux = torch.empty(nb, dtype=torch.float64, device="cuda:0")
+    diag = torch.empty((1, P.NDIAG), dtype=torch.uint64, device="cuda:0")
+    ctx.run_histories(lcg, [prob], opts)          # warm-up (and table upload)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        ctx.run_histories(lcg, [prob], opts)
+        times.append(ctx.last_run_ms())
+    ctx.reduce_tallies(raw, flux, diag)
+    torch.cuda.synchronize()
+    d = diag.view(torch.int64).cpu().numpy().view(np.uint64)[0]
+    dd = dict(zip(P.DIAG_NAMES, (int(v) for v in d)))
+    ms = float(np.median(times))
+    return {"ms": ms, "histories_per_s": prob.n_histories / (ms * 1e-3),
+            "draws_per_s": dd["draws"] / (ms * 1e-3), "events_per_s": dd["events"] / (ms * 1e-3),
+            "draws_per_history": dd["draws"] / max(1, dd["histories"]),
+            "events_per_history": dd["events"] / max(1, dd["histories"]),
+            "flux": flux.cpu().numpy(), "diag": dd}
+
+
+def rel_err(a, b):
+    m = (np.abs(b) > 0)
+    r = np.abs(a[m] - b[m]) / np.abs(b[m])
+    return float(r.max()) if r.size else 0.0, float(np.sqrt(np.mean(r ** 2))) if r.size else 0.0
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--full", action="store_true", help="add the batched and multi-region legs")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-transport", action="store_true", help="headline draw workload only")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one plain 512 MiB device copy (reference kernel for HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on exactly one GPU (--gpus 1); multi-GPU runs are not "
+              "part of it (the path would shard histories by first_index and all-reduce the "
+              "integer tallies).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2403_06362_amd as M
+    import workloads as W
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    M.lib()
+    dev = "cuda:0"
+    lcg = W.Lcg()
+    n = 1 << 26
+    log("generating draw counts")
+    counts = W.draw_counts(n, seed=42)
+    total_draws = int(counts.sum(dtype=np.uint64))
+    d_count = torch.from_numpy(counts).to(dev)
+
+    log("headline: hash seeding, %d streams, %d draws" % (n, total_draws))
+    hsh = draw_workload(M, W, torch, dev, "hash", args.steps, args.warmup, d_count, n, total_draws, lcg)
+    log("stride seeding")
+    strd = draw_workload(M, W, torch, dev, "stride", args.steps, args.warmup, d_count, n, total_draws, lcg)
+
+    if args.copy_probe:
+        src_t = torch.ones(1 << 27, dtype=torch.float32, device=dev)
+        dst_t = torch.empty_like(src_t)
+        torch.cuda.synchronize()
+        dst_t.copy_(src_t)
+        torch.cuda.synchronize()
+        del src_t, dst_t
+
+    import oracle
+    ok_h = spot_check(oracle, W, lcg, "hash", counts, hsh["chk"].view(torch.int64).cpu().numpy().view(np.uint64))
+    ok_s = spot_check(oracle, W, lcg, "stride", counts, strd["chk"].view(torch.int64).cpu().numpy().view(np.uint64))
+
+    digits = max(1, int(np.ceil(np.log2(n) / 4)))
+    ops_hash = OPS_PER_DRAW * total_draws + OPS_PER_HASH_SEED * n
+    ops_stride = OPS_PER_DRAW * total_draws + OPS_PER_STRIDE_DIGIT * digits * n
+    achieved = ops_hash / (hsh["kernel_ms"] * 1e-3)
+    src = open(os.path.join(ROOT, "paper_2403_06362_amd", "csrc", "rng_kernels.hip"), "rb").read()
+    src += open(os.path.join(ROOT, "paper_2403_06362_amd", "csrc", "device_rng.hpp"), "rb").read()
+    src += open(os.path.join(ROOT, "paper_2403_06362_amd", "csrc", "internal.hpp"), "rb").read()
+    sha = hashlib.sha256(src).hexdigest()
+    traffic = traffic_from_profiles(sha)
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": INT_VALU_PEAK / 1e12,
+                "unit": "Tera int32 VALU lane-ops/s", "frac": achieved / INT_VALU_PEAK,
+                "traffic": traffic, "kernel": "k_draw<hash>",
+                "algorithmic_ops_per_launch": ops_hash, "kernel_ms": hsh["kernel_ms"],
+                "algorithmic_hbm_bytes_per_launch": 12 * n}
+
+    out = {
+        "metric": METRIC, "value": hsh["draws_per_s"], "unit": "draws/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": hsh["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "seed+draw microbenchmark: 2^26 streams, geometric draw counts (mean 64, "
+                               "seed 42), hash seeding (s=1), LCG g=2806196910506780709 c=1 m=63",
+                   "streams": n, "draws_per_step": total_draws, "seeding": "hash"},
+        "streams_per_s": n / (hsh["ms_per_step"] * 1e-3),
+        "stride_seeding": {"draws_per_s": strd["draws_per_s"], "ms_per_step": strd["ms_per_step"],
+                           "kernel_ms": strd["kernel_ms"],
+                           "int_valu_frac": ops_stride / (strd["kernel_ms"] * 1e-3) / INT_VALU_PEAK,
+                           "hash_over_stride": strd["ms_per_step"] / hsh["ms_per_step"]},
+        "verified_vs_oracle": {"hash_sampled_streams": ok_h, "stride_sampled_streams": ok_s},
+        "roofline": roofline,
+    }
+
+    if not args.no_transport:
+        ctx = M.Context(0)
+        prob = W.long_chain()
+        legs = {}
+        for name, sd, prec in (("hash_fp64", W.hash_seeding(), 0), ("hash_fp32", W.hash_seeding(), 1),
+                               ("stride_fp64", W.stride_seeding(), 0)):
+            log("transport long chain", name)
+            legs[name] = transport_leg(M, W, torch, lcg, ctx, prob.with_(seeding=sd), M.make_opts(precision=prec))
+        emax, erms = rel_err(legs["hash_fp32"]["flux"], legs["hash_fp64"]["flux"])
+        tr = {"workload": "long-chain slab: 50 mfp, sigma_t=1, c=0.99, 200 bins, 1e8 histories, 64 batches"}
+        for k, v in legs.items():
+            tr[k] = {kk: vv for kk, vv in v.items() if kk not in ("flux", "diag")}
+        tr["fp32_vs_fp64_flux_rel_err"] = {"max": emax, "rms": erms}
+        tr["fp32_speedup"] = legs["hash_fp64"]["ms"] / legs["hash_fp32"]["ms"]
+        tr["hash_over_stride"] = legs["stride_fp64"]["ms"] / legs["hash_fp64"]["ms"]
+        out["histories_per_s"] = legs["hash_fp64"]["histories_per_s"]
+        out["transport"] = tr
+        if args.full:
+            out["batched"] = batched_leg(M, W, torch, lcg, ctx)
+            out["multi_region"] = multi_region_leg(M, W, torch, lcg, ctx)
+        ctx.close()
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(oracle, W, lcg, counts)
+
+    print(json.dumps(out), flush=True)
+
+
+def batched_leg(M, W, torch, lcg, ctx):
+    probs = W.batched()
+    res = {"workload": "512 slabs (seed 7), log-uniform 1e3..1e7 histories, sum %d" %
+                       sum(p.n_histories for p in probs)}
+    # per-problem FP64 baseline: one run (launch) per problem
+    log("batched: one launch per problem (fp64)")
+    ctx1 = M.Context(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p in probs:
+        ctx1.run_histories(lcg, [p], M.make_opts())
+    torch.cuda.synchronize()
+    per_problem_s = time.perf_counter() - t0
+    ctx1.close()
+    res["per_problem_fp64_s"] = per_problem_s
+    for name, prec in (("fp64", 0), ("fp32", 1)):
+        log("batched: autotune", name)
+        best, best_ms = ctx.autotune(lcg, probs, M.make_opts(precision=prec))
+        best.use_graph = 1
+        ctx.run_histories(lcg, probs, best)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.run_histories(lcg, probs, best)
+        torch.cuda.synchronize()
+        s = time.perf_counter() - t0
+        res["persistent_graph_" + name] = {"s": s, "kernel_ms": ctx.last_run_ms(), "opts": best.as_dict(),
+                                           "histories_per_s": sum(p.n_histories for p in probs) / s}
+    res["speedup_fp32_batched_over_fp64_per_problem"] = per_problem_s / res["persistent_graph_fp32"]["s"]
+    res["speedup_fp64_batched_over_fp64_per_problem"] = per_problem_s / res["persistent_graph_fp64"]["s"]
+    return res
+
+
+def multi_region_leg(M, W, torch, lcg, ctx):
+    prob = W.multi_region()
+    res = {"workload": "10-region slab (seed 11), 50x20 space-time bins, 2e8 histories, hash"}
+    for name, opts in (("history", M.make_opts()), ("history_fp32", M.make_opts(precision=1))):
+        log("multi region", name)
+        r = transport_leg(M, W, torch, lcg, ctx, prob, opts, reps=1)
+        res[name] = {k: v for k, v in r.items() if k not in ("flux", "diag")}
+    return res
+
+
+def cpu_baseline(oracle, W, lcg, counts):
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    threads = max(1, min(threads, 16))
+    ns = counts.size
+    sample = counts[:ns]
+    log("cpu baseline: oracle seed+draw on %d streams, %d threads" % (ns, threads))
+    t0 = time.perf_counter()
+    oracle.seed_and_draw(lcg, W.hash_seeding(), sample, threads=threads)
+    dt = time.perf_counter() - t0
+    draws = int(sample.sum(dtype=np.uint64))
+    return {"value": draws / dt, "unit": "draws/s", "cores": threads, "kind": "oracle",
+            "sample": "all %d streams of the workload (%d draws), hash seeding, %.2f s wall" % (ns, draws, dt)}
+
+
+if __name__ == "__main__":
+    main()
