@@ -57,7 +57,7 @@ struct DrawParams {
 
 hipError_t launch_init_streams(const LcgDev& L, const SeedDev& S, uint64_t n, uint64_t* out,
                                hipStream_t st);
-hipError_t launch_draw(const DrawParams& p, int seed_mode, hipStream_t st, int blocks_per_cu);
+hipError_t launch_draw(const DrawParams& p, int seed_mode, hipStream_t st, int blocks_per_cu, int round);
 
 // ------------------------------------------------------------ transport
 

@@ -1,13 +1,10 @@
 // Stream seeding and LCG draw kernels for gfx950.
 //
 // k_init_streams: one stream per lane, grid-stride; writes S_i.
-// k_draw: persistent waves.  Each wave owns a contiguous range of streams and
-//   keeps one stream per lane.  A lane draws from its stream in blocks of D
-//   LCG steps (masked by the remaining count); between blocks the lanes whose
-//   stream ended store its checksum and take the next streams of the wave's
-//   range in order (ballot + prefix count), seeding them in registers.  The
-//   state, sum and remaining count never leave registers; HBM sees 4 bytes of
-//   count in and 8 bytes of checksum (+ 8 of state) out per stream.
+// k_draw: persistent waves, one active stream per lane, refilled from a
+//   per-wave queue of pre-seeded streams (see the kernel).  The state, sum and
+//   remaining count never leave registers; HBM sees 4 bytes of count in and
+//   8 bytes of checksum (+ 8 of state) out per stream.
 #include "internal.hpp"
 
 namespace mcrng {
@@ -26,16 +23,57 @@ hipError_t launch_init_streams(const LcgDev& L, const SeedDev& S, uint64_t n, ui
     return hipGetLastError();
 }
 
-template <int MODE, int D, bool STORE_STATE>
+// One LCG step for m = 63, c = 1: with the increment and the mask known at
+// compile time this is one v_mad_u64_u32 (g_lo * x_lo + 1), two
+// v_mul_lo_u32 (cross products), one v_add3_u32 and one v_and_b32.
+template <bool M63C1>
+__device__ __forceinline__ uint64_t draw_step(const LcgDev& L, uint64_t x, uint64_t g) {
+    if (M63C1) return (g * x + 1ull) & 0x7fffffffffffffffull;
+    return lcg_next(L, x);
+}
+
+template <int MODE>
+__device__ __forceinline__ uint64_t queue_seed(const DrawParams& P, uint64_t j) {
+    if (MODE == SEED_LOAD) return P.state[j];
+    return stream_start(P.lcg, P.seed, j);
+}
+
+// Persistent seed + draw kernel.  Each wave owns the streams [lo, hi) and
+// keeps a queue of the next 64 of them: lane l holds the start state of
+// stream qbase + l (seeded with all 64 lanes at once) in a register, and the
+// 64 draw counts sit in the wave's LDS row (loaded one queue ahead).  Each
+// lane carries one active stream; a round draws D steps (only the checksum is
+// masked by the remaining count); after a round, lanes whose stream ended
+// store its checksum and take the next queue entries in order through a
+// ballot, a prefix count, cross-lane reads of the seeds and LDS reads of the
+// counts.  The queue position and range are wave-uniform (scalar registers);
+// the refill path has no dependence on vector-memory loads, so it never waits
+// for the checksum stores in flight.
+template <int MODE, int D, bool STORE_STATE, bool M63C1>
 __global__ void __launch_bounds__(256) k_draw(DrawParams P) {
+    __shared__ uint32_t s_count[4][64];
     const uint32_t lane = threadIdx.x & 63u;
-    const uint64_t wave = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
-    const uint64_t nwaves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) >> 6;
+    const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave in block
+    const uint64_t wave = static_cast<uint64_t>(blockIdx.x) * (blockDim.x >> 6) + wib;
+    const uint64_t nwaves = static_cast<uint64_t>(gridDim.x) * (blockDim.x >> 6);
     const uint64_t lo = wave * P.n / nwaves;
     const uint64_t hi = (wave + 1) * P.n / nwaves;
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const uint64_t g = P.lcg.g;
+    uint32_t* my_count = s_count[wib];
 
-    uint64_t head = lo;          // wave-uniform: next unassigned stream
+    // queue of the next 64 streams: qbase, qhead wave-uniform
+    uint64_t qbase = lo;
+    uint32_t qhead = 0;
+    uint64_t qx = 0;
+    uint32_t qc_next = 0;
+    {
+        const uint64_t j = qbase + lane;
+        my_count[lane] = (j < hi) ? P.count[j] : 0u;
+        if (j < hi) qx = queue_seed<MODE>(P, j);
+        const uint64_t jn = j + 64;
+        if (jn < hi) qc_next = P.count[jn];
+    }
+
     uint64_t x = 0, sum = 0, sid = 0;
     uint32_t rem = 0;
     bool active = false;
@@ -45,61 +83,101 @@ __global__ void __launch_bounds__(256) k_draw(DrawParams P) {
             if (STORE_STATE) P.state[sid] = x;
             active = false;
         }
-        const uint64_t need = __ballot(!active);
-        if (need != 0 && head < hi) {
-            const uint64_t j = head + static_cast<uint64_t>(__popcll(need & lt_mask));
-            if (!active && j < hi) {
-                sid = j;
-                if (MODE == SEED_LOAD)
-                    x = P.state[j];
-                else
-                    x = stream_start(P.lcg, P.seed, j);
-                rem = P.count[j];
+        uint64_t need = __ballot(!active);
+        while (need != 0 && qbase + qhead < hi) {
+            const uint64_t left = hi - (qbase + qhead);
+            const uint32_t room = 64u - qhead;
+            const uint32_t avail = left < room ? static_cast<uint32_t>(left) : room;
+            const uint32_t nneed = static_cast<uint32_t>(__popcll(need));
+            const uint32_t take = __builtin_amdgcn_readfirstlane(nneed < avail ? nneed : avail);
+            const uint32_t rank = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(need >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(need), 0u));
+            const uint32_t src = qhead + (rank < take ? rank : 0u);
+            const uint64_t vx = __shfl(qx, static_cast<int>(src));
+            const uint32_t vc = my_count[src];
+            if (!active && rank < take) {
+                x = vx;
+                rem = vc;
+                sid = qbase + src;
                 sum = 0;
                 active = true;
             }
-            head += static_cast<uint64_t>(__popcll(need));
+            qhead = __builtin_amdgcn_readfirstlane(qhead + take);
+            if (qhead == 64u) {
+                qbase += 64;
+                qhead = 0;
+                const uint64_t j = qbase + lane;
+                my_count[lane] = qc_next;   // the one wait on vector memory per 64 streams
+                if (j < hi) qx = queue_seed<MODE>(P, j);
+                const uint64_t jn = j + 64;
+                qc_next = (jn < hi) ? P.count[jn] : 0u;
+            }
+            need = __ballot(!active);
         }
         if (__ballot(active) == 0) break;
         const uint32_t k = active ? (rem < static_cast<uint32_t>(D) ? rem : static_cast<uint32_t>(D)) : 0u;
+        if (STORE_STATE) {
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-            if (static_cast<uint32_t>(d) < k) {
-                x = lcg_next(P.lcg, x);
-                sum += x;
+            for (int d = 0; d < D; ++d) {
+                if (static_cast<uint32_t>(d) < k) {
+                    x = draw_step<M63C1>(P.lcg, x, g);
+                    sum += x;
+                }
+            }
+        } else {
+            // the state may run past the end of the stream (it is not
+            // stored); only the checksum is masked
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                x = draw_step<M63C1>(P.lcg, x, g);
+                if (static_cast<uint32_t>(d) < k) sum += x;
             }
         }
         rem -= k;
     }
 }
 
-template <int MODE, int D>
+template <int MODE, int D, bool M63C1>
 static hipError_t launch_draw_t(const DrawParams& p, hipStream_t st, int blocks) {
     if (p.state != nullptr)
-        hipLaunchKernelGGL((k_draw<MODE, D, true>), dim3(blocks), dim3(256), 0, st, p);
+        hipLaunchKernelGGL((k_draw<MODE, D, true, M63C1>), dim3(blocks), dim3(256), 0, st, p);
     else
-        hipLaunchKernelGGL((k_draw<MODE, D, false>), dim3(blocks), dim3(256), 0, st, p);
+        hipLaunchKernelGGL((k_draw<MODE, D, false, M63C1>), dim3(blocks), dim3(256), 0, st, p);
     return hipGetLastError();
 }
 
-hipError_t launch_draw(const DrawParams& p, int seed_mode, hipStream_t st, int blocks_per_cu) {
+template <int MODE, bool M63C1>
+static hipError_t launch_draw_d(const DrawParams& p, hipStream_t st, int blocks, int d) {
+    switch (d) {
+        case 8: return launch_draw_t<MODE, 8, M63C1>(p, st, blocks);
+        case 32: return launch_draw_t<MODE, 32, M63C1>(p, st, blocks);
+        default: return launch_draw_t<MODE, 16, M63C1>(p, st, blocks);
+    }
+}
+
+template <int MODE>
+static hipError_t launch_draw_m(const DrawParams& p, hipStream_t st, int blocks, int d) {
+    const bool m63c1 = p.lcg.m == 63 && p.lcg.c == 1;
+    return m63c1 ? launch_draw_d<MODE, true>(p, st, blocks, d) : launch_draw_d<MODE, false>(p, st, blocks, d);
+}
+
+hipError_t launch_draw(const DrawParams& p, int seed_mode, hipStream_t st, int blocks_per_cu, int round) {
     if (p.n == 0) return hipSuccess;
     int dev = 0, cus = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    if (blocks_per_cu <= 0) blocks_per_cu = 8;
+    if (blocks_per_cu <= 0) blocks_per_cu = 16;
     uint64_t blocks = static_cast<uint64_t>(cus) * blocks_per_cu;
-    // at least one stream per lane on average
+    // at least one queue of streams per wave on average
     const uint64_t max_blocks = (p.n + 255) / 256;
     if (blocks > max_blocks) blocks = max_blocks;
     if (blocks < 1) blocks = 1;
-    constexpr int D = 8;
     switch (seed_mode) {
-        case SEED_LOAD: return launch_draw_t<SEED_LOAD, D>(p, st, static_cast<int>(blocks));
-        case SEED_HASH: return launch_draw_t<SEED_HASH, D>(p, st, static_cast<int>(blocks));
-        default: return launch_draw_t<SEED_STRIDE, D>(p, st, static_cast<int>(blocks));
+        case SEED_LOAD: return launch_draw_m<SEED_LOAD>(p, st, static_cast<int>(blocks), round);
+        case SEED_HASH: return launch_draw_m<SEED_HASH>(p, st, static_cast<int>(blocks), round);
+        default: return launch_draw_m<SEED_STRIDE>(p, st, static_cast<int>(blocks), round);
     }
 }
 
