@@ -231,6 +231,8 @@ struct mcrng_ctx {
 
     DevBuf problems, edges64, sig64, scat64, cbin, edges32, sig32, tedges64, tedges32;
     DevBuf units, order, partial, unit_diag, counter, groups, dx, dt, pu_begin;
+    DevBuf bank_a, bank_b, records, rec_begin;   // event schedule
+    std::vector<uint64_t> h_rec_begin;
 
     // host copies of the current tables (kept alive while copies are staged)
     std::vector<DevProblem> h_problems;
@@ -308,7 +310,8 @@ extern "C" int mcrng_ctx_destroy(mcrng_ctx* ctx) {
     clear_graphs(ctx);
     DevBuf* bufs[] = {&ctx->problems, &ctx->edges64, &ctx->sig64, &ctx->scat64, &ctx->cbin, &ctx->edges32,
                       &ctx->sig32, &ctx->tedges64, &ctx->tedges32, &ctx->units, &ctx->order, &ctx->partial,
-                      &ctx->unit_diag, &ctx->counter, &ctx->groups, &ctx->dx, &ctx->dt, &ctx->pu_begin};
+                      &ctx->unit_diag, &ctx->counter, &ctx->groups, &ctx->dx, &ctx->dt, &ctx->pu_begin,
+                      &ctx->bank_a, &ctx->bank_b, &ctx->records, &ctx->rec_begin};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
@@ -545,6 +548,9 @@ static int build_tables(mcrng_ctx* ctx, const LcgDev& L, const mcrng_problem* P,
     }
     if (ctx->h_dt.empty()) ctx->h_dt.push_back(0.0);
     ctx->partial_words = slot;
+    ctx->h_rec_begin.assign(ctx->h_units.size() + 1, 0);
+    for (size_t u = 0; u < ctx->h_units.size(); ++u)
+        ctx->h_rec_begin[u + 1] = ctx->h_rec_begin[u] + ctx->h_units[u].count;
     int rc;
     if ((rc = upload(ctx->problems, ctx->h_problems, st)) < 0) return rc;
     if ((rc = upload(ctx->edges64, ctx->h_edges64, st)) < 0) return rc;
@@ -561,6 +567,7 @@ static int build_tables(mcrng_ctx* ctx, const LcgDev& L, const mcrng_problem* P,
     if ((rc = upload(ctx->dx, ctx->h_dx, st)) < 0) return rc;
     if ((rc = upload(ctx->dt, ctx->h_dt, st)) < 0) return rc;
     if ((rc = upload(ctx->pu_begin, ctx->h_pu_begin, st)) < 0) return rc;
+    if ((rc = upload(ctx->rec_begin, ctx->h_rec_begin, st)) < 0) return rc;
     if ((rc = ensure(ctx->partial, std::max<uint64_t>(slot, 2) * sizeof(uint64_t), st)) < 0) return rc;
     if ((rc = ensure(ctx->unit_diag, std::max<size_t>(ctx->h_units.size(), 1) * kNDiag * sizeof(uint64_t), st)) < 0)
         return rc;
@@ -666,8 +673,87 @@ static int enqueue_run(mcrng_ctx* ctx, const LcgDev& L, const mcrng_run_opts& o,
         return fail(MCRNG_EINVAL, "LDS needed (%zu bytes) exceeds the device's %d", transport_lds_bytes(tp, sh.f32),
                     dev_lds);
     HIP_TRY(launch_fill_u32(tp.unit_counter, 16, 0u, st));
-    if (o.schedule == MCRNG_SCHED_EVENT) return fail(MCRNG_EINVAL, "event schedule not available in this build");
     HIP_TRY(launch_transport(tp, sh, st, nullptr));
+    return MCRNG_OK;
+}
+
+// Carves one particle bank of `cap` entries out of a device buffer.
+static EventBank carve_bank(void* base, uint64_t cap) {
+    char* p = static_cast<char*>(base);
+    auto take = [&](size_t bytes) {
+        char* r = p;
+        p += (bytes + 255) & ~static_cast<size_t>(255);
+        return r;
+    };
+    EventBank b;
+    b.x64 = reinterpret_cast<double*>(take(cap * 8));
+    b.mu64 = reinterpret_cast<double*>(take(cap * 8));
+    b.t64 = reinterpret_cast<double*>(take(cap * 8));
+    b.tau64 = reinterpret_cast<double*>(take(cap * 8));
+    b.x32 = reinterpret_cast<float*>(take(cap * 4));
+    b.mu32 = reinterpret_cast<float*>(take(cap * 4));
+    b.t32 = reinterpret_cast<float*>(take(cap * 4));
+    b.tau32 = reinterpret_cast<float*>(take(cap * 4));
+    b.X = reinterpret_cast<uint64_t*>(take(cap * 8));
+    b.cell = reinterpret_cast<int32_t*>(take(cap * 4));
+    b.tb = reinterpret_cast<int32_t*>(take(cap * 4));
+    b.hdraws = reinterpret_cast<uint32_t*>(take(cap * 4));
+    b.events = reinterpret_cast<uint32_t*>(take(cap * 4));
+    b.colls = reinterpret_cast<uint32_t*>(take(cap * 4));
+    b.flags = reinterpret_cast<uint32_t*>(take(cap * 4));
+    b.unit = reinterpret_cast<uint32_t*>(take(cap * 4));
+    b.rec = reinterpret_cast<uint32_t*>(take(cap * 4));
+    return b;
+}
+static size_t bank_bytes(uint64_t cap) { return 17 * (((cap * 8) + 255) & ~static_cast<uint64_t>(255)); }
+
+// Event-sorted schedule: slices of whole work units fill a particle bank;
+// each launch advances every live particle by one event and compacts the
+// survivors into the other bank; the host reads the live count after each
+// launch.  Partial slots are zeroed and accumulated with integer atomics.
+static int run_event_schedule(mcrng_ctx* ctx, const LcgDev& L, const mcrng_run_opts& o, hipStream_t st) {
+    const uint64_t total = ctx->h_rec_begin.back();
+    if (total >> 32) return fail(MCRNG_EINVAL, "event schedule: more than 2^32 histories in one run");
+    uint64_t cap = o.bank_size ? o.bank_size : (1u << 22);
+    for (const WorkUnit& U : ctx->h_units) cap = std::max<uint64_t>(cap, U.count);
+    int rc;
+    if ((rc = ensure(ctx->bank_a, bank_bytes(cap), st)) < 0) return rc;
+    if ((rc = ensure(ctx->bank_b, bank_bytes(cap), st)) < 0) return rc;
+    if ((rc = ensure(ctx->records, std::max<uint64_t>(total, 1) * sizeof(HistoryRecord), st)) < 0) return rc;
+    EventParams ep;
+    std::memset(&ep, 0, sizeof ep);
+    ep.tp = make_params(ctx, L, 1);
+    ep.records = static_cast<HistoryRecord*>(ctx->records.p);
+    ep.rec_begin = static_cast<const uint64_t*>(ctx->rec_begin.p);
+    ep.n_out = static_cast<uint32_t*>(ctx->counter.p) + 1;
+    EventBank A = carve_bank(ctx->bank_a.p, cap), B = carve_bank(ctx->bank_b.p, cap);
+    const int f32 = o.precision == MCRNG_FP32;
+    const int timed = ctx->any_timed;
+    HIP_TRY(launch_fill_u64(ep.tp.partial, ctx->partial_words, 0ull, st));
+    const uint32_t nu = static_cast<uint32_t>(ctx->h_units.size());
+    uint32_t u0 = 0;
+    while (u0 < nu) {
+        uint32_t u1 = u0;
+        while (u1 < nu && ctx->h_rec_begin[u1 + 1] - ctx->h_rec_begin[u0] <= cap) ++u1;
+        ep.unit_begin = u0;
+        ep.unit_end = u1;
+        ep.in = A;
+        ep.out = B;
+        ep.n_in = static_cast<uint32_t>(ctx->h_rec_begin[u1] - ctx->h_rec_begin[u0]);
+        HIP_TRY(launch_event_init(ep, f32, timed, st));
+        while (ep.n_in > 0) {
+            HIP_TRY(launch_fill_u32(ep.n_out, 1, 0u, st));
+            HIP_TRY(launch_event_step(ep, f32, timed, st));
+            uint32_t live = 0;
+            HIP_TRY(hipMemcpyAsync(&live, ep.n_out, sizeof live, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            if (live > ep.n_in) return fail(MCRNG_EDEVICE, "event schedule: bank count grew");
+            std::swap(ep.in, ep.out);
+            ep.n_in = live;
+        }
+        u0 = u1;
+    }
+    HIP_TRY(launch_event_unit_diag(ep, st));
     return MCRNG_OK;
 }
 
@@ -677,7 +763,10 @@ static uint64_t opts_key(uint64_t tables_sig, const mcrng_run_opts& o) {
 
 static int run_prepared(mcrng_ctx* ctx, const LcgDev& L, const mcrng_run_opts& o, hipStream_t st) {
     HIP_TRY(hipEventRecord(ctx->ev0, st));
-    if (o.use_graph && o.schedule == MCRNG_SCHED_HISTORY) {
+    if (o.schedule == MCRNG_SCHED_EVENT) {
+        int rc = run_event_schedule(ctx, L, o, st);
+        if (rc < 0) return rc;
+    } else if (o.use_graph) {
         const uint64_t key = opts_key(ctx->tables_sig, o);
         auto it = ctx->graphs.find(key);
         if (it == ctx->graphs.end()) {

@@ -1,0 +1,220 @@
+// Event-sorted schedule for gfx950.
+//
+// The live particles sit in a structure-of-arrays bank in HBM.  One launch of
+// k_event_step advances every live particle by exactly one event (the same
+// step_particle as the history-based kernel, so the per-particle operation
+// sequence is identical); survivors are appended to the other bank through a
+// wave-aggregated atomic, so each launch compacts the bank.  Scores go to the
+// work unit's partial-tally slot with 64-bit global integer atomics (the
+// slots are zeroed first); the sums are exact, so the result is the same as
+// the history-based schedule's bit for bit.  A history that ends writes one
+// outcome record; k_event_unit_diag reduces the records of each unit in
+// history order into the unit's diagnostics slot.
+#include "particle.hpp"
+
+namespace mcrng {
+
+template <bool F32>
+struct BankView {
+    using R = typename std::conditional<F32, float, double>::type;
+    R* x; R* mu; R* t; R* tau;
+};
+
+template <bool F32>
+__device__ __forceinline__ BankView<F32> view(const EventBank& b) {
+    BankView<F32> v;
+    if constexpr (F32) {
+        v.x = b.x32; v.mu = b.mu32; v.t = b.t32; v.tau = b.tau32;
+    } else {
+        v.x = b.x64; v.mu = b.mu64; v.t = b.t64; v.tau = b.tau64;
+    }
+    return v;
+}
+
+template <bool F32>
+__device__ __forceinline__ CellsLds<F32> global_cells(const TransportParams& P, const DevProblem& PR) {
+    CellsLds<F32> C;
+    if constexpr (F32) {
+        C.edge = P.edges32 + PR.edge_off;
+        C.sig = P.sig32 + PR.cell_off;
+        C.tedge = P.tedges32 + PR.tedge_off;
+    } else {
+        C.edge = P.edges64 + PR.edge_off;
+        C.sig = P.sig64 + PR.cell_off;
+        C.tedge = P.tedges64 + PR.tedge_off;
+    }
+    C.scat = P.scat64 + PR.cell_off;
+    C.bin = P.cbin + PR.cell_off;
+    C.n_cells = static_cast<int32_t>(PR.n_cells);
+    C.n_time_bins = static_cast<int32_t>(PR.n_time_bins);
+    C.n_space_bins = static_cast<int32_t>(PR.n_space_bins);
+    return C;
+}
+
+template <bool F32>
+__device__ __forceinline__ void store_particle(const EventBank& b, uint32_t i, const Particle<F32>& p, uint32_t ev,
+                                               uint32_t co, uint32_t unit, uint32_t rec) {
+    BankView<F32> v = view<F32>(b);
+    v.x[i] = p.x;
+    v.mu[i] = p.mu;
+    v.t[i] = p.t;
+    v.tau[i] = p.tau;
+    b.X[i] = p.X;
+    b.cell[i] = p.cell;
+    b.tb[i] = p.tb;
+    b.hdraws[i] = p.hdraws;
+    b.events[i] = ev;
+    b.colls[i] = co;
+    b.flags[i] = p.need_tau ? 1u : 0u;
+    b.unit[i] = unit;
+    b.rec[i] = rec;
+}
+
+// Particle i of the slice [unit_begin, unit_end): the unit is found by binary
+// search over the units' first-record indices.
+template <bool F32, bool TIMED>
+__global__ void __launch_bounds__(256) k_event_init(EventParams E) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= E.n_in) return;
+    const uint64_t r = E.rec_begin[E.unit_begin] + i;
+    uint32_t lo = E.unit_begin, hi = E.unit_end;   // last unit with rec_begin <= r
+    while (hi - lo > 1) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        if (E.rec_begin[mid] <= r) lo = mid; else hi = mid;
+    }
+    const WorkUnit U = E.tp.units[lo];
+    const DevProblem PR = E.tp.problems[U.problem];
+    const CellsLds<F32> C = global_cells<F32>(E.tp, PR);
+    SeedDev S;
+    S.kind = static_cast<int>(PR.seed_kind);
+    S.stride_digits = PR.stride_digits;
+    S.base = PR.seed_base;
+    S.first_index = PR.first_index;
+    S.table = PR.table;
+    Particle<F32> p;
+    init_particle<F32, TIMED>(p, C, E.tp.lcg, S, U.j0 + (r - E.rec_begin[lo]));
+    store_particle<F32>(E.in, i, p, 0u, 0u, lo, static_cast<uint32_t>(r));
+}
+
+template <bool F32, bool TIMED>
+__global__ void __launch_bounds__(256) k_event_step(EventParams E) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t lane = threadIdx.x & 63u;
+    bool alive = false;
+    Particle<F32> p;
+    uint32_t unit = 0, rec = 0;
+    LaneCounters cnt;
+    if (i < E.n_in) {
+        BankView<F32> v = view<F32>(E.in);
+        p.x = v.x[i];
+        p.mu = v.mu[i];
+        p.t = v.t[i];
+        p.tau = v.tau[i];
+        p.X = E.in.X[i];
+        p.cell = E.in.cell[i];
+        p.tb = E.in.tb[i];
+        p.hdraws = E.in.hdraws[i];
+        p.need_tau = (E.in.flags[i] & 1u) != 0;
+        cnt.events = E.in.events[i];
+        cnt.collisions = E.in.colls[i];
+        unit = E.in.unit[i];
+        rec = E.in.rec[i];
+        const WorkUnit U = E.tp.units[unit];
+        const DevProblem PR = E.tp.problems[U.problem];
+        const CellsLds<F32> C = global_cells<F32>(E.tp, PR);
+        uint64_t* tally = E.tp.partial + U.slot;
+        const int end = step_particle<F32, TIMED>(p, C, E.tp.lcg, tally, cnt);
+        if (end != END_NONE) {
+            HistoryRecord h;
+            h.events = static_cast<uint32_t>(cnt.events);
+            h.collisions = static_cast<uint32_t>(cnt.collisions);
+            h.draws = p.hdraws;
+            h.end = static_cast<uint32_t>(end);
+            E.records[rec] = h;
+        } else {
+            alive = true;
+        }
+    }
+    // compaction: survivors of the wave go to consecutive slots of `out`
+    const uint64_t mask = __ballot(alive);
+    if (mask == 0) return;
+    const uint32_t cnt_alive = static_cast<uint32_t>(__popcll(mask));
+    const int leader = __ffsll(static_cast<unsigned long long>(mask)) - 1;
+    uint32_t base = 0;
+    if (static_cast<int>(lane) == leader) base = atomicAdd(E.n_out, cnt_alive);
+    base = __shfl(base, leader);
+    if (alive) {
+        const uint32_t lt = static_cast<uint32_t>(__popcll(mask & ((lane == 0) ? 0ull : (~0ull >> (64 - lane)))));
+        store_particle<F32>(E.out, base + lt, p, static_cast<uint32_t>(cnt.events),
+                            static_cast<uint32_t>(cnt.collisions), unit, rec);
+    }
+}
+
+// One block per unit: the unit's records, in history order, into its
+// diagnostics slot.
+__global__ void __launch_bounds__(256) k_event_unit_diag(EventParams E) {
+    const uint32_t u = blockIdx.x;
+    const WorkUnit U = E.tp.units[u];
+    const DevProblem PR = E.tp.problems[U.problem];
+    __shared__ unsigned long long acc[kNDiag];
+    if (threadIdx.x < kNDiag) acc[threadIdx.x] = 0;
+    __syncthreads();
+    unsigned long long loc[kNDiag];
+#pragma unroll
+    for (int k = 0; k < kNDiag; ++k) loc[k] = 0;
+    const uint64_t r0 = E.rec_begin[u];
+    for (uint32_t j = threadIdx.x; j < U.count; j += blockDim.x) {
+        const HistoryRecord h = E.records[r0 + j];
+        loc[D_HISTORIES] += 1;
+        loc[D_LEAK_LEFT] += (h.end == END_LEAK_LEFT);
+        loc[D_LEAK_RIGHT] += (h.end == END_LEAK_RIGHT);
+        loc[D_ABSORBED] += (h.end == END_ABSORBED);
+        loc[D_CENSUS] += (h.end == END_CENSUS);
+        loc[D_EVENTS] += h.events;
+        loc[D_COLLISIONS] += h.collisions;
+        loc[D_DRAWS] += h.draws;
+        loc[D_MAX_DRAWS] = h.draws > loc[D_MAX_DRAWS] ? h.draws : loc[D_MAX_DRAWS];
+        loc[D_OVER_STRIDE] += (PR.stride_q != 0 && h.draws > PR.stride_q);
+    }
+#pragma unroll
+    for (int k = 0; k < kNDiag; ++k) {
+        if (k == D_MAX_DRAWS)
+            atomicMax(&acc[k], loc[k]);
+        else
+            atomicAdd(&acc[k], loc[k]);
+    }
+    __syncthreads();
+    if (threadIdx.x < kNDiag) E.tp.unit_diag[static_cast<size_t>(u) * kNDiag + threadIdx.x] = acc[threadIdx.x];
+}
+
+template <bool F32, bool TIMED>
+static hipError_t init_t(const EventParams& p, hipStream_t st) {
+    hipLaunchKernelGGL((k_event_init<F32, TIMED>), dim3((p.n_in + 255) / 256), dim3(256), 0, st, p);
+    return hipGetLastError();
+}
+
+template <bool F32, bool TIMED>
+static hipError_t step_t(const EventParams& p, hipStream_t st) {
+    hipLaunchKernelGGL((k_event_step<F32, TIMED>), dim3((p.n_in + 255) / 256), dim3(256), 0, st, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_event_init(const EventParams& p, int f32, int timed, hipStream_t st) {
+    if (p.n_in == 0) return hipSuccess;
+    if (f32) return timed ? init_t<true, true>(p, st) : init_t<true, false>(p, st);
+    return timed ? init_t<false, true>(p, st) : init_t<false, false>(p, st);
+}
+
+hipError_t launch_event_step(const EventParams& p, int f32, int timed, hipStream_t st) {
+    if (p.n_in == 0) return hipSuccess;
+    if (f32) return timed ? step_t<true, true>(p, st) : step_t<true, false>(p, st);
+    return timed ? step_t<false, true>(p, st) : step_t<false, false>(p, st);
+}
+
+hipError_t launch_event_unit_diag(const EventParams& p, hipStream_t st) {
+    if (p.tp.n_units == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_event_unit_diag, dim3(p.tp.n_units), dim3(256), 0, st, p);
+    return hipGetLastError();
+}
+
+}  // namespace mcrng

@@ -127,29 +127,45 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t st);
 
 // ------------------------------------------------------------ event schedule
 
+// Structure-of-arrays particle bank (capacity entries per array).  The
+// FP64 or FP32 position arrays are used according to the precision.
 struct EventBank {
-    // structure-of-arrays particle bank, capacity entries each
     double* x64; double* mu64; double* t64; double* tau64;
     float* x32; float* mu32; float* t32; float* tau32;
     uint64_t* X;             // LCG state
     int32_t* cell;
     int32_t* tb;
-    uint32_t* hdraws;        // draws of the history so far
-    uint32_t* flags;         // bit 0: need a fresh tau
-    uint32_t* unit;          // work unit (selects the partial-tally slice)
+    uint32_t* hdraws;        // numbers drawn by the history so far
+    uint32_t* events;        // events of the history so far
+    uint32_t* colls;         // collisions of the history so far
+    uint32_t* flags;         // bit 0: the next step samples a flight
+    uint32_t* unit;          // work unit (partial-tally slot, problem)
+    uint32_t* rec;           // index of the history's outcome record
+};
+
+// Outcome of one history, written once when it ends.
+struct HistoryRecord {
+    uint32_t events;
+    uint32_t collisions;
+    uint32_t draws;
+    uint32_t end;            // END_LEAK_LEFT .. END_CENSUS
 };
 
 struct EventParams {
-    TransportParams tp;
+    TransportParams tp;      // tables, units, partial slots (atomically accumulated)
     EventBank in, out;
-    uint32_t n_in;
-    uint32_t* n_out;         // atomic append counter of the next bank
-    // init only: histories [j0, j0 + n_in) of unit `unit`
-    uint32_t init_unit;
+    uint32_t n_in;           // live particles in `in`
+    uint32_t* n_out;         // append counter of `out`
+    HistoryRecord* records;  // one per history of the run
+    const uint64_t* rec_begin;   // per unit: index of its first record
+    // init: the histories of units [unit_begin, unit_end), n_in in total
+    uint32_t unit_begin;
+    uint32_t unit_end;
 };
 
 hipError_t launch_event_init(const EventParams& p, int f32, int timed, hipStream_t st);
 hipError_t launch_event_step(const EventParams& p, int f32, int timed, hipStream_t st);
+hipError_t launch_event_unit_diag(const EventParams& p, hipStream_t st);
 
 // ------------------------------------------------------------ reduction
 

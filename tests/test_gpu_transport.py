@@ -127,6 +127,33 @@ def test_graph_replays_match_eager(M, ctx, orc):
     assert split(eager[0], probs)[:8] == ref
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_event_schedule_matches_oracle_and_history(M, ctx, orc, precision):
+    """Event-sorted schedule (one event per particle per launch, compacted
+    bank) gives the history-based schedule's and the oracle's bits."""
+    p = W.multi_region(n_histories=60_007)
+    ref = orc.transport(p, LCG, float_mode=bool(precision), threads=8)
+    hist = run(M, ctx, [p], precision=precision)
+    assert hist[0] == ref.raw
+    for bank, unit in ((0, 0), (10_000, 3_001), (4_000, 4_096)):
+        say("event schedule", precision, bank, unit)
+        ev = run(M, ctx, [p], precision=precision, schedule=1, bank_size=bank, unit_histories=unit)
+        assert ev[0] == ref.raw, (bank, unit)
+        assert ev[2][0] == ref.diag
+        assert np.array_equal(ev[1], hist[1])
+
+
+def test_event_schedule_batched_and_stride(M, ctx, orc):
+    probs = W.batched(seeding_kind="stride", scale=5e-4)[:40] + [W.small_slab(n_histories=333)]
+    say("event schedule batched")
+    ev = run(M, ctx, probs, schedule=1, bank_size=20_000)
+    hist = run(M, ctx, probs)
+    assert ev[0] == hist[0] and ev[2] == hist[2]
+    parts = split(ev[0], probs)
+    for i in (0, 7, 40):
+        assert parts[i] == orc.transport(probs[i], LCG).raw
+
+
 def test_zero_histories_and_edge_problems(M, ctx, orc):
     probs = [W.small_slab(n_histories=0), W.small_slab(n_histories=1),
              W.homogeneous(1.0, 2.0, 0.0, 1, 777), W.small_slab(n_histories=64)]
@@ -188,6 +215,9 @@ def test_multi_region_full_size_sharded(M, ctx, orc):
     rs, _, ds = run(M, ctx, [sub])
     ref = orc.transport(sub, LCG, threads=16)
     assert rs == ref.raw and ds[0] == ref.diag
+    say("multi region full, event-sorted schedule")
+    re_, _, de = run(M, ctx, [p], schedule=1)
+    assert re_ == raw and de == diag
 
 
 def test_batched_full_size_small_problems(M, ctx, orc):
