@@ -267,10 +267,17 @@ double orc_ln(double u)
  *
  * FP32 flight mode: tau is computed in double by orc_ln and rounded once
  * to float; mu = 2 u2 - 1 is computed in double (exact) and rounded once
- * to float; s, x, mu, t, sigma_t and the edges are floats (edges and
- * sigma_t rounded once from the double inputs); every distance, position
- * and time operation is one IEEE single operation.  The absorption test
- * u1 < c stays in double; q is computed from (double)s.
+ * to float; the position is kept relative to the current cell's left edge
+ * (xl in [0, W[cell]]) and the time relative to the current time bin's
+ * start (tl in [0, DT[tb]]), so FP32 keeps its relative precision deep in a
+ * thick slab and late in a long run; s, xl, mu, tl, sigma_t, the cell widths
+ * W and the time-bin durations DT are floats (W, DT and sigma_t rounded once
+ * from doubles); every distance, position and time operation is one IEEE
+ * single operation:  se = (W - xl)/mu (mu > 0), (0 - xl)/mu (mu < 0);
+ * st = DT[tb] - tl; tl = tl + s clamped to DT[tb]; an edge crossing sets
+ * xl = 0 (moving right) or xl = W[new cell] (moving left); a time step sets
+ * tl = 0.  The absorption test u1 < c stays in double; q is computed from
+ * (double)s.
  */
 /* ------------------------------------------------------------------ */
 
@@ -415,36 +422,36 @@ static void history_f64(const orc_problem *P, orc_rng *R, u128 *T, uint64_t *d, 
     }
 }
 
-static void history_f32(const orc_problem *P, const float *E, const float *SG, const float *TE,
+static void history_f32(const orc_problem *P, const float *W, const float *SG, const float *DT,
                         orc_rng *R, u128 *T, uint64_t *d, orc_log *lg)
 {
     const int nc = P->n_cells, nt = P->n_time_bins, nsb = P->n_space_bins;
     const int timed = nt > 0;
-    float x = E[0], mu = 1.0f, t = timed ? TE[0] : 0.0f;
+    float xl = 0.0f, mu = 1.0f, tl = 0.0f;   /* position in the cell, time in the time bin */
     int cell = 0, tb = 0;
     float tau = (float)(-orc_ln(rng_draw(R)));
     for (;;) {
-        const float sig = SG[cell];
+        const float sig = SG[cell], w = W[cell];
         float s = tau / sig;
         int ev = EV_COLL;
         float se;
         if (mu > 0.0f)
-            se = (E[cell + 1] - x) / mu;
+            se = (w - xl) / mu;
         else if (mu < 0.0f)
-            se = (E[cell] - x) / mu;
+            se = (0.0f - xl) / mu;
         else
             se = INFINITY;
         if (se < s) { s = se; ev = EV_EDGE; }
         if (timed) {
-            float st = TE[tb + 1] - t;
+            float st = DT[tb] - tl;
             if (st < s) { s = st; ev = EV_TIME; }
         }
         T[(size_t)tb * nsb + P->bin[cell]] += quantise((double)s);
         d[ORC_D_EVENTS]++;
         log_event(lg, ev, cell, tb, (double)s);
         if (timed) {
-            t = t + s;
-            if (t > TE[tb + 1]) t = TE[tb + 1];
+            tl = tl + s;
+            if (tl > DT[tb]) tl = DT[tb];
         }
         float dtau = sig * s;
         tau = tau - dtau;
@@ -453,22 +460,22 @@ static void history_f32(const orc_problem *P, const float *E, const float *SG, c
             if (mu > 0.0f) {
                 cell = cell + 1;
                 if (cell == nc) { d[ORC_D_LEAK_RIGHT]++; break; }
-                x = E[cell];
+                xl = 0.0f;
             } else {
-                x = E[cell];
                 cell = cell - 1;
                 if (cell < 0) { d[ORC_D_LEAK_LEFT]++; break; }
+                xl = W[cell];
             }
             continue;
         }
         float step = mu * s;
-        float nx = x + step;
-        if (nx < E[cell]) nx = E[cell];
-        if (nx > E[cell + 1]) nx = E[cell + 1];
-        x = nx;
+        float nx = xl + step;
+        if (nx < 0.0f) nx = 0.0f;
+        if (nx > w) nx = w;
+        xl = nx;
         if (ev == EV_TIME) {
             tb = tb + 1;
-            t = TE[tb];
+            tl = 0.0f;
             if (tb == nt) { d[ORC_D_CENSUS]++; break; }
             continue;
         }
@@ -480,6 +487,25 @@ static void history_f32(const orc_problem *P, const float *E, const float *SG, c
         double u3 = rng_draw(R);
         tau = (float)(-orc_ln(u3));
     }
+}
+
+/* FP32 copies, each rounded once from a double: cell widths
+ * W[c] = (float)(E[c+1] - E[c]), total cross sections, time-bin durations
+ * DT[t] = (float)(T[t+1] - T[t]). */
+static float *f32_tables(const orc_problem *P, float **W, float **SG, float **DT)
+{
+    const int nc = P->n_cells, nt = P->n_time_bins;
+    float *f = (float *)calloc((size_t)(2 * nc + nt + 1), sizeof(float));
+    if (!f) return NULL;
+    *W = f;
+    *SG = f + nc;
+    *DT = f + 2 * nc;
+    for (int i = 0; i < nc; ++i) {
+        (*W)[i] = (float)(P->edges[i + 1] - P->edges[i]);
+        (*SG)[i] = (float)P->sigma_t[i];
+    }
+    for (int i = 0; i < nt; ++i) (*DT)[i] = (float)(P->t_edges[i + 1] - P->t_edges[i]);
+    return f;
 }
 
 /* Tally slice sizes: per batch, n_time_bins' x n_space_bins, with
@@ -522,17 +548,12 @@ int orc_transport(const orc_problem *P, int float_mode, uint64_t j0, uint64_t j1
     if (P->lcg.m < 53 || P->lcg.m > 64) return -1;
     const size_t sb = slice_bins(P);
     const size_t nb = P->n_batches ? P->n_batches : 1;
-    const int nc = P->n_cells, nt = P->n_time_bins;
     const size_t need = sb * nb;
     /* 128-bit accumulators for this call, added into the caller's words at the end */
     u128 *acc = (u128 *)calloc(need, sizeof(u128));
-    float *f32 = (float *)calloc((size_t)(2 * nc + nt + 3), sizeof(float));
+    float *W32 = NULL, *SG32 = NULL, *DT32 = NULL;
+    float *f32 = f32_tables(P, &W32, &SG32, &DT32);
     if (!acc || !f32) { free(acc); free(f32); return -1; }
-    /* FP32 mode copies: edges (nc+1), sigma_t (nc), time edges (nt+1) */
-    float *E32 = f32, *SG32 = f32 + nc + 1, *TE32 = f32 + 2 * nc + 1;
-    for (int i = 0; i <= nc; ++i) E32[i] = (float)P->edges[i];
-    for (int i = 0; i < nc; ++i) SG32[i] = (float)P->sigma_t[i];
-    for (int i = 0; nt > 0 && i <= nt; ++i) TE32[i] = (float)P->t_edges[i];
     for (uint64_t j = j0; j < j1; ++j) {
         orc_rng R;
         memset(&R, 0, sizeof R);
@@ -540,7 +561,7 @@ int orc_transport(const orc_problem *P, int float_mode, uint64_t j0, uint64_t j1
         R.x = orc_stream_start(&P->lcg, &P->seeding, j);
         u128 *T = acc + (size_t)batch_of(P, j) * sb;
         if (float_mode)
-            history_f32(P, E32, SG32, TE32, &R, T, diag, NULL);
+            history_f32(P, W32, SG32, DT32, &R, T, diag, NULL);
         else
             history_f64(P, &R, T, diag, NULL);
         update_diag_history(P, diag, R.draws);
@@ -568,7 +589,6 @@ int64_t orc_transport_scripted(const orc_problem *P, int float_mode,
 {
     if (!P || !u || !tally_lo || !tally_hi || !diag) return -1;
     const size_t sb = slice_bins(P);
-    const int nc = P->n_cells, nt = P->n_time_bins;
     u128 T[4096];
     if (sb > 4096) return -1;
     memset(T, 0, sizeof T);
@@ -579,13 +599,10 @@ int64_t orc_transport_scripted(const orc_problem *P, int float_mode,
     R.n_script = n_u;
     orc_log lg = { log, log_cap, 0 };
     if (float_mode) {
-        float *f32 = (float *)calloc((size_t)(2 * nc + nt + 3), sizeof(float));
+        float *W32 = NULL, *SG32 = NULL, *DT32 = NULL;
+        float *f32 = f32_tables(P, &W32, &SG32, &DT32);
         if (!f32) return -1;
-        float *E32 = f32, *SG32 = f32 + nc + 1, *TE32 = f32 + 2 * nc + 1;
-        for (int i = 0; i <= nc; ++i) E32[i] = (float)P->edges[i];
-        for (int i = 0; i < nc; ++i) SG32[i] = (float)P->sigma_t[i];
-        for (int i = 0; nt > 0 && i <= nt; ++i) TE32[i] = (float)P->t_edges[i];
-        history_f32(P, E32, SG32, TE32, &R, T, diag, &lg);
+        history_f32(P, W32, SG32, DT32, &R, T, diag, &lg);
         free(f32);
     } else {
         history_f64(P, &R, T, diag, &lg);

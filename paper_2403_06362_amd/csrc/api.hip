@@ -538,13 +538,23 @@ static int build_tables(mcrng_ctx* ctx, const LcgDev& L, const mcrng_problem* P,
     std::stable_sort(ctx->h_order.begin(), ctx->h_order.end(), [&](uint32_t x, uint32_t y) {
         return ctx->h_units[x].count > ctx->h_units[y].count;
     });
-    // FP32 copies, rounded once from the doubles
-    ctx->h_edges32.assign(ctx->h_edges64.begin(), ctx->h_edges64.end());
+    // FP32 flight tables, each rounded once from a double: per problem the
+    // cell widths (n_cells, then a 0 to keep the edge offsets) and the
+    // time-bin durations (n_time_bins, then a 0)
+    ctx->h_edges32.assign(ctx->h_edges64.size(), 0.0f);
+    ctx->h_tedges32.assign(ctx->h_tedges64.size(), 0.0f);
+    for (const DevProblem& D : ctx->h_problems) {
+        for (uint32_t c = 0; c < D.n_cells; ++c)
+            ctx->h_edges32[D.edge_off + c] =
+                static_cast<float>(ctx->h_edges64[D.edge_off + c + 1] - ctx->h_edges64[D.edge_off + c]);
+        for (uint32_t t = 0; t < D.n_time_bins; ++t)
+            ctx->h_tedges32[D.tedge_off + t] =
+                static_cast<float>(ctx->h_tedges64[D.tedge_off + t + 1] - ctx->h_tedges64[D.tedge_off + t]);
+    }
     ctx->h_sig32.assign(ctx->h_sig64.begin(), ctx->h_sig64.end());
-    ctx->h_tedges32.assign(ctx->h_tedges64.begin(), ctx->h_tedges64.end());
     if (ctx->h_tedges64.empty()) {
         ctx->h_tedges64.push_back(0.0);
-        ctx->h_tedges32.push_back(0.0f);
+        ctx->h_tedges32.assign(1, 0.0f);
     }
     if (ctx->h_dt.empty()) ctx->h_dt.push_back(0.0);
     ctx->partial_words = slot;

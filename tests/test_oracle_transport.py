@@ -115,21 +115,40 @@ def test_scripted_regions_change_cross_section(orc):
 
 
 def test_scripted_float_mode(orc):
-    p = slab([0, 4], [1.0], [0.5], [0, 1, 2, 3, 4])
-    raw, d, ev, used = orc.transport_scripted(p, LCG, [0.125, 0.25, 0.125, 0.5, 0.75], float_mode=True)
+    """FP32 flight: position relative to the cell's left edge, every
+    operation a single-precision one, widths rounded once from doubles."""
+    p = slab([0, 10], [1.0], [0.5], [0, 3.3, 10])
+    raw, d, ev, used = orc.transport_scripted(p, LCG, [2.0 ** -5, 0.25, 0.125, 0.5, 0.75], float_mode=True)
     f = np.float32
-    tau = f(-orc.ln(0.125))
-    tau = f(tau - f(1.0))
-    tau = f(tau - f(1.0))
-    s3 = f(tau / f(1.0))
-    x3 = f(f(2.0) + f(f(1.0) * s3))
+    W0, W1 = f(3.3 - 0.0), f(10.0 - 3.3)
+    tau = f(-orc.ln(2.0 ** -5))
+    s1 = f(f(W0 - f(0)) / f(1))                 # edge of cell 0 (tau > 3.3)
+    tau = f(tau - f(f(1) * s1))
+    s2 = f(tau / f(1))                          # collision in cell 1, local position s2
+    xl = f(f(0) + f(f(1) * s2))
     mu = f(2.0 * 0.125 - 1.0)
     tau = f(-orc.ln(0.5))
-    s4 = f(f(f(2.0) - x3) / mu)
-    s5 = f(f(tau - f(f(1.0) * s4)) / f(1.0))
-    assert [e[0] for e in ev] == [1, 1, 0, 1, 0]
-    assert [e[3] for e in ev] == [1.0, 1.0, float(s3), float(s4), float(s5)]
-    assert raw == [qexact(1.0), qexact(1.0) + qexact(float(s5)), qexact(float(s3)) + qexact(float(s4)), 0]
+    s3 = f(f(f(0) - xl) / mu)                   # back to the edge at 3.3
+    tau = f(tau - f(f(1) * s3))
+    s4 = f(tau / f(1))                          # collision in cell 0, then absorbed
+    assert used == 5 and d["absorbed"] == 1
+    assert [e[0] for e in ev] == [1, 0, 1, 0] and [e[1] for e in ev] == [0, 1, 1, 0]
+    assert [e[3] for e in ev] == [float(s1), float(s2), float(s3), float(s4)]
+    assert raw == [qexact(float(s1)) + qexact(float(s4)), qexact(float(s2)) + qexact(float(s3))]
+
+
+def test_scripted_float_mode_time_local(orc):
+    """FP32 time is kept relative to the time bin's start."""
+    p = slab([0, 200], [0.3], [1.0], [0, 80, 200], time_edges=[0, 33.3, 100])
+    raw, d, ev, used = orc.transport_scripted(p, LCG, [2.0 ** -53], float_mode=True)
+    f = np.float32
+    assert d["census"] == 1 and used == 1 and [e[0] for e in ev] == [2, 1, 2]
+    dt0, dt1, w0 = f(33.3 - 0.0), f(100.0 - 33.3), f(80.0 - 0.0)
+    s1 = dt0                                      # end of the first time bin at x = s1
+    s2 = f(w0 - s1)                               # the edge at x = 80, local time s2
+    s3 = f(dt1 - s2)                              # rest of the second time bin: census
+    assert [e[3] for e in ev] == [float(s1), float(s2), float(s3)]
+    assert raw == [qexact(float(s1)), 0, qexact(float(s2)), qexact(float(s3))]
 
 
 # ------------------------------------------------------------ closed forms
