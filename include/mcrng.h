@@ -144,7 +144,11 @@ enum { MCRNG_SCHED_HISTORY = 0, MCRNG_SCHED_EVENT = 1 };
  *   tally_copies    LDS tally copies per block: 1, or one per wave (= 2)
  *   use_graph       1 = capture the launches of a run in a hipGraph once
  *                   per (problem set, options) and replay it
- *   bank_size       event schedule: particles per bank slice */
+ *   bank_size       event schedule: particles per bank slice
+ *   coll_batch      history schedule: a wave runs its collision phase
+ *                   (absorption draw, new direction, next flight) once this
+ *                   many of its lanes wait at a collision site (1..64 per
+ *                   history slot; default 32) */
 typedef struct {
     uint32_t precision;
     uint32_t schedule;
@@ -155,7 +159,8 @@ typedef struct {
     uint32_t tally_copies;
     uint32_t use_graph;
     uint32_t bank_size;
-    uint32_t reserved[7];        /* must be 0 */
+    uint32_t coll_batch;
+    uint32_t reserved[6];        /* must be 0 */
 } mcrng_run_opts;
 
 /* Diagnostics per problem, MCRNG_NDIAG uint64 words in this order.  All are

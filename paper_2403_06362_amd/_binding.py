@@ -57,7 +57,7 @@ class RunOpts(C.Structure):
     _fields_ = [("precision", C.c_uint32), ("schedule", C.c_uint32), ("block", C.c_uint32),
                 ("hist_per_lane", C.c_uint32), ("unit_histories", C.c_uint32), ("grid", C.c_uint32),
                 ("tally_copies", C.c_uint32), ("use_graph", C.c_uint32), ("bank_size", C.c_uint32),
-                ("reserved", C.c_uint32 * 7)]
+                ("coll_batch", C.c_uint32), ("reserved", C.c_uint32 * 6)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}

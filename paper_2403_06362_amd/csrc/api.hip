@@ -598,6 +598,7 @@ static TransportParams make_params(mcrng_ctx* ctx, const LcgDev& L, uint32_t cop
     tp.max_tedges = ctx->max_tedges;
     tp.max_slice = ctx->max_slice;
     tp.tally_copies = copies;
+    tp.coll_batch = 1;
     tp.edges64 = static_cast<const double*>(ctx->edges64.p);
     tp.sig64 = static_cast<const double*>(ctx->sig64.p);
     tp.scat64 = static_cast<const double*>(ctx->scat64.p);
@@ -625,6 +626,8 @@ static int normalise_opts(const mcrng_run_opts* in, mcrng_run_opts* o) {
     if (o->hist_per_lane == 0) o->hist_per_lane = 1;
     if (o->hist_per_lane != 1 && o->hist_per_lane != 2 && o->hist_per_lane != 4)
         return fail(MCRNG_EINVAL, "opts.hist_per_lane = %u not in {1,2,4}", o->hist_per_lane);
+    if (o->coll_batch == 0) o->coll_batch = 32;
+    if (o->coll_batch > 64 * o->hist_per_lane) o->coll_batch = 64 * o->hist_per_lane;
     if (o->tally_copies == 0) o->tally_copies = 1;
     if (o->tally_copies > 2) return fail(MCRNG_EINVAL, "opts.tally_copies must be 1 or 2");
     return MCRNG_OK;
@@ -671,6 +674,7 @@ extern "C" int mcrng_run_histories(mcrng_ctx* ctx, const mcrng_lcg* lcg, const m
 
 static int enqueue_run(mcrng_ctx* ctx, const LcgDev& L, const mcrng_run_opts& o, hipStream_t st) {
     TransportParams tp = make_params(ctx, L, o.tally_copies == 2 ? std::max<uint32_t>(o.block / 64, 1) : 1);
+    tp.coll_batch = o.coll_batch;
     LaunchShape sh;
     sh.block = static_cast<int>(o.block);
     sh.hist_per_lane = static_cast<int>(o.hist_per_lane);
@@ -894,6 +898,7 @@ extern "C" int mcrng_autotune(mcrng_ctx* ctx, const mcrng_lcg* lcg, const mcrng_
     if ((rc = try_field(&mcrng_run_opts::block, {64, 128, 256, 512, 1024})) < 0) return rc;
     if ((rc = try_field(&mcrng_run_opts::hist_per_lane, {1, 2, 4})) < 0) return rc;
     if ((rc = try_field(&mcrng_run_opts::tally_copies, {1, 2})) < 0) return rc;
+    if ((rc = try_field(&mcrng_run_opts::coll_batch, {1, 16, 24, 32, 48})) < 0) return rc;
     const uint32_t u0 = default_unit_histories(problems, n_problems);
     if ((rc = try_field(&mcrng_run_opts::unit_histories, {u0 / 4 > 256 ? u0 / 4 : 256, u0, u0 * 4})) < 0) return rc;
     if (cur.unit_histories == 0) cur.unit_histories = u0;

@@ -97,7 +97,7 @@ struct TransportParams {
     uint32_t max_tedges;         // largest n_time_bins + 1 (0 if all steady)
     uint32_t max_slice;          // largest slice_bins
     uint32_t tally_copies;       // 1 or waves per block
-    uint32_t pad_;
+    uint32_t coll_batch;         // run a wave's collision phase once this many of its lanes wait (>= 1)
     const double* edges64;       // flat cell arrays
     const double* sig64;
     const double* scat64;

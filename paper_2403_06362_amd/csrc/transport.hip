@@ -165,11 +165,16 @@ __global__ void __launch_bounds__(BLOCK) k_transport(TransportParams P) {
 
         LaneCounters cnt;
         Particle<F32> p[H];
-        bool alive[H];
+        bool alive[H], pend[H], pcoll[H];
 #pragma unroll
-        for (int h = 0; h < H; ++h) alive[h] = false;
+        for (int h = 0; h < H; ++h) alive[h] = pend[h] = pcoll[h] = false;
         bool exhausted = false;   // wave-uniform
 
+        // Each iteration: refill idle lanes; geometry step for the lanes not
+        // waiting on a collision; then, once enough lanes wait (or none can
+        // move), the collision phase for all waiting lanes together
+        // (collision draws and the next flight, the expensive, rarer part).
+        // Every particle still runs its own operations in its own order.
         for (;;) {
 #pragma unroll
             for (int h = 0; h < H; ++h) {
@@ -187,6 +192,8 @@ __global__ void __launch_bounds__(BLOCK) k_transport(TransportParams P) {
                             if (j < U.count) {
                                 init_particle<F32, TIMED>(p[h], C, P.lcg, S, U.j0 + j);
                                 alive[h] = true;
+                                pend[h] = true;     // waits for its first flight
+                                pcoll[h] = false;
                             }
                         }
                     }
@@ -198,11 +205,37 @@ __global__ void __launch_bounds__(BLOCK) k_transport(TransportParams P) {
             if (__ballot(any) == 0) break;
 #pragma unroll
             for (int h = 0; h < H; ++h) {
-                if (alive[h]) {
-                    const int end = step_particle<F32, TIMED>(p[h], C, P.lcg, tally, cnt);
-                    if (end != END_NONE) {
-                        end_history(cnt, end, p[h].hdraws, PR.stride_q);
+                if (alive[h] && !pend[h]) {
+                    const int r = geom_step<F32, TIMED>(p[h], C, tally, cnt);
+                    if (r == STEP_COLLIDE) {
+                        pend[h] = true;
+                        pcoll[h] = true;
+                    } else if (r != END_NONE) {
+                        end_history(cnt, r, p[h].hdraws, PR.stride_q);
                         alive[h] = false;
+                    }
+                }
+            }
+            uint32_t npend = 0, nfree = 0;
+#pragma unroll
+            for (int h = 0; h < H; ++h) {
+                npend += static_cast<uint32_t>(__popcll(__ballot(alive[h] && pend[h])));
+                nfree += static_cast<uint32_t>(__popcll(__ballot(alive[h] && !pend[h])));
+            }
+            if (npend > 0 && (npend >= P.coll_batch || nfree == 0)) {
+#pragma unroll
+                for (int h = 0; h < H; ++h) {
+                    if (alive[h] && pend[h]) {
+                        int r = END_NONE;
+                        if (pcoll[h]) r = collide<F32>(p[h], C, P.lcg, cnt);
+                        if (r != END_NONE) {
+                            end_history(cnt, r, p[h].hdraws, PR.stride_q);
+                            alive[h] = false;
+                        } else {
+                            sample_tau<F32>(p[h], P.lcg);
+                        }
+                        pend[h] = false;
+                        pcoll[h] = false;
                     }
                 }
             }

@@ -81,11 +81,12 @@ def test_launch_shapes_bit_identical(M, ctx, orc):
         for hpl in (1, 2, 4):
             for unit in (300, 4096):
                 for copies in (1, 2):
-                    say("shape", block, hpl, unit, copies)
-                    raw, _, diag = run(M, ctx, [p], block=block, hist_per_lane=hpl, unit_histories=unit,
-                                       tally_copies=copies)
-                    assert raw == ref.raw, (block, hpl, unit, copies)
-                    assert diag[0] == ref.diag
+                    for cb in (1, 24, 64 * hpl):
+                        say("shape", block, hpl, unit, copies, cb)
+                        raw, _, diag = run(M, ctx, [p], block=block, hist_per_lane=hpl, unit_histories=unit,
+                                           tally_copies=copies, coll_batch=cb)
+                        assert raw == ref.raw, (block, hpl, unit, copies, cb)
+                        assert diag[0] == ref.diag
 
 
 @pytest.mark.parametrize("precision", [0, 1])
