@@ -279,44 +279,85 @@ def main():
 
 
 def batched_leg(M, W, torch, lcg, ctx):
+    """512 slabs.  Baseline: the plain FP64 per-problem form, one run (and
+    reduce) per problem.  Against it: every problem in one persistent launch
+    replayed from a captured hipGraph, launch options from the autotuner,
+    in FP64 (bit-identical to the baseline) and FP32-flight."""
+    import paper_2403_06362_amd as P
     probs = W.batched()
-    res = {"workload": "512 slabs (seed 7), log-uniform 1e3..1e7 histories, sum %d" %
-                       sum(p.n_histories for p in probs)}
-    # per-problem FP64 baseline: one run (launch) per problem
-    log("batched: one launch per problem (fp64)")
+    ntot = sum(p.n_histories for p in probs)
+    res = {"workload": "512 slabs (seed 7), log-uniform 1e3..1e7 histories, %d in total" % ntot}
+    nb = [P.tally_bins([p]) for p in probs]
+    raws = [torch.empty((b, 2), dtype=torch.uint64, device="cuda:0") for b in nb]
+    fls = [torch.empty(b, dtype=torch.float64, device="cuda:0") for b in nb]
+    log("batched: one run per problem (fp64)")
     ctx1 = M.Context(0)
+    ctx1.run_histories(lcg, [probs[0]], M.make_opts())
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for p in probs:
+    for p, r, f in zip(probs, raws, fls):
         ctx1.run_histories(lcg, [p], M.make_opts())
+        ctx1.reduce_tallies(r, f)
     torch.cuda.synchronize()
     per_problem_s = time.perf_counter() - t0
     ctx1.close()
-    res["per_problem_fp64_s"] = per_problem_s
+    ref_raw = torch.cat(raws).view(torch.int64).cpu().numpy()
+    ref_flux = torch.cat(fls).cpu().numpy()
+    res["per_problem_fp64"] = {"s": per_problem_s, "histories_per_s": ntot / per_problem_s}
+    tot = P.tally_bins(probs)
+    raw = torch.empty((tot, 2), dtype=torch.uint64, device="cuda:0")
+    flux = torch.empty(tot, dtype=torch.float64, device="cuda:0")
     for name, prec in (("fp64", 0), ("fp32", 1)):
         log("batched: autotune", name)
-        best, best_ms = ctx.autotune(lcg, probs, M.make_opts(precision=prec))
+        best, _ = ctx.autotune(lcg, probs, M.make_opts(precision=prec))
         best.use_graph = 1
         ctx.run_histories(lcg, probs, best)
+        ctx.reduce_tallies(raw, flux)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ctx.run_histories(lcg, probs, best)
-        torch.cuda.synchronize()
-        s = time.perf_counter() - t0
-        res["persistent_graph_" + name] = {"s": s, "kernel_ms": ctx.last_run_ms(), "opts": best.as_dict(),
-                                           "histories_per_s": sum(p.n_histories for p in probs) / s}
-    res["speedup_fp32_batched_over_fp64_per_problem"] = per_problem_s / res["persistent_graph_fp32"]["s"]
-    res["speedup_fp64_batched_over_fp64_per_problem"] = per_problem_s / res["persistent_graph_fp64"]["s"]
+        times = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            ctx.run_histories(lcg, probs, best)
+            ctx.reduce_tallies(raw, flux)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        sec = float(np.median(times))
+        leg = {"s": sec, "kernel_ms": ctx.last_run_ms(), "opts": best.as_dict(), "histories_per_s": ntot / sec,
+               "speedup_over_per_problem_fp64": per_problem_s / sec}
+        if prec == 0:
+            leg["bit_identical_to_per_problem"] = bool(np.array_equal(raw.view(torch.int64).cpu().numpy(), ref_raw))
+        else:
+            f = flux.cpu().numpy()
+            m = ref_flux > 0
+            rel = np.abs(f[m] - ref_flux[m]) / ref_flux[m]
+            l1, off = [], 0
+            for b in nb:
+                a, r = f[off:off + b], ref_flux[off:off + b]
+                l1.append(float(np.abs(a - r).sum() / r.sum()) if r.sum() > 0 else 0.0)
+                off += b
+            leg["flux_rel_err_vs_fp64"] = {
+                "per_bin_max": float(rel.max()), "per_bin_rms": float(np.sqrt(np.mean(rel ** 2))),
+                "bins_above_1e-6": float(np.mean(rel > 1e-6)),
+                "per_problem_l1_max": float(max(l1)), "per_problem_l1_median": float(np.median(l1))}
+        res["persistent_graph_" + name] = leg
     return res
 
 
 def multi_region_leg(M, W, torch, lcg, ctx):
     prob = W.multi_region()
     res = {"workload": "10-region slab (seed 11), 50x20 space-time bins, 2e8 histories, hash"}
-    for name, opts in (("history", M.make_opts()), ("history_fp32", M.make_opts(precision=1))):
+    for name, opts in (("history_fp64", M.make_opts()), ("history_fp32", M.make_opts(precision=1)),
+                       ("event_sorted_fp64", M.make_opts(schedule=1))):
         log("multi region", name)
         r = transport_leg(M, W, torch, lcg, ctx, prob, opts, reps=1)
         res[name] = {k: v for k, v in r.items() if k not in ("flux", "diag")}
+        res[name]["_flux"] = r["flux"]
+    res["event_sorted_equals_history"] = bool(np.array_equal(res["event_sorted_fp64"].pop("_flux"),
+                                                             res["history_fp64"]["_flux"]))
+    f32, f64 = res["history_fp32"].pop("_flux"), res["history_fp64"].pop("_flux")
+    m = f64 > 0
+    rel = np.abs(f32[m] - f64[m]) / f64[m]
+    res["fp32_vs_fp64_flux_rel_err"] = {"max": float(rel.max()), "rms": float(np.sqrt(np.mean(rel ** 2)))}
     return res
 
 

@@ -38,81 +38,81 @@ __device__ __forceinline__ uint64_t queue_seed(const DrawParams& P, uint64_t j) 
     return stream_start(P.lcg, P.seed, j);
 }
 
-// Persistent seed + draw kernel.  Each wave owns the streams [lo, hi) and
-// keeps a queue of the next 64 of them: lane l holds the start state of
-// stream qbase + l (seeded with all 64 lanes at once) in a register, and the
-// 64 draw counts sit in the wave's LDS row (loaded one queue ahead).  Each
-// lane carries one active stream; a round draws D steps (only the checksum is
-// masked by the remaining count); after a round, lanes whose stream ended
-// store its checksum and take the next queue entries in order through a
-// ballot, a prefix count, cross-lane reads of the seeds and LDS reads of the
-// counts.  The queue position and range are wave-uniform (scalar registers);
-// the refill path has no dependence on vector-memory loads, so it never waits
-// for the checksum stores in flight.
+// Persistent seed + draw kernel.  Each wave owns the streams [lo, hi)
+// (fewer than 2^32) and keeps the next 128 of them ready in two queues of 64:
+// lane l holds the start states of streams qbase + l (queue A) and
+// qbase + 64 + l (queue B), each queue seeded with all 64 lanes at once, and
+// the wave's 128-entry LDS ring holds their draw counts (loaded one queue
+// ahead).  Each lane carries one active stream; a round draws D steps (only
+// the checksum is masked by the remaining count); after a round, lanes whose
+// stream ended store its checksum and take the next queue entries in order
+// (ballot, prefix count, cross-lane reads of both queues, one LDS read).  Up
+// to 64 lanes are served per round without a loop, and the refill path never
+// waits on vector memory (one wait per 64 streams, when a queue is rebuilt).
 template <int MODE, int D, bool STORE_STATE, bool M63C1>
 __global__ void __launch_bounds__(256) k_draw(DrawParams P) {
-    __shared__ uint32_t s_count[4][64];
+    __shared__ uint32_t s_count[4][128];
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave in block
     const uint64_t wave = static_cast<uint64_t>(blockIdx.x) * (blockDim.x >> 6) + wib;
     const uint64_t nwaves = static_cast<uint64_t>(gridDim.x) * (blockDim.x >> 6);
     const uint64_t lo = wave * P.n / nwaves;
-    const uint64_t hi = (wave + 1) * P.n / nwaves;
+    const uint32_t nw = static_cast<uint32_t>((wave + 1) * P.n / nwaves - lo);   // streams of this wave
     const uint64_t g = P.lcg.g;
-    uint32_t* my_count = s_count[wib];
+    uint32_t* ring = s_count[wib];
 
-    // queue of the next 64 streams: qbase, qhead wave-uniform
-    uint64_t qbase = lo;
-    uint32_t qhead = 0;
-    uint64_t qx = 0;
+    // queue bookkeeping, wave-uniform: qbase = offset of queue A's first
+    // stream from lo; qhead = next entry (0..63 in A, 64..127 in B)
+    uint32_t qbase = 0, qhead = 0;
+    uint64_t qa = 0, qb = 0;
     uint32_t qc_next = 0;
     {
-        const uint64_t j = qbase + lane;
-        my_count[lane] = (j < hi) ? P.count[j] : 0u;
-        if (j < hi) qx = queue_seed<MODE>(P, j);
-        const uint64_t jn = j + 64;
-        if (jn < hi) qc_next = P.count[jn];
+        const uint32_t ja = lane, jb = 64u + lane, jn = 128u + lane;
+        ring[ja] = (ja < nw) ? P.count[lo + ja] : 0u;
+        ring[jb] = (jb < nw) ? P.count[lo + jb] : 0u;
+        if (ja < nw) qa = queue_seed<MODE>(P, lo + ja);
+        if (jb < nw) qb = queue_seed<MODE>(P, lo + jb);
+        if (jn < nw) qc_next = P.count[lo + jn];
     }
 
-    uint64_t x = 0, sum = 0, sid = 0;
-    uint32_t rem = 0;
+    uint64_t x = 0, sum = 0;
+    uint32_t sid = 0, rem = 0;
     bool active = false;
     for (;;) {
         if (active && rem == 0) {
-            P.checksum[sid] = sum;
-            if (STORE_STATE) P.state[sid] = x;
+            P.checksum[lo + sid] = sum;
+            if (STORE_STATE) P.state[lo + sid] = x;
             active = false;
         }
-        uint64_t need = __ballot(!active);
-        while (need != 0 && qbase + qhead < hi) {
-            const uint64_t left = hi - (qbase + qhead);
-            const uint32_t room = 64u - qhead;
-            const uint32_t avail = left < room ? static_cast<uint32_t>(left) : room;
+        const uint64_t need = __ballot(!active);
+        const uint32_t left = nw - (qbase + qhead);   // streams not yet handed out
+        if (need != 0 && left != 0) {
             const uint32_t nneed = static_cast<uint32_t>(__popcll(need));
-            const uint32_t take = __builtin_amdgcn_readfirstlane(nneed < avail ? nneed : avail);
+            const uint32_t take = __builtin_amdgcn_readfirstlane(nneed < left ? nneed : left);
             const uint32_t rank = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(need >> 32),
                                                             __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(need), 0u));
-            const uint32_t src = qhead + (rank < take ? rank : 0u);
-            const uint64_t vx = __shfl(qx, static_cast<int>(src));
-            const uint32_t vc = my_count[src];
+            const uint32_t src = qhead + rank;               // < 128 for rank < take
+            const uint64_t va = __shfl(qa, static_cast<int>(src & 63u));
+            const uint64_t vb = __shfl(qb, static_cast<int>(src & 63u));
             if (!active && rank < take) {
-                x = vx;
-                rem = vc;
+                x = (src < 64u) ? va : vb;
+                rem = ring[(qbase + src) & 127u];
                 sid = qbase + src;
                 sum = 0;
                 active = true;
             }
             qhead = __builtin_amdgcn_readfirstlane(qhead + take);
-            if (qhead == 64u) {
-                qbase += 64;
-                qhead = 0;
-                const uint64_t j = qbase + lane;
-                my_count[lane] = qc_next;   // the one wait on vector memory per 64 streams
-                if (j < hi) qx = queue_seed<MODE>(P, j);
-                const uint64_t jn = j + 64;
-                qc_next = (jn < hi) ? P.count[jn] : 0u;
+            if (qhead >= 64u) {
+                // queue A is used up: B becomes A, a new B is seeded
+                qbase += 64u;
+                qhead -= 64u;
+                qa = qb;
+                const uint32_t jb = qbase + 64u + lane;
+                ring[jb & 127u] = qc_next;   // the one wait on vector memory per 64 streams
+                if (jb < nw) qb = queue_seed<MODE>(P, lo + jb);
+                const uint32_t jn = jb + 64u;
+                qc_next = (jn < nw) ? P.count[lo + jn] : 0u;
             }
-            need = __ballot(!active);
         }
         if (__ballot(active) == 0) break;
         const uint32_t k = active ? (rem < static_cast<uint32_t>(D) ? rem : static_cast<uint32_t>(D)) : 0u;
