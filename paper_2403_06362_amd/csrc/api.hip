@@ -534,6 +534,8 @@ static int build_tables(mcrng_ctx* ctx, const LcgDev& L, const mcrng_problem* P,
     }
     ctx->h_pu_begin[n] = static_cast<uint32_t>(ctx->h_units.size());
     if (ctx->h_units.size() > 0xffffffffull) return fail(MCRNG_EINVAL, "too many work units");
+    if (ctx->h_groups.size() > 65535)
+        return fail(MCRNG_EINVAL, "more than 65535 (problem, batch) tally groups in one run");
     // schedule: largest units first (stable), so short units fill the tail
     ctx->h_order.resize(ctx->h_units.size());
     for (uint32_t i = 0; i < ctx->h_order.size(); ++i) ctx->h_order[i] = i;

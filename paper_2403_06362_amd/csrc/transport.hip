@@ -343,28 +343,47 @@ __device__ __forceinline__ double u128_to_double(uint64_t lo, uint64_t hi) {
     return __builtin_ldexp(static_cast<double>(static_cast<uint64_t>(mant)), sh);
 }
 
-// One thread per output bin; the groups' bins are laid out back to back.
+// Block = (group, tile of 32 bins); 8 unit lanes per bin.  A group's units
+// are consecutive with consecutive partial slots (2 x slice_bins words each),
+// so unit u's words for bin i sit at slot0 + (u - u0) 2 slice + 2 i.  Unit
+// lane l sums units u0 + l, u0 + l + 8, ...; the 8 partial sums are then
+// added in lane order (integers: any order gives the same bits).
+constexpr int kRedBins = 32, kRedLanes = 8;
+
 __global__ void __launch_bounds__(256) k_reduce_bins(ReduceParams P) {
-    const uint32_t g = blockIdx.y;
-    const ReduceGroup G = P.groups[g];
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < G.slice_bins; i += gridDim.x * blockDim.x) {
-        unsigned __int128 acc = 0;
-        for (uint32_t u = G.unit_begin; u < G.unit_end; ++u) {
-            const uint64_t* s = P.partial + P.units[u].slot + 2 * static_cast<uint64_t>(i);
-            acc += static_cast<unsigned __int128>(s[0]);
-            acc += static_cast<unsigned __int128>(s[1]) << 32;
+    typedef unsigned __int128 u128;
+    __shared__ uint64_t part[kRedLanes][kRedBins][2];
+    const ReduceGroup G = P.groups[blockIdx.y];
+    const uint32_t bl = threadIdx.x % kRedBins, ul = threadIdx.x / kRedBins;
+    const uint32_t i = blockIdx.x * kRedBins + bl;
+    u128 acc = 0;
+    if (i < G.slice_bins && G.unit_end > G.unit_begin) {
+        const uint64_t slot0 = P.units[G.unit_begin].slot;
+        const uint64_t stride = 2ull * G.slice_bins;
+        for (uint32_t u = ul; u < G.unit_end - G.unit_begin; u += kRedLanes) {
+            const uint64_t* s = P.partial + slot0 + u * stride + 2ull * i;
+            acc += static_cast<u128>(s[0]);
+            acc += static_cast<u128>(s[1]) << 32;
         }
-        const uint64_t lo = static_cast<uint64_t>(acc), hi = static_cast<uint64_t>(acc >> 64);
-        const uint64_t o = G.out_off + i;
-        P.raw[2 * o] = lo;
-        P.raw[2 * o + 1] = hi;
-        const uint32_t sb = i % G.n_space_bins;
-        const uint32_t tb = i / G.n_space_bins;
-        const double r = u128_to_double(lo, hi) * 0x1p-56;
-        double d = static_cast<double>(G.n_hist) * P.dx[G.dx_off + sb];
-        if (G.n_time_bins > 0) d = d * P.dt[G.dt_off + tb];
-        P.flux[o] = (d != 0.0) ? r / d : 0.0;
     }
+    part[ul][bl][0] = static_cast<uint64_t>(acc);
+    part[ul][bl][1] = static_cast<uint64_t>(acc >> 64);
+    __syncthreads();
+    if (ul != 0 || i >= G.slice_bins) return;
+    u128 tot = 0;
+#pragma unroll
+    for (int l = 0; l < kRedLanes; ++l)
+        tot += (static_cast<u128>(part[l][bl][1]) << 64) | part[l][bl][0];
+    const uint64_t lo = static_cast<uint64_t>(tot), hi = static_cast<uint64_t>(tot >> 64);
+    const uint64_t o = G.out_off + i;
+    P.raw[2 * o] = lo;
+    P.raw[2 * o + 1] = hi;
+    const uint32_t sb = i % G.n_space_bins;
+    const uint32_t tb = i / G.n_space_bins;
+    const double r = u128_to_double(lo, hi) * 0x1p-56;
+    double d = static_cast<double>(G.n_hist) * P.dx[G.dx_off + sb];
+    if (G.n_time_bins > 0) d = d * P.dt[G.dt_off + tb];
+    P.flux[o] = (d != 0.0) ? r / d : 0.0;
 }
 
 __global__ void __launch_bounds__(256) k_reduce_diag(ReduceParams P) {
@@ -399,9 +418,9 @@ __global__ void __launch_bounds__(256) k_reduce_diag(ReduceParams P) {
 
 hipError_t launch_reduce(const ReduceParams& p, hipStream_t st) {
     if (p.n_groups > 0) {
-        uint32_t bx = (p.max_slice + 255) / 256;
+        uint32_t bx = (p.max_slice + kRedBins - 1) / kRedBins;
         if (bx < 1) bx = 1;
-        hipLaunchKernelGGL(k_reduce_bins, dim3(bx, p.n_groups), dim3(256), 0, st, p);
+        hipLaunchKernelGGL(k_reduce_bins, dim3(bx, p.n_groups), dim3(kRedBins * kRedLanes), 0, st, p);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
