@@ -209,7 +209,8 @@ int mcrng_reduce_tallies(mcrng_ctx *ctx, uint64_t *d_raw, double *d_flux, uint64
  * once after a warm-up, timed with HIP events on `stream`; the call
  * synchronises the stream) and writes the fastest to *best.  `base` fixes
  * precision and schedule; the search covers block size, histories per
- * lane, work-unit size and tally copies.  The choice is cached in the
+ * lane, work-unit size, tally copies and (history schedule) the collision
+ * batch.  The choice is cached in the
  * context per problem-set shape.  *best_ms receives its time (may be NULL). */
 int mcrng_autotune(mcrng_ctx *ctx, const mcrng_lcg *lcg, const mcrng_problem *problems,
                    uint32_t n_problems, const mcrng_run_opts *base, mcrng_run_opts *best,

@@ -902,7 +902,8 @@ extern "C" int mcrng_autotune(mcrng_ctx* ctx, const mcrng_lcg* lcg, const mcrng_
     if ((rc = try_field(&mcrng_run_opts::block, {64, 128, 256, 512, 1024})) < 0) return rc;
     if ((rc = try_field(&mcrng_run_opts::hist_per_lane, {1, 2, 4})) < 0) return rc;
     if ((rc = try_field(&mcrng_run_opts::tally_copies, {1, 2})) < 0) return rc;
-    if ((rc = try_field(&mcrng_run_opts::coll_batch, {1, 16, 24, 32, 48})) < 0) return rc;
+    if (cur.schedule == MCRNG_SCHED_HISTORY)
+        if ((rc = try_field(&mcrng_run_opts::coll_batch, {1, 16, 24, 32, 48})) < 0) return rc;
     const uint32_t u0 = default_unit_histories(problems, n_problems);
     if ((rc = try_field(&mcrng_run_opts::unit_histories, {u0 / 4 > 256 ? u0 / 4 : 256, u0, u0 * 4})) < 0) return rc;
     if (cur.unit_histories == 0) cur.unit_histories = u0;
