@@ -68,6 +68,23 @@ class _Event(C.Structure):
                 ("pad_", C.c_int32), ("s", C.c_double)]
 
 
+class _Pulse(C.Structure):
+    _fields_ = [("sigma_t", C.c_double), ("scatter", C.c_double), ("nu", C.c_double),
+                ("x_lo", C.c_double), ("x_hi", C.c_double), ("n_time_bins", C.c_int32),
+                ("n_batches", C.c_uint32), ("t_edges", C.POINTER(C.c_double)),
+                ("per_batch", C.c_uint64), ("first_batch", C.c_uint64),
+                ("lcg", _Lcg), ("seeding", _Seeding)]
+
+
+class _PTrace(C.Structure):
+    _fields_ = [("start", C.c_uint64), ("end", C.c_uint64), ("x0", C.c_double), ("t0", C.c_double),
+                ("n_out", C.c_uint32), ("draws", C.c_uint32)]
+
+
+PULSE_DIAG_NAMES = ("sources", "collisions", "tallied", "scatters", "absorbed", "census",
+                    "secondaries", "draws", "max_draws", "over_stride")
+
+
 def lib():
     global _lib
     with _lock:
@@ -93,6 +110,13 @@ def lib():
                                                  C.c_void_p, C.c_void_p, C.c_void_p, u64, P(u64)]
             L.orc_transport_scripted.restype = C.c_int64
             L.orc_u128_to_f64.argtypes = [u64, u64]; L.orc_u128_to_f64.restype = dbl
+            L.orc_pulse_run.argtypes = [P(_Pulse), u64, u64, C.c_void_p, C.c_void_p]
+            L.orc_pulse_run.restype = C.c_int
+            L.orc_pulse_scripted.argtypes = [P(_Pulse), C.c_void_p, u64, C.c_void_p, C.c_void_p]
+            L.orc_pulse_scripted.restype = C.c_int64
+            L.orc_pulse_flux.argtypes = [P(_Pulse), C.c_void_p, C.c_void_p]
+            L.orc_pulse_trace.argtypes = [P(_Pulse), u64, u64, C.c_void_p, C.c_void_p, C.c_void_p, u64, P(u64)]
+            L.orc_pulse_trace.restype = C.c_int
             _lib = L
     return _lib
 
@@ -369,3 +393,92 @@ def flux(prob, tally: Tally, n_per_batch=None):
                     d = d * dt[t]
                 out[i] = r / d if d != 0.0 else 0.0
     return out
+
+
+# ---------------------------------------------------------------- pulse problem
+
+def _pulse_struct(prob, lcg):
+    k = _Keep()
+    k.te = np.ascontiguousarray(prob.time_edges, dtype=np.float64)
+    st = _Pulse()
+    st.sigma_t, st.scatter, st.nu = float(prob.sigma_t), float(prob.scatter), float(prob.nu)
+    st.x_lo, st.x_hi = float(prob.x_lo), float(prob.x_hi)
+    st.n_time_bins = len(k.te) - 1
+    st.n_batches = int(prob.n_batches)
+    st.t_edges = k.te.ctypes.data_as(C.POINTER(C.c_double))
+    st.per_batch = int(prob.per_batch)
+    st.first_batch = int(prob.first_batch)
+    st.lcg = _lcg_struct(lcg)
+    st.seeding = _seeding_struct(prob.seeding)
+    k.st = st
+    return k
+
+
+@dataclass
+class PulseTally:
+    counts: np.ndarray   # uint64, (n_batches, n_time_bins)
+    diag: dict
+
+
+def pulse(prob, lcg, b0=0, b1=None, threads=1) -> PulseTally:
+    """Collision counts per (batch, time bin) of batches b0 .. b1-1 (the rest
+    stay 0) and the diagnostics of those batches."""
+    b1 = prob.n_batches if b1 is None else b1
+    keep = _pulse_struct(prob, lcg)
+    nt = keep.st.n_time_bins
+
+    def part(lo, hi):
+        cnt = np.zeros(prob.n_batches * nt, np.uint64)
+        dg = np.zeros(NDIAG, np.uint64)
+        if lib().orc_pulse_run(C.byref(keep.st), lo, hi, cnt.ctypes.data, dg.ctypes.data) != 0:
+            raise ValueError("orc_pulse_run rejected the problem")
+        return cnt, dg
+
+    n = b1 - b0
+    threads = max(1, min(int(threads), max(n, 1)))
+    cuts = [b0 + n * i // threads for i in range(threads + 1)]
+    with ThreadPoolExecutor(threads) as ex:
+        parts = list(ex.map(lambda i: part(cuts[i], cuts[i + 1]), range(threads)))
+    cnt = np.zeros(prob.n_batches * nt, np.uint64)
+    dg = np.zeros(NDIAG, np.uint64)
+    for c, d in parts:
+        cnt += c
+        mx = max(dg[8], d[8])
+        dg += d
+        dg[8] = mx
+    return PulseTally(cnt.reshape(prob.n_batches, nt), dict(zip(PULSE_DIAG_NAMES, (int(v) for v in dg))))
+
+
+def pulse_scripted(prob, lcg, uniforms):
+    """One source family driven by the given uniforms (stride semantics).
+    Returns (counts per time bin, diag dict, uniforms used)."""
+    keep = _pulse_struct(prob, lcg)
+    u = np.ascontiguousarray(uniforms, dtype=np.float64)
+    cnt = np.zeros(keep.st.n_time_bins, np.uint64)
+    dg = np.zeros(NDIAG, np.uint64)
+    used = lib().orc_pulse_scripted(C.byref(keep.st), u.ctypes.data, u.size, cnt.ctypes.data, dg.ctypes.data)
+    return [int(v) for v in cnt], dict(zip(PULSE_DIAG_NAMES, (int(v) for v in dg))), int(used)
+
+
+def pulse_flux(prob, lcg, counts):
+    keep = _pulse_struct(prob, lcg)
+    c = np.ascontiguousarray(counts, dtype=np.uint64).reshape(-1)
+    out = np.zeros(c.size, np.float64)
+    lib().orc_pulse_flux(C.byref(keep.st), c.ctypes.data, out.ctypes.data)
+    return out.reshape(prob.n_batches, keep.st.n_time_bins)
+
+
+def pulse_trace(prob, lcg, b, i, cap=1 << 16):
+    """Source i of batch b alone: (counts per time bin, diag, list of
+    per-particle records (start, end, x0, t0, n_out, draws) in processing
+    order)."""
+    keep = _pulse_struct(prob, lcg)
+    cnt = np.zeros(keep.st.n_time_bins, np.uint64)
+    dg = np.zeros(NDIAG, np.uint64)
+    log = (_PTrace * cap)()
+    n = C.c_uint64()
+    if lib().orc_pulse_trace(C.byref(keep.st), b, i, cnt.ctypes.data, dg.ctypes.data, log, cap, C.byref(n)) != 0:
+        raise ValueError("orc_pulse_trace rejected the problem")
+    recs = [(int(log[k].start), int(log[k].end), float(log[k].x0), float(log[k].t0), int(log[k].n_out),
+             int(log[k].draws)) for k in range(min(n.value, cap))]
+    return [int(v) for v in cnt], dict(zip(PULSE_DIAG_NAMES, (int(v) for v in dg))), recs

@@ -19,6 +19,8 @@
  *   hash(k, s) .......... Sec. "Parallel LCG with Seed Hashing", Listing 1
  *   seed splitting ...... Sec. "Seed Splitting", eq. (3): S_k = hash(k, s)
  *   hierarchical seeds .. Sec. "Hierarchical Seed Splitting", eq. (4)
+ *   secondary seeds ..... Sec. "On-Demand Seed Splitting", eq. (5)
+ *   pulse problem ....... Sec. "Implementation and Results" (the test problem)
  * The transport loop, the uniform mapping, the logarithm and the fixed-point
  * tally are readings of points the paper leaves open; each is stated where
  * it is implemented.
@@ -615,6 +617,309 @@ int64_t orc_transport_scripted(const orc_problem *P, int float_mode,
     if (log_n) *log_n = lg.n;
     if (R.exhausted) return -1;
     return (int64_t)R.pos;
+}
+
+/* ------------------------------------------------------------------ */
+/* Supercritical pulse in an infinite homogeneous medium: the paper's test
+ * problem (Sec. "Implementation and Results"): a pulse of particles at
+ * x = 0, t = 0 in an infinite medium with total cross section sigma_t,
+ * isotropic scattering ratio c = Sigma_s / Sigma_t and scattering
+ * multiplicity nu (c nu is the multiplication factor), run to a census
+ * time; the flux averaged over a central interval [x_lo, x_hi] is tallied
+ * with the collision estimator in time bins.
+ *
+ * Secondary particles (Sec. "On-Demand Seed Splitting", eq. 5):
+ *   hash seeding:   the k-th particle emerging from a scattering (k = 1..n)
+ *                   starts its own stream at hash(k, X_p) mod 2^m, where X_p
+ *                   is the parent's state after the scattering's draws;
+ *   stride seeding: only source particles receive streams (X_{Q i}); the
+ *                   particles a source gives rise to draw from the source's
+ *                   stream one after another, depth first: the first
+ *                   emerging particle continues at once, its siblings wait
+ *                   on a last-in-first-out stack (siblings are identical
+ *                   until they draw, so their order among themselves does
+ *                   not matter).
+ * Source i (0-based) of batch b has the global batch id B = first_batch + b:
+ *   hash:   S = hash(i + 1, hash(B + 1, base))   (eq. 4, batch id first)
+ *   stride: S = X_{Q (B per_batch + i)}           (X_0 = base)
+ *
+ * Readings (the paper gives the problem, not these details):
+ *   start:     a particle's first draw u gives its direction mu = 2u - 1
+ *              (isotropic); sources start at x = 0, t = 0, secondaries at
+ *              their parent's collision site and time;
+ *   flight:    draw u, tau = -ln(u) (orc_ln), s = tau / sigma_t; with
+ *              tn = t + s: if tn < T_end the particle moves to x + mu s
+ *              (x = x + (mu * s)) and t = tn and collides there, else it
+ *              reaches the census and ends (no score);
+ *   score:     a collision with x_lo <= x <= x_hi and t >= T[0] adds 1 to
+ *              its batch and time bin b with T[b] <= t < T[b+1];
+ *   collision: draw u1; absorbed unless u1 < c; else draw u2 and
+ *              n = floor(nu) + (u2 < nu - floor(nu)) particles emerge (the
+ *              parent ends; n may be 0);
+ *   flux:      count / (((sigma_t N_b) (x_hi - x_lo)) (T[b+1] - T[b])),
+ *              N_b = per_batch, one IEEE operation per step.
+ * T_end is the last time edge.  Every floating-point step is one IEEE
+ * double operation, rounded to nearest, without contraction.
+ */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    double sigma_t, scatter, nu;
+    double x_lo, x_hi;
+    int32_t n_time_bins;        /* >= 1 */
+    uint32_t n_batches;         /* >= 1 */
+    const double *t_edges;      /* n_time_bins + 1 */
+    uint64_t per_batch;         /* sources per batch */
+    uint64_t first_batch;       /* global id of batch 0 */
+    orc_lcg lcg;
+    orc_seeding seeding;        /* kind, base, stride used */
+} orc_pulse;
+
+enum {
+    ORC_P_SOURCES = 0, ORC_P_COLLISIONS, ORC_P_TALLIED, ORC_P_SCATTERS,
+    ORC_P_ABSORBED, ORC_P_CENSUS, ORC_P_SECONDARIES, ORC_P_DRAWS,
+    ORC_P_MAX_DRAWS, ORC_P_OVER_STRIDE, ORC_P_NDIAG
+};
+
+/* a particle waiting to start: position, time, time bin, and (hash
+ * seeding) its stream's start state; `count` identical stride siblings */
+typedef struct {
+    double x, t;
+    int32_t tb;
+    uint32_t count;
+    uint64_t seed;
+} orc_pending;
+
+typedef struct {
+    orc_pending *a;
+    size_t n, cap;
+} orc_stack;
+
+static int stack_push(orc_stack *S, orc_pending e)
+{
+    if (S->n == S->cap) {
+        size_t nc = S->cap ? 2 * S->cap : 64;
+        orc_pending *na = (orc_pending *)realloc(S->a, nc * sizeof *na);
+        if (!na) return -1;
+        S->a = na;
+        S->cap = nc;
+    }
+    S->a[S->n++] = e;
+    return 0;
+}
+
+/* time bin of t: the largest b < n_time_bins with T[b] <= t, starting the
+ * search from the bin of an earlier time; -1 before T[0] */
+static int32_t advance_tbin(const orc_pulse *P, int32_t tb, double t)
+{
+    while (tb + 1 < P->n_time_bins && P->t_edges[tb + 1] <= t) ++tb;
+    return tb;
+}
+
+/* Runs one particle from its start to its end with random numbers from R.
+ * Adds its scores to cnt (the batch's n_time_bins counters) and its counts
+ * to d.  On a scattering, *n_out receives the number of emerging particles,
+ * and *xo, *to, *tbo their start; otherwise *n_out = 0. */
+static void pulse_particle(const orc_pulse *P, orc_rng *R, double x, double t, int32_t tb,
+                           uint64_t *cnt, uint64_t *d, uint32_t *n_out,
+                           double *xo, double *to, int32_t *tbo)
+{
+    const double t_end = P->t_edges[P->n_time_bins];
+    const double nu_floor = floor(P->nu);
+    const double nu_frac = P->nu - nu_floor;
+    *n_out = 0;
+    double mu = 2.0 * rng_draw(R) - 1.0;
+    double tau = -orc_ln(rng_draw(R));
+    double s = tau / P->sigma_t;
+    double tn = t + s;
+    if (!(tn < t_end)) { d[ORC_P_CENSUS]++; return; }
+    double step = mu * s;
+    x = x + step;
+    t = tn;
+    tb = advance_tbin(P, tb, t);
+    d[ORC_P_COLLISIONS]++;
+    if (tb >= 0 && P->x_lo <= x && x <= P->x_hi) {
+        cnt[tb]++;
+        d[ORC_P_TALLIED]++;
+    }
+    double u1 = rng_draw(R);
+    if (!(u1 < P->scatter)) { d[ORC_P_ABSORBED]++; return; }
+    double u2 = rng_draw(R);
+    uint32_t n = (uint32_t)nu_floor + (u2 < nu_frac ? 1u : 0u);
+    d[ORC_P_SCATTERS]++;
+    d[ORC_P_SECONDARIES] += n;
+    *n_out = n;
+    *xo = x;
+    *to = t;
+    *tbo = tb;
+}
+
+static void note_stream(const orc_pulse *P, uint64_t *d, uint64_t draws)
+{
+    d[ORC_P_DRAWS] += draws;
+    if (draws > d[ORC_P_MAX_DRAWS]) d[ORC_P_MAX_DRAWS] = draws;
+    if (P->seeding.kind == ORC_SEED_STRIDE && draws > P->seeding.stride) d[ORC_P_OVER_STRIDE]++;
+}
+
+/* per-particle record of a traced family (tests) */
+typedef struct {
+    uint64_t start, end;     /* stream state when the particle starts / ends */
+    double x0, t0;           /* start position and time */
+    uint32_t n_out;          /* particles emerging from its end (0 unless it scattered) */
+    uint32_t draws;          /* numbers drawn by the particle */
+} orc_ptrace;
+
+typedef struct {
+    orc_ptrace *a;
+    uint64_t cap, n;
+} orc_plog;
+
+/* One source and everything it gives rise to.  Stride seeding: one stream
+ * for the whole family (R), depth first.  Hash seeding: each particle its
+ * own stream; the family is walked depth first too, which for hash seeding
+ * is only one of many orders that give the same counts. */
+static int pulse_family(const orc_pulse *P, orc_rng *R, uint64_t *cnt, uint64_t *d, orc_stack *S,
+                        orc_plog *lg)
+{
+    const int hash = P->seeding.kind == ORC_SEED_HASH;
+    const uint64_t msk = mask_of(P->lcg.m);
+    double x = 0.0, t = 0.0;
+    int32_t tb = advance_tbin(P, -1, 0.0);
+    S->n = 0;
+    d[ORC_P_SOURCES]++;
+    for (;;) {
+        uint32_t n = 0;
+        double xo = 0, to = 0;
+        int32_t tbo = -1;
+        const uint64_t start = R->x, draws0 = R->draws;
+        pulse_particle(P, R, x, t, tb, cnt, d, &n, &xo, &to, &tbo);
+        if (lg && lg->a) {
+            if (lg->n < lg->cap) {
+                orc_ptrace *e = &lg->a[lg->n];
+                e->start = start; e->end = R->x; e->x0 = x; e->t0 = t;
+                e->n_out = n; e->draws = (uint32_t)(R->draws - draws0);
+            }
+            lg->n++;
+        }
+        if (hash) {
+            /* this particle's stream ends here */
+            note_stream(P, d, R->draws);
+            for (uint32_t k = n; k >= 1; --k) {   /* k = 1 ends on top */
+                orc_pending e = { xo, to, tbo, 1, orc_hash(k, R->x) & msk };
+                if (stack_push(S, e)) return -1;
+            }
+        } else if (n > 0) {
+            orc_pending e = { xo, to, tbo, n, 0 };
+            if (stack_push(S, e)) return -1;
+        }
+        if (S->n == 0) break;
+        orc_pending *top = &S->a[S->n - 1];
+        x = top->x;
+        t = top->t;
+        tb = top->tb;
+        if (hash) {
+            R->x = top->seed;
+            R->draws = 0;
+            S->n--;
+        } else if (--top->count == 0) {
+            S->n--;
+        }
+    }
+    if (!hash) note_stream(P, d, R->draws);
+    return 0;
+}
+
+static int pulse_check(const orc_pulse *P)
+{
+    if (!P || P->n_time_bins < 1 || !P->t_edges || P->n_batches < 1) return -1;
+    if (P->lcg.m < 53 || P->lcg.m > 64) return -1;
+    if (!(P->sigma_t > 0) || !(P->scatter >= 0 && P->scatter <= 1) || !(P->nu >= 0 && P->nu <= 64)) return -1;
+    return 0;
+}
+
+/* Runs batches b0 .. b1-1 (every source of each) and ADDS their scores into
+ * counts (n_batches x n_time_bins) and their counts into diag
+ * (ORC_P_NDIAG words; ORC_P_MAX_DRAWS is a maximum).  Returns 0 or -1. */
+int orc_pulse_run(const orc_pulse *P, uint64_t b0, uint64_t b1, uint64_t *counts, uint64_t *diag)
+{
+    if (pulse_check(P) || !counts || !diag || b1 > P->n_batches) return -1;
+    orc_stack S = { NULL, 0, 0 };
+    int rc = 0;
+    for (uint64_t b = b0; b < b1 && rc == 0; ++b) {
+        const uint64_t B = P->first_batch + b;
+        const uint64_t parent = orc_hash(B + 1, P->seeding.base);
+        for (uint64_t i = 0; i < P->per_batch && rc == 0; ++i) {
+            orc_rng R;
+            memset(&R, 0, sizeof R);
+            R.lcg = &P->lcg;
+            if (P->seeding.kind == ORC_SEED_HASH)
+                R.x = orc_hash(i + 1, parent) & mask_of(P->lcg.m);
+            else
+                R.x = orc_skip(P->seeding.base & mask_of(P->lcg.m), P->seeding.stride * (B * P->per_batch + i),
+                               P->lcg.g, P->lcg.c, P->lcg.m);
+            rc = pulse_family(P, &R, counts + b * (uint64_t)P->n_time_bins, diag, &S, NULL);
+        }
+    }
+    free(S.a);
+    return rc;
+}
+
+/* One source family driven by a given list of uniforms (stride-seeding
+ * semantics: the whole family draws from the list in order).  Scores go to
+ * counts (n_time_bins, overwritten).  Returns the number of uniforms used,
+ * or -1 if the list ran out or an argument is bad. */
+int64_t orc_pulse_scripted(const orc_pulse *P, const double *u, uint64_t n_u, uint64_t *counts,
+                           uint64_t *diag)
+{
+    if (pulse_check(P) || !u || !counts || !diag || P->seeding.kind != ORC_SEED_STRIDE) return -1;
+    memset(counts, 0, (size_t)P->n_time_bins * sizeof *counts);
+    orc_stack S = { NULL, 0, 0 };
+    orc_rng R;
+    memset(&R, 0, sizeof R);
+    R.lcg = &P->lcg;
+    R.script = u;
+    R.n_script = n_u;
+    int rc = pulse_family(P, &R, counts, diag, &S, NULL);
+    free(S.a);
+    if (rc || R.exhausted) return -1;
+    return (int64_t)R.pos;
+}
+
+/* Source i of batch b alone, with every particle of its family recorded in
+ * processing order (up to cap records; *n receives the full number).
+ * Scores go to counts (n_time_bins, overwritten).  Returns 0 or -1. */
+int orc_pulse_trace(const orc_pulse *P, uint64_t b, uint64_t i, uint64_t *counts, uint64_t *diag,
+                    orc_ptrace *log, uint64_t cap, uint64_t *n)
+{
+    if (pulse_check(P) || !counts || !diag || b >= P->n_batches) return -1;
+    memset(counts, 0, (size_t)P->n_time_bins * sizeof *counts);
+    const uint64_t B = P->first_batch + b;
+    orc_rng R;
+    memset(&R, 0, sizeof R);
+    R.lcg = &P->lcg;
+    if (P->seeding.kind == ORC_SEED_HASH)
+        R.x = orc_hash(i + 1, orc_hash(B + 1, P->seeding.base)) & mask_of(P->lcg.m);
+    else
+        R.x = orc_skip(P->seeding.base & mask_of(P->lcg.m), P->seeding.stride * (B * P->per_batch + i),
+                       P->lcg.g, P->lcg.c, P->lcg.m);
+    orc_stack S = { NULL, 0, 0 };
+    orc_plog lg = { log, cap, 0 };
+    int rc = pulse_family(P, &R, counts, diag, &S, &lg);
+    free(S.a);
+    if (n) *n = lg.n;
+    return rc;
+}
+
+/* Flux of each (batch, time bin) from the integer counts. */
+void orc_pulse_flux(const orc_pulse *P, const uint64_t *counts, double *flux)
+{
+    const double dx = P->x_hi - P->x_lo;
+    for (uint32_t b = 0; b < P->n_batches; ++b)
+        for (int32_t k = 0; k < P->n_time_bins; ++k) {
+            const double dt = P->t_edges[k + 1] - P->t_edges[k];
+            const double den = ((P->sigma_t * (double)P->per_batch) * dx) * dt;
+            flux[(size_t)b * P->n_time_bins + k] = (double)counts[(size_t)b * P->n_time_bins + k] / den;
+        }
 }
 
 /* 128-bit unsigned integer to double, rounded to nearest, ties to even:

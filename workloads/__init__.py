@@ -155,10 +155,49 @@ def multi_region(seeding=None, n_histories=200_000_000, seed=11, n_regions=10,
     return SlabProblem(re, sig, c, be, int(n_histories), seeding or hash_seeding(), 1, te)
 
 
+@dataclass
+class PulseProblem:
+    """Supercritical pulse at x = t = 0 in an infinite homogeneous medium
+    (the paper's test problem: scattering ratio 0.4, multiplicity 2.75, run
+    to t = 20, collision-estimator flux over x in [-1, 1] in unit time
+    bins).  Batch b (0-based) holds `per_batch` sources; its global id is
+    first_batch + b.  The seeding's kind, base and stride are used."""
+    sigma_t: float = 1.0
+    scatter: float = 0.4
+    nu: float = 2.75
+    x_lo: float = -1.0
+    x_hi: float = 1.0
+    time_edges: np.ndarray = field(default_factory=lambda: np.arange(21, dtype=np.float64))
+    n_batches: int = 1000
+    per_batch: int = 1000
+    first_batch: int = 0
+    seeding: Seeding = field(default_factory=lambda: hash_seeding())
+
+    @property
+    def n_time_bins(self) -> int:
+        return len(self.time_edges) - 1
+
+    @property
+    def n_sources(self) -> int:
+        return self.n_batches * self.per_batch
+
+    def with_(self, **kw) -> "PulseProblem":
+        return replace(self, **kw)
+
+
+def pulse(seeding=None, n_batches=1000, per_batch=1000, first_batch=0):
+    """The paper's pulse problem: 1000 batches of 1000 sources by default;
+    a study of R repetitions is R x 1000 batches (repetition r holds the
+    batches r*1000 .. r*1000+999)."""
+    return PulseProblem(n_batches=n_batches, per_batch=per_batch, first_batch=first_batch,
+                        seeding=seeding or hash_seeding())
+
+
 CONFIG_NAMES = {
     "small_slab": "20 mfp slab, c=0.9, 20 bins, 1e4 histories, FP64",
     "draw_counts": "2^26 streams, geometric draw counts (mean 64, seed 42)",
     "long_chain": "50 mfp slab, c=0.99, 200 bins, 1e8 histories, 64 batches",
     "batched": "512 slabs (seed 7), log-uniform 1e3..1e7 histories",
     "multi_region": "10-region slab (seed 11), 50x20 space-time bins, 2e8 histories",
+    "pulse": "pulse in an infinite medium, c=0.4, nu=2.75, t<20, 1000 batches x 1000 sources",
 }
