@@ -221,6 +221,97 @@ int mcrng_autotune(mcrng_ctx *ctx, const mcrng_lcg *lcg, const mcrng_problem *pr
  * run; negative if unavailable. */
 float mcrng_last_run_ms(mcrng_ctx *ctx);
 
+/* ------------------------------------------------------------------ */
+/* Pulse in an infinite multiplying medium, with secondary particles   */
+/* ------------------------------------------------------------------ */
+
+/* The paper's test problem (Sec. "Implementation and Results"): a pulse of
+ * source particles at x = 0, t = 0 in an infinite homogeneous medium with
+ * total cross section sigma_t, isotropic scattering ratio
+ * scatter = Sigma_s / Sigma_t and scattering multiplicity nu, run to the
+ * census time (the last time edge), with the collision estimator of the
+ * flux averaged over [x_lo, x_hi] in time bins.  Particle speed 1.
+ * One particle: its first draw u gives mu = 2u - 1; its flight is
+ * s = -ln(u) / sigma_t; if t + s is not below the census time it ends at
+ * census, else it moves to (x + mu s, t + s) and collides there; a
+ * collision with x_lo <= x <= x_hi and t >= time_edges[0] adds 1 to its
+ * (batch, time bin); the next draw decides absorption (absorbed unless
+ * u < scatter); on a scattering the next draw gives the number of emerging
+ * particles n = floor(nu) + (u < nu - floor(nu)), which start at the
+ * collision site, and the parent ends.
+ * Seeds (Secs. "Hierarchical Seed Splitting" and "On-Demand Seed
+ * Splitting", eqs. 4 and 5).  Source i (0-based) of batch b has the global
+ * batch id B = first_batch + b:
+ *   MCRNG_SEED_HASH:   the source starts at hash(i + 1, hash(B + 1, base));
+ *                      the k-th particle emerging from a scattering
+ *                      (k = 1..n) starts its own stream at hash(k, X_p),
+ *                      X_p the parent's state after its draws (all states
+ *                      reduced modulo 2^m);
+ *   MCRNG_SEED_STRIDE: the source starts at X_{Q (B per_batch + i)}; the
+ *                      particles it gives rise to draw from its stream,
+ *                      depth first (the first emerging particle at once,
+ *                      its siblings afterwards in order).
+ * Host array: time_edges, n_time_bins + 1 values, finite, >= 0, strictly
+ * increasing. */
+typedef struct {
+    double sigma_t;              /* > 0 */
+    double scatter;              /* in [0, 1] */
+    double multiplicity;         /* nu in [0, 14] */
+    double x_lo, x_hi;           /* finite, x_lo < x_hi */
+    uint32_t n_time_bins;        /* 1 .. 4096 */
+    uint32_t n_batches;          /* >= 1 */
+    const double *time_edges;
+    uint64_t per_batch;          /* sources per batch, >= 1; n_batches x per_batch < 2^40 */
+    uint64_t first_batch;        /* global id of batch 0 (shards, repetitions) */
+    mcrng_seeding seeding;       /* kind, base, stride; hier, first_index, group_key must be 0 */
+} mcrng_pulse_problem;
+
+enum { MCRNG_PULSE_AUTO = 0, MCRNG_PULSE_BANK = 1, MCRNG_PULSE_FAMILY = 2 };
+
+/* Options (zero = default).  No option changes a result bit: counts are
+ * integers.
+ *   schedule     MCRNG_PULSE_BANK (hash seeding only): particles run one
+ *                flight per launch from a particle bank, in any order, the
+ *                emerging particles going to the next generation's bank;
+ *                MCRNG_PULSE_FAMILY: one source family per lane, depth
+ *                first; AUTO: bank for hash seeding, family for stride
+ *   block        threads per block: 64, 128, 256, 512 or 1024
+ *   stack_depth  family schedule: stack entries per lane (default 128; an
+ *                entry holds the siblings of one scattering on the current
+ *                line of descent) */
+typedef struct {
+    uint32_t schedule;
+    uint32_t block;
+    uint32_t stack_depth;
+    uint32_t reserved[5];        /* must be 0 */
+} mcrng_pulse_opts;
+
+/* Diagnostics of a pulse run, MCRNG_NDIAG uint64 words in this order; sums
+ * except MCRNG_PD_MAX_DRAWS (the most numbers one stream drew: a particle's
+ * under hash seeding, a family's under stride seeding).  OVER_STRIDE counts
+ * stride families that drew more than Q numbers. */
+enum {
+    MCRNG_PD_SOURCES = 0, MCRNG_PD_COLLISIONS, MCRNG_PD_TALLIED, MCRNG_PD_SCATTERS,
+    MCRNG_PD_ABSORBED, MCRNG_PD_CENSUS, MCRNG_PD_SECONDARIES, MCRNG_PD_DRAWS,
+    MCRNG_PD_MAX_DRAWS, MCRNG_PD_OVER_STRIDE
+};
+
+/* Runs every source of every batch and everything they give rise to.
+ *   d_counts  n_batches x n_time_bins uint64 (required): collisions scored
+ *             per (batch, time bin)
+ *   d_flux    same shape, double (may be NULL):
+ *             count / (((sigma_t per_batch) (x_hi - x_lo)) dt)
+ *   d_diag    MCRNG_NDIAG uint64 (may be NULL)
+ * Unlike the other calls this one returns after the run has finished on
+ * `stream` (the bank schedule reads each generation's size).  Errors:
+ * MCRNG_EINVAL (arguments), MCRNG_ERANGE (a family outgrew
+ * opts.stack_depth; the outputs are then incomplete), MCRNG_ENOMEM.
+ * Returns MCRNG_WSTRIDE_WRAP when the stride allocation passes 2^m states.
+ * The run's time (first to last launch of the run) is mcrng_last_run_ms. */
+int mcrng_run_pulse(mcrng_ctx *ctx, const mcrng_lcg *lcg, const mcrng_pulse_problem *problem,
+                    const mcrng_pulse_opts *opts, uint64_t *d_counts, double *d_flux,
+                    uint64_t *d_diag, void *stream);
+
 /* Thread-local text of the last failure (never NULL). */
 const char *mcrng_last_error(void);
 

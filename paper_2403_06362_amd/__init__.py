@@ -5,17 +5,20 @@ Paper: Cuneo & Variansyah, "An Alternative to Stride-Based RNG for Monte
 Carlo Transport" (arXiv 2403.06362).
 
 The entry points mirror the C ABI: init_streams, draw, Context.run_histories,
-Context.reduce_tallies (plus Context.autotune).  Tensors are torch device
-tensors; the library does all the arithmetic.  `transport()` is a
-convenience wrapper that allocates the output tensors.
+Context.reduce_tallies, Context.run_pulse (plus Context.autotune).  Tensors
+are torch device tensors; the library does all the arithmetic.
+`transport()` and `pulse()` are convenience wrappers that allocate the
+output tensors.
 """
 from ._binding import (  # noqa: F401
-    DIAG_NAMES, EXPORTS, FP32, FP64, NDIAG, SCHED_EVENT, SCHED_HISTORY, Context, McrngError, RunOpts,
-    draw, init_streams, lib, make_opts, tally_bins,
+    DIAG_NAMES, EXPORTS, FP32, FP64, NDIAG, PULSE_AUTO, PULSE_BANK, PULSE_DIAG_NAMES, PULSE_FAMILY, SCHED_EVENT,
+    SCHED_HISTORY, Context, McrngError, PulseOpts, RunOpts, draw, init_streams, lib, make_opts, make_pulse_opts,
+    tally_bins,
 )
 
-__all__ = ["init_streams", "draw", "Context", "RunOpts", "make_opts", "tally_bins", "transport",
-           "McrngError", "lib", "FP64", "FP32", "SCHED_HISTORY", "SCHED_EVENT", "NDIAG", "DIAG_NAMES"]
+__all__ = ["init_streams", "draw", "Context", "RunOpts", "make_opts", "tally_bins", "transport", "pulse",
+           "PulseOpts", "make_pulse_opts", "McrngError", "lib", "FP64", "FP32", "SCHED_HISTORY", "SCHED_EVENT",
+           "PULSE_AUTO", "PULSE_BANK", "PULSE_FAMILY", "NDIAG", "DIAG_NAMES", "PULSE_DIAG_NAMES"]
 
 
 def transport(problems, lcg, ctx=None, opts=None, stream=None, device="cuda:0"):
@@ -34,6 +37,26 @@ def transport(problems, lcg, ctx=None, opts=None, stream=None, device="cuda:0"):
         ctx.run_histories(lcg, problems, opts, stream)
         ctx.reduce_tallies(raw, flux, diag, stream)
         return raw[:nb], flux[:nb], diag
+    finally:
+        if own:
+            torch.cuda.synchronize()
+            ctx.close()
+
+
+def pulse(problem, lcg, ctx=None, opts=None, stream=None, device="cuda:0"):
+    """Runs a pulse problem.  Returns (counts, flux, diag): counts a uint64
+    tensor [n_batches, n_time_bins], flux float64 of the same shape, diag a
+    uint64 tensor [NDIAG]."""
+    import torch
+    own = ctx is None
+    ctx = ctx or Context(torch.device(device).index or 0)
+    try:
+        nt = len(problem.time_edges) - 1
+        counts = torch.empty((problem.n_batches, nt), dtype=torch.uint64, device=device)
+        flux = torch.empty((problem.n_batches, nt), dtype=torch.float64, device=device)
+        diag = torch.empty(NDIAG, dtype=torch.uint64, device=device)
+        ctx.run_pulse(lcg, problem, counts, flux, diag, opts, stream)
+        return counts, flux, diag
     finally:
         if own:
             torch.cuda.synchronize()

@@ -20,14 +20,17 @@ EINVAL, ENOMEM, EDEVICE, ERANGE, ESTATE = -1, -2, -3, -4, -5
 SEED_STRIDE, SEED_HASH = 0, 1
 FP64, FP32 = 0, 1
 SCHED_HISTORY, SCHED_EVENT = 0, 1
+PULSE_AUTO, PULSE_BANK, PULSE_FAMILY = 0, 1, 2
 NDIAG = 10
 DIAG_NAMES = ("histories", "leak_left", "leak_right", "absorbed", "census",
               "events", "collisions", "draws", "max_draws", "over_stride")
+PULSE_DIAG_NAMES = ("sources", "collisions", "tallied", "scatters", "absorbed", "census",
+                    "secondaries", "draws", "max_draws", "over_stride")
 
 # every symbol include/mcrng.h declares
 EXPORTS = ("mcrng_init_streams", "mcrng_draw", "mcrng_ctx_create", "mcrng_ctx_destroy",
            "mcrng_tally_bins", "mcrng_run_histories", "mcrng_reduce_tallies", "mcrng_autotune",
-           "mcrng_last_run_ms", "mcrng_last_error", "mcrng_version")
+           "mcrng_last_run_ms", "mcrng_last_error", "mcrng_version", "mcrng_run_pulse")
 
 
 class McrngError(RuntimeError):
@@ -63,6 +66,18 @@ class RunOpts(C.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}
 
 
+class PulseProblem(C.Structure):
+    _fields_ = [("sigma_t", C.c_double), ("scatter", C.c_double), ("multiplicity", C.c_double),
+                ("x_lo", C.c_double), ("x_hi", C.c_double), ("n_time_bins", C.c_uint32),
+                ("n_batches", C.c_uint32), ("time_edges", C.POINTER(C.c_double)),
+                ("per_batch", C.c_uint64), ("first_batch", C.c_uint64), ("seeding", Seeding)]
+
+
+class PulseOpts(C.Structure):
+    _fields_ = [("schedule", C.c_uint32), ("block", C.c_uint32), ("stack_depth", C.c_uint32),
+                ("reserved", C.c_uint32 * 5)]
+
+
 _lib = None
 
 
@@ -90,6 +105,7 @@ def lib():
         L.mcrng_last_error.argtypes = []
         L.mcrng_last_error.restype = C.c_char_p
         L.mcrng_version.argtypes = []
+        L.mcrng_run_pulse.argtypes = [vp, P(Lcg), P(PulseProblem), P(PulseOpts), vp, vp, vp, vp]
         for name in EXPORTS:
             if name not in ("mcrng_tally_bins", "mcrng_last_run_ms", "mcrng_last_error"):
                 getattr(L, name).restype = C.c_int
@@ -197,6 +213,27 @@ def draw(lcg, seeding, d_count, d_checksum, d_state=None, stream=None):
                                    _ptr(d_checksum, torch.uint64, n, "d_checksum"), _stream(stream)))
 
 
+def make_pulse_problem(pr):
+    """ctypes struct of a workloads.PulseProblem-like object (and the host
+    array it points into, to keep alive)."""
+    import numpy as np
+    te = np.ascontiguousarray(pr.time_edges, dtype=np.float64)
+    sd = make_seeding(pr.seeding)
+    sd.hier, sd.first_index, sd.group_key = 0, 0, 0
+    st = PulseProblem(float(pr.sigma_t), float(pr.scatter), float(pr.nu), float(pr.x_lo), float(pr.x_hi),
+                      len(te) - 1, int(pr.n_batches), te.ctypes.data_as(C.POINTER(C.c_double)),
+                      int(pr.per_batch), int(pr.first_batch), sd)
+    return st, te
+
+
+def make_pulse_opts(**kw):
+    o = PulseOpts()
+    for k, v in kw.items():
+        if v is not None:
+            setattr(o, k, int(v))
+    return o
+
+
 def tally_bins(problems):
     arr, _keep = make_problems(problems)
     return int(lib().mcrng_tally_bins(arr, len(problems)))
@@ -242,6 +279,18 @@ class Context:
         _check(lib().mcrng_autotune(self._h, C.byref(L), arr, len(problems), C.byref(b), C.byref(best),
                                     C.byref(ms), _stream(stream)))
         return best, float(ms.value)
+
+    def run_pulse(self, lcg, problem, d_counts, d_flux=None, d_diag=None, opts=None, stream=None):
+        """mcrng_run_pulse (returns after the run has finished)."""
+        import torch
+        st, _te = make_pulse_problem(problem)
+        L = make_lcg(lcg)
+        o = opts if opts is not None else PulseOpts()
+        n = int(problem.n_batches) * (len(_te) - 1)
+        return _check(lib().mcrng_run_pulse(self._h, C.byref(L), C.byref(st), C.byref(o),
+                                            _ptr(d_counts, torch.uint64, n, "d_counts"),
+                                            _ptr(d_flux, torch.float64, n, "d_flux"),
+                                            _ptr(d_diag, torch.uint64, NDIAG, "d_diag"), _stream(stream)))
 
     def last_run_ms(self):
         return float(lib().mcrng_last_run_ms(self._h))

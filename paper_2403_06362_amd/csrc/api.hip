@@ -1,6 +1,7 @@
 // Host side of the C ABI declared in include/mcrng.h: argument validation,
 // slab geometry (merged cells), stride skip-ahead tables, work units, device
-// buffers of a context, hipGraph capture and the launch-option autotuner.
+// buffers of a context, hipGraph capture, the launch-option autotuner and the
+// generation loop of the pulse problem.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -14,6 +15,7 @@
 #include <vector>
 
 #include "internal.hpp"
+#include "pulse.hpp"
 #include "mcrng.h"
 
 using namespace mcrng;
@@ -234,6 +236,8 @@ struct mcrng_ctx {
     DevBuf problems, edges64, sig64, scat64, cbin, edges32, sig32, tedges64, tedges32;
     DevBuf units, order, partial, unit_diag, counter, groups, dx, dt, pu_begin;
     DevBuf bank_a, bank_b, records, rec_begin;   // event schedule
+    DevBuf pulse_tedges, pulse_misc, pulse_diag, pulse_bank[2], pulse_stack;   // pulse problem
+    std::vector<double> h_pulse_tedges;
     std::vector<uint64_t> h_rec_begin;
 
     // host copies of the current tables (kept alive while copies are staged)
@@ -313,7 +317,9 @@ extern "C" int mcrng_ctx_destroy(mcrng_ctx* ctx) {
     DevBuf* bufs[] = {&ctx->problems, &ctx->edges64, &ctx->sig64, &ctx->scat64, &ctx->cbin, &ctx->edges32,
                       &ctx->sig32, &ctx->tedges64, &ctx->tedges32, &ctx->units, &ctx->order, &ctx->partial,
                       &ctx->unit_diag, &ctx->counter, &ctx->groups, &ctx->dx, &ctx->dt, &ctx->pu_begin,
-                      &ctx->bank_a, &ctx->bank_b, &ctx->records, &ctx->rec_begin};
+                      &ctx->bank_a, &ctx->bank_b, &ctx->records, &ctx->rec_begin, &ctx->pulse_tedges,
+                      &ctx->pulse_misc, &ctx->pulse_diag, &ctx->pulse_bank[0], &ctx->pulse_bank[1],
+                      &ctx->pulse_stack};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
@@ -912,4 +918,180 @@ extern "C" int mcrng_autotune(mcrng_ctx* ctx, const mcrng_lcg* lcg, const mcrng_
     *best = cur;
     if (best_ms) *best_ms = cur_ms;
     return MCRNG_OK;
+}
+
+// ------------------------------------------------------------ pulse problem
+
+static int validate_pulse(const mcrng_pulse_problem* P) {
+    if (!P) return fail(MCRNG_EINVAL, "problem is NULL");
+    if (!(P->sigma_t > 0.0) || !std::isfinite(P->sigma_t)) return fail(MCRNG_EINVAL, "sigma_t must be finite and > 0");
+    if (!(P->scatter >= 0.0 && P->scatter <= 1.0)) return fail(MCRNG_EINVAL, "scatter must be in [0, 1]");
+    if (!(P->multiplicity >= 0.0 && P->multiplicity <= 14.0))
+        return fail(MCRNG_EINVAL, "multiplicity must be in [0, 14]");
+    if (!std::isfinite(P->x_lo) || !std::isfinite(P->x_hi) || !(P->x_lo < P->x_hi))
+        return fail(MCRNG_EINVAL, "the tally interval needs finite x_lo < x_hi");
+    if (P->n_time_bins < 1 || P->n_time_bins > 4096) return fail(MCRNG_EINVAL, "n_time_bins must be in 1..4096");
+    if (!P->time_edges) return fail(MCRNG_EINVAL, "time_edges is NULL");
+    if (!(P->time_edges[0] >= 0.0) || !increasing(P->time_edges, P->n_time_bins + 1) ||
+        !std::isfinite(P->time_edges[P->n_time_bins]))
+        return fail(MCRNG_EINVAL, "time edges must be finite, >= 0 and strictly increasing");
+    if (P->n_batches < 1 || P->per_batch < 1) return fail(MCRNG_EINVAL, "n_batches and per_batch must be >= 1");
+    if ((static_cast<u128>(P->n_batches) * P->per_batch) >> 40) return fail(MCRNG_EINVAL, "more than 2^40 sources");
+    if ((static_cast<u128>(P->first_batch) + P->n_batches) * P->per_batch >> 64)
+        return fail(MCRNG_EINVAL, "source index overflows 64 bits");
+    const mcrng_seeding& S = P->seeding;
+    if (S.kind != MCRNG_SEED_HASH && S.kind != MCRNG_SEED_STRIDE) return fail(MCRNG_EINVAL, "seeding.kind unknown");
+    if (S.hier || S.first_index || S.group_key)
+        return fail(MCRNG_EINVAL, "pulse seeding uses first_batch; hier, first_index and group_key must be 0");
+    if (S.kind == MCRNG_SEED_STRIDE && S.stride == 0) return fail(MCRNG_EINVAL, "stride seeding needs stride >= 1");
+    return MCRNG_OK;
+}
+
+static PulseBankView carve_pulse_bank(void* base, uint64_t cap) {
+    char* p = static_cast<char*>(base);
+    PulseBankView v;
+    v.x = reinterpret_cast<double*>(p);
+    v.t = reinterpret_cast<double*>(p + cap * 8);
+    v.X = reinterpret_cast<uint64_t*>(p + cap * 16);
+    v.batch = reinterpret_cast<uint32_t*>(p + cap * 24);
+    v.tb = reinterpret_cast<int32_t*>(p + cap * 28);
+    return v;
+}
+
+static int read_u64(const uint64_t* d, uint64_t* h, hipStream_t st) {
+    HIP_TRY(hipMemcpyAsync(h, d, sizeof *h, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return MCRNG_OK;
+}
+
+extern "C" int mcrng_run_pulse(mcrng_ctx* ctx, const mcrng_lcg* lcg, const mcrng_pulse_problem* P,
+                               const mcrng_pulse_opts* opts, uint64_t* d_counts, double* d_flux, uint64_t* d_diag,
+                               void* stream) {
+    LcgDev L;
+    int rc = validate_lcg(lcg, 53, &L);
+    if (rc < 0) return rc;
+    if ((rc = validate_pulse(P)) < 0) return rc;
+    mcrng_pulse_opts o;
+    std::memset(&o, 0, sizeof o);
+    if (opts) o = *opts;
+    for (uint32_t r : o.reserved)
+        if (r) return fail(MCRNG_EINVAL, "opts.reserved must be 0");
+    const bool hash = P->seeding.kind == MCRNG_SEED_HASH;
+    if (o.schedule == MCRNG_PULSE_AUTO) o.schedule = hash ? MCRNG_PULSE_BANK : MCRNG_PULSE_FAMILY;
+    if (o.schedule != MCRNG_PULSE_BANK && o.schedule != MCRNG_PULSE_FAMILY)
+        return fail(MCRNG_EINVAL, "opts.schedule unknown");
+    if (o.schedule == MCRNG_PULSE_BANK && !hash)
+        return fail(MCRNG_EINVAL, "the bank schedule needs hash seeding (stride families share one stream)");
+    if (o.block == 0) o.block = 256;
+    if (o.block != 64 && o.block != 128 && o.block != 256 && o.block != 512 && o.block != 1024)
+        return fail(MCRNG_EINVAL, "opts.block = %u not in {64,128,256,512,1024}", o.block);
+    if (o.stack_depth == 0) o.stack_depth = 128;
+    if (o.stack_depth > 65535) return fail(MCRNG_EINVAL, "opts.stack_depth must be <= 65535");
+    if (!ctx) return fail(MCRNG_EINVAL, "ctx is NULL");
+    if (!d_counts) return fail(MCRNG_EINVAL, "d_counts is NULL");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+
+    const uint64_t n_src = static_cast<uint64_t>(P->n_batches) * P->per_batch;
+    PulseParams pp;
+    std::memset(&pp, 0, sizeof pp);
+    pp.lcg = L;
+    pp.first_batch = P->first_batch;
+    pp.per_batch = P->per_batch;
+    pp.n_batches = P->n_batches;
+    pp.n_time_bins = P->n_time_bins;
+    pp.hash = hash ? 1u : 0u;
+    const double nu_floor = std::floor(P->multiplicity);
+    pp.n_floor = static_cast<uint32_t>(nu_floor);
+    pp.nu_frac = P->multiplicity - nu_floor;
+    pp.sigma_t = P->sigma_t;
+    pp.scatter = P->scatter;
+    pp.x_lo = P->x_lo;
+    pp.x_hi = P->x_hi;
+    pp.t_end = P->time_edges[P->n_time_bins];
+    pp.tb0 = -1;
+    while (pp.tb0 + 1 < static_cast<int32_t>(P->n_time_bins) && P->time_edges[pp.tb0 + 1] <= 0.0) pp.tb0++;
+    pp.stack_depth = o.stack_depth;
+    int warn = MCRNG_OK;
+    if (hash) {
+        pp.seed.kind = SEED_HASH;
+        pp.seed.base = P->seeding.base;   // the global seed s; batch parents are hashed on the device
+    } else {
+        mcrng_seeding sd = P->seeding;
+        sd.first_index = P->first_batch * P->per_batch;
+        if ((rc = build_seed(L, &sd, n_src, &pp.seed)) < 0) return rc;
+        warn = rc;
+        pp.stride_q = P->seeding.stride;
+    }
+    const uint32_t n_max = pp.n_floor + (pp.nu_frac > 0.0 ? 1u : 0u);
+
+    ctx->h_pulse_tedges.assign(P->time_edges, P->time_edges + P->n_time_bins + 1);
+    if ((rc = upload(ctx->pulse_tedges, ctx->h_pulse_tedges, st)) < 0) return rc;
+    if ((rc = ensure(ctx->pulse_misc, 64, st)) < 0) return rc;
+    if ((rc = ensure(ctx->pulse_diag, kNDiag * sizeof(uint64_t), st)) < 0) return rc;
+    pp.t_edges = static_cast<const double*>(ctx->pulse_tedges.p);
+    pp.counts = d_counts;
+    pp.diag = static_cast<uint64_t*>(ctx->pulse_diag.p);
+    uint64_t* misc = static_cast<uint64_t*>(ctx->pulse_misc.p);
+    pp.out_count = misc;
+    pp.family_counter = misc + 1;
+    pp.overflow = reinterpret_cast<uint32_t*>(misc + 2);
+    HIP_TRY(launch_fill_u64(misc, 8, 0ull, st));
+    HIP_TRY(launch_fill_u64(pp.diag, kNDiag, 0ull, st));
+    HIP_TRY(launch_fill_u64(d_counts, static_cast<uint64_t>(P->n_batches) * P->n_time_bins, 0ull, st));
+    HIP_TRY(hipEventRecord(ctx->ev0, st));
+    ctx->timing_valid = false;
+
+    if (o.schedule == MCRNG_PULSE_BANK) {
+        // generations: every particle of a bank runs one flight; sources in
+        // chunks so that the banks stay within a few GB
+        const uint64_t chunk = 1ull << 22;
+        for (uint64_t c0 = 0; c0 < n_src; c0 += chunk) {
+            const uint64_t c1 = std::min(n_src, c0 + chunk);
+            int cur = 0;
+            uint64_t cap = std::max<uint64_t>(n_max * (c1 - c0), 1);
+            if ((rc = ensure(ctx->pulse_bank[cur], cap * 32, st)) < 0) return rc;
+            pp.src_begin = c0;
+            pp.src_end = c1;
+            pp.out = carve_pulse_bank(ctx->pulse_bank[cur].p, cap);
+            pp.out_cap = cap;
+            HIP_TRY(launch_fill_u64(pp.out_count, 1, 0ull, st));
+            HIP_TRY(launch_pulse_bank(pp, true, static_cast<int>(o.block), st));
+            uint64_t n = 0;
+            if ((rc = read_u64(pp.out_count, &n, st)) < 0) return rc;
+            uint64_t in_cap = cap;
+            while (n > 0) {
+                const int nxt = 1 - cur;
+                const uint64_t ocap = n_max * n;
+                if ((rc = ensure(ctx->pulse_bank[nxt], ocap * 32, st)) < 0) return rc;
+                pp.in = carve_pulse_bank(ctx->pulse_bank[cur].p, in_cap);
+                pp.n_in = n;
+                pp.out = carve_pulse_bank(ctx->pulse_bank[nxt].p, ocap);
+                pp.out_cap = ocap;
+                HIP_TRY(launch_fill_u64(pp.out_count, 1, 0ull, st));
+                HIP_TRY(launch_pulse_bank(pp, false, static_cast<int>(o.block), st));
+                if ((rc = read_u64(pp.out_count, &n, st)) < 0) return rc;
+                cur = nxt;
+                in_cap = ocap;
+            }
+        }
+    } else {
+        const uint32_t grid = pulse_family_grid(static_cast<int>(o.block));
+        const uint64_t lanes = static_cast<uint64_t>(grid) * o.block;
+        if ((rc = ensure(ctx->pulse_stack, lanes * o.stack_depth * sizeof(PulseStackEntry), st)) < 0) return rc;
+        pp.stack = static_cast<PulseStackEntry*>(ctx->pulse_stack.p);
+        pp.src_begin = 0;
+        pp.src_end = n_src;
+        HIP_TRY(launch_pulse_family(pp, static_cast<int>(o.block), grid, st));
+    }
+    HIP_TRY(hipEventRecord(ctx->ev1, st));
+    ctx->timing_valid = true;
+    if (d_flux) HIP_TRY(launch_pulse_flux(pp, d_flux, st));
+    if (d_diag)
+        HIP_TRY(hipMemcpyAsync(d_diag, pp.diag, kNDiag * sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
+    uint64_t flags = 0;
+    if ((rc = read_u64(misc + 2, &flags, st)) < 0) return rc;
+    if (flags & 0xffffffffull)
+        return fail(MCRNG_ERANGE, "a family stack (opts.stack_depth = %u) or a bank ran out of room", o.stack_depth);
+    return warn;
 }

@@ -61,3 +61,36 @@ def test_tally_bins_host_only(M):
     import workloads as W
     probs = [W.small_slab(), W.long_chain(n_histories=10), W.multi_region(n_histories=10)]
     assert M.tally_bins(probs) == 20 + 64 * 200 + 20 * 50
+
+
+def test_pulse_host_validation_without_gpu(M):
+    """mcrng_run_pulse checks the generator, the problem and the options
+    before it touches a context or the GPU."""
+    import numpy as np
+    import workloads as W
+    from paper_2403_06362_amd import _binding as B
+    lib = B.lib()
+    L = B.make_lcg(W.Lcg())
+
+    def call(prob, group_key=0, **opts):
+        st, keep = B.make_pulse_problem(prob)
+        st.seeding.hier, st.seeding.group_key = (1, group_key) if group_key else (0, 0)
+        o = B.make_pulse_opts(**opts)
+        rc = lib.mcrng_run_pulse(None, C.byref(L), C.byref(st), C.byref(o), None, None, None, None)
+        return rc, lib.mcrng_last_error().decode()
+
+    good = W.pulse(n_batches=2, per_batch=3)
+    assert call(good) == (B.EINVAL, "ctx is NULL")
+    for bad, word in ((good.with_(sigma_t=0.0), "sigma_t"), (good.with_(scatter=1.5), "scatter"),
+                      (good.with_(nu=15.0), "multiplicity"), (good.with_(x_lo=2.0), "x_lo"),
+                      (good.with_(time_edges=np.array([0.0, 2.0, 1.0])), "time edges"),
+                      (good.with_(time_edges=np.array([-1.0, 2.0])), "time edges"),
+                      (good.with_(per_batch=0), "per_batch")):
+        rc, msg = call(bad)
+        assert rc == B.EINVAL and word in msg, (word, msg)
+    rc, msg = call(good, group_key=3)
+    assert rc == B.EINVAL and "first_batch" in msg
+    rc, msg = call(good.with_(seeding=W.stride_seeding()), schedule=B.PULSE_BANK)
+    assert rc == B.EINVAL and "hash" in msg
+    rc, msg = call(good, block=96)
+    assert rc == B.EINVAL and "block" in msg

@@ -1,0 +1,147 @@
+"""GPU parity of the pulse problem (mcrng_run_pulse) against the CPU oracle:
+a pulse in an infinite multiplying medium whose secondaries are seeded on
+demand by hashing (eq. 5) or continue their source's stride stream.
+
+Counts are integers, so the bar is bit-exact counts per (batch, time bin),
+bit-exact flux and equal diagnostics, for every schedule (particle banks by
+generation, depth-first families per lane) and launch shape.  At the
+paper's full study size (30 repetitions x 1000 batches x 1000 sources) the
+oracle recomputes sampled batches; the run is checked whole by its exact
+balances."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from helpers import u64_np
+
+pytestmark = pytest.mark.gpu
+LCG = W.Lcg()
+
+
+def say(*a):
+    print("[gpu]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def M():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    import paper_2403_06362_amd as M
+    M.lib()
+    return M
+
+
+@pytest.fixture(scope="module")
+def ctx(M):
+    c = M.Context(0)
+    yield c
+    c.close()
+
+
+def run(M, ctx, prob, **opts):
+    import torch
+    counts, flux, diag = M.pulse(prob, LCG, ctx=ctx, opts=M.make_pulse_opts(**opts))
+    torch.cuda.synchronize()
+    d = dict(zip(M.PULSE_DIAG_NAMES, (int(v) for v in u64_np(diag))))
+    return u64_np(counts).reshape(prob.n_batches, -1), flux.cpu().numpy(), d
+
+
+def check(orc, prob, counts, flux, diag, threads=8):
+    ref = orc.pulse(prob, LCG, threads=threads)
+    assert np.array_equal(counts, ref.counts)
+    assert diag == ref.diag
+    assert np.array_equal(flux, orc.pulse_flux(prob, LCG, ref.counts))
+    return ref
+
+
+@pytest.mark.parametrize("kind", ["hash", "stride"])
+def test_small_pulse_parity(M, ctx, orc, kind):
+    sd = W.hash_seeding() if kind == "hash" else W.stride_seeding()
+    p = W.pulse(sd, n_batches=10, per_batch=100)
+    say("small pulse", kind)
+    check(orc, p, *run(M, ctx, p))
+    say("small pulse family schedule", kind)
+    check(orc, p, *run(M, ctx, p, schedule=M.PULSE_FAMILY))
+
+
+def test_schedules_and_shapes_bit_identical(M, ctx, orc):
+    p = W.pulse(W.hash_seeding(), n_batches=17, per_batch=333, first_batch=4)
+    ref = orc.pulse(p, LCG, threads=8)
+    for schedule in (M.PULSE_BANK, M.PULSE_FAMILY):
+        for block in (64, 256, 1024):
+            say("shape", schedule, block)
+            c, _, d = run(M, ctx, p, schedule=schedule, block=block, stack_depth=40)
+            assert np.array_equal(c, ref.counts), (schedule, block)
+            assert d == ref.diag
+    ps = p.with_(seeding=W.stride_seeding())
+    refs = orc.pulse(ps, LCG, threads=8)
+    for block in (64, 512):
+        c, _, d = run(M, ctx, ps, block=block)
+        assert np.array_equal(c, refs.counts) and d == refs.diag
+
+
+def test_paper_problem_parity(M, ctx, orc):
+    """The paper's problem, 1000 batches x 1000 sources, both seedings."""
+    for kind in ("hash", "stride"):
+        sd = W.hash_seeding() if kind == "hash" else W.stride_seeding()
+        p = W.pulse(sd)
+        say("paper problem", kind)
+        check(orc, p, *run(M, ctx, p), threads=16)
+
+
+def test_edge_problems(M, ctx, orc):
+    base = W.pulse(W.hash_seeding(), n_batches=3, per_batch=50)
+    probs = [
+        base.with_(n_batches=1, per_batch=1),
+        base.with_(scatter=0.0),                                   # no secondaries
+        base.with_(nu=0.0),                                        # scatterings end the line
+        base.with_(nu=3.0, scatter=0.3),                           # integer multiplicity
+        base.with_(time_edges=np.array([0.5, 1.0, 3.0, 4.5])),     # collisions before T[0] unscored
+        base.with_(x_lo=0.25, x_hi=0.5, sigma_t=2.5),
+    ]
+    for i, p in enumerate(probs):
+        for kind in ("hash", "stride"):
+            q = p.with_(seeding=W.hash_seeding() if kind == "hash" else W.stride_seeding())
+            say("edge problem", i, kind)
+            check(orc, q, *run(M, ctx, q), threads=2)
+
+
+def test_stack_overflow_is_reported(M, ctx):
+    """A family that outgrows opts.stack_depth is reported (MCRNG_ERANGE);
+    the kernel checks the depth before every push, so nothing is written out
+    of bounds."""
+    p = W.pulse(W.stride_seeding(), n_batches=4, per_batch=200)
+    with pytest.raises(M.McrngError) as e:
+        run(M, ctx, p, stack_depth=1)
+    assert e.value.code == -4
+    # the context stays usable
+    c, _, d = run(M, ctx, p.with_(n_batches=1, per_batch=5))
+    assert d["sources"] == 5
+
+
+def test_full_study_sampled(M, ctx, orc):
+    """The paper's normality study at full size: 30 repetitions x 1000
+    batches x 1000 sources = 3e7 sources in one run (the bank schedule goes
+    through several source chunks).  Sampled batches are recomputed by the
+    oracle; the whole run satisfies the exact particle and draw balances."""
+    p = W.pulse(W.hash_seeding(), n_batches=30000, per_batch=1000)
+    say("full study, hash")
+    counts, _, d = run(M, ctx, p)
+    assert d["sources"] == p.n_sources
+    particles = d["sources"] + d["secondaries"]
+    assert particles == d["absorbed"] + d["census"] + d["scatters"]
+    assert d["draws"] == 2 * particles + d["collisions"] + d["scatters"]
+    assert int(counts.sum()) == d["tallied"]
+    for b in (0, 4321, 29999):
+        ref = orc.pulse(p, LCG, b, b + 1)
+        assert np.array_equal(counts[b], ref.counts[b]), b
+    say("full study, stride")
+    ps = p.with_(seeding=W.stride_seeding())
+    counts, _, d = run(M, ctx, ps)
+    assert d["sources"] == p.n_sources and d["over_stride"] <= d["sources"]
+    for b in (1, 17000, 29998):
+        ref = orc.pulse(ps, LCG, b, b + 1)
+        assert np.array_equal(counts[b], ref.counts[b]), b
