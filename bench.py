@@ -13,6 +13,10 @@ Also reported, each timed separately after the headline loop:
   transport     the 1e8-history long-chain slab (50 mfp, c = 0.99, 200 bins,
                 64 batches): histories/s, draws/s, events/s for hash FP64,
                 hash FP32-flight and stride FP64 (kernel time, HIP events)
+  pulse         the paper's test problem (pulse in an infinite multiplying
+                medium, secondaries seeded on demand), 1000 x 1000 sources:
+                hash-seeded particle banks vs depth-first families, and the
+                paper's normality study at full size (30 x 1000 batches)
   roofline      of the draw kernel: integer VALU lane-ops per launch over the
                 average kernel duration (HIP events on the launch stream)
   cpu_baseline  the CPU oracle on the host cores, same workload
@@ -267,6 +271,7 @@ def main():
         tr["hash_over_stride"] = legs["stride_fp64"]["ms"] / legs["hash_fp64"]["ms"]
         out["histories_per_s"] = legs["hash_fp64"]["histories_per_s"]
         out["transport"] = tr
+        out["pulse"] = pulse_leg(M, W, torch, lcg, ctx, oracle)
         if args.full:
             out["batched"] = batched_leg(M, W, torch, lcg, ctx)
             out["multi_region"] = multi_region_leg(M, W, torch, lcg, ctx)
@@ -359,6 +364,74 @@ def multi_region_leg(M, W, torch, lcg, ctx):
     rel = np.abs(f32[m] - f64[m]) / f64[m]
     res["fp32_vs_fp64_flux_rel_err"] = {"max": float(rel.max()), "rms": float(np.sqrt(np.mean(rel ** 2)))}
     return res
+
+
+def pulse_run(M, torch, lcg, ctx, prob, schedule, reps):
+    nt = len(prob.time_edges) - 1
+    counts = torch.empty((prob.n_batches, nt), dtype=torch.uint64, device="cuda:0")
+    flux = torch.empty((prob.n_batches, nt), dtype=torch.float64, device="cuda:0")
+    diag = torch.empty(M.NDIAG, dtype=torch.uint64, device="cuda:0")
+    o = M.make_pulse_opts(schedule=schedule)
+    times = []
+    for _ in range(reps):
+        ctx.run_pulse(lcg, prob, counts, flux, diag, o)
+        times.append(ctx.last_run_ms())
+    d = dict(zip(M.PULSE_DIAG_NAMES, (int(v) for v in diag.view(torch.int64).cpu().numpy())))
+    return float(np.median(times)), flux.cpu().numpy(), d
+
+
+def pulse_leg(M, W, torch, lcg, ctx, oracle):
+    """The paper's test problem: a pulse in an infinite medium (c = 0.4,
+    nu = 2.75, census t = 20), 1000 batches x 1000 sources; secondaries
+    seeded on demand by hashing (eq. 5) or drawing from their source's
+    stride stream.  Then the paper's normality study at full size: 30
+    repetitions x 1000 batches, Shapiro-Wilk on each of the 20 center-flux
+    time points (600 tests per seeding)."""
+    from scipy import stats
+    out = {"workload": "pulse at x=t=0 in an infinite medium: sigma_t=1, c=0.4, nu=2.75, census t=20, "
+                       "collision estimator on x in [-1,1], 20 unit time bins, 1000 batches x 1000 sources",
+           "few_sources_workload": "the same medium, one batch of 4096 sources run to t=60 "
+                                   "(60 unit time bins, population about 400-fold)"}
+    p = W.pulse(W.hash_seeding())
+    few = W.pulse_few_sources()
+    for tag, base in (("", p), ("few_sources_", few)):
+        for name, prob, sched in (("hash_bank", base, M.PULSE_BANK), ("hash_family", base, M.PULSE_FAMILY),
+                                  ("stride_family", base.with_(seeding=W.stride_seeding()), M.PULSE_FAMILY)):
+            log("pulse", tag + name)
+            ms, _, d = pulse_run(M, torch, lcg, ctx, prob, sched, 3)
+            out[tag + name] = {"ms": ms, "sources_per_s": prob.n_sources / (ms * 1e-3),
+                               "particles_per_s": (d["sources"] + d["secondaries"]) / (ms * 1e-3),
+                               "collisions_per_s": d["collisions"] / (ms * 1e-3),
+                               "draws_per_s": d["draws"] / (ms * 1e-3),
+                               "collisions_per_source": d["collisions"] / d["sources"], "max_draws": d["max_draws"]}
+    out["few_sources_hash_bank_over_stride_family"] = (out["few_sources_stride_family"]["ms"] /
+                                                       out["few_sources_hash_bank"]["ms"])
+    out["hash_family_over_stride_family"] = out["stride_family"]["ms"] / out["hash_family"]["ms"]
+    # CPU oracle on a sample of the same problem (threads over batches)
+    threads = min(16, os.cpu_count() or 1)
+    sample = p.with_(n_batches=64)
+    t0 = time.perf_counter()
+    oracle.pulse(sample, lcg, threads=threads)
+    dt = time.perf_counter() - t0
+    out["cpu_oracle"] = {"sources_per_s": sample.n_sources / dt, "threads": threads,
+                         "sample": "64 batches x 1000 sources, hash seeding"}
+    out["gpu_over_cpu_oracle"] = out["hash_family"]["sources_per_s"] / out["cpu_oracle"]["sources_per_s"]
+
+    study = {}
+    for kind in ("hash", "stride"):
+        sd = W.hash_seeding() if kind == "hash" else W.stride_seeding()
+        prob = W.pulse(sd, n_batches=30000)
+        log("pulse normality study", kind)
+        ms, flux, d = pulse_run(M, torch, lcg, ctx, prob, M.PULSE_AUTO, 1)
+        f = flux.reshape(30, 1000, 20)
+        pv = np.array([[stats.shapiro(f[r, :, k]).pvalue for k in range(20)] for r in range(30)])
+        study[kind] = {"ms": ms, "sources_per_s": prob.n_sources / (ms * 1e-3), "tests": int(pv.size),
+                       "fail_p_lt_0.05": int(np.sum(pv < 0.05)),
+                       "median_p_per_time_bin": [float(v) for v in np.median(pv, axis=0)],
+                       "over_stride_families": d["over_stride"], "max_draws": d["max_draws"]}
+    study["paper_fails_of_600"] = {"stride": 369, "hash": 339}
+    out["normality_study"] = study
+    return out
 
 
 def cpu_baseline(oracle, W, lcg, counts):

@@ -238,6 +238,7 @@ struct mcrng_ctx {
     DevBuf bank_a, bank_b, records, rec_begin;   // event schedule
     DevBuf pulse_tedges, pulse_misc, pulse_diag, pulse_bank[2], pulse_stack;   // pulse problem
     std::vector<double> h_pulse_tedges;
+    uint64_t* h_pinned = nullptr;   // pinned host words for per-generation readbacks
     std::vector<uint64_t> h_rec_begin;
 
     // host copies of the current tables (kept alive while copies are staged)
@@ -260,7 +261,7 @@ struct mcrng_ctx {
     std::map<uint64_t, mcrng_run_opts> tuned;           // shape -> options
 };
 
-static int ensure(DevBuf& b, size_t bytes, hipStream_t st) {
+static int ensure(DevBuf& b, size_t bytes, hipStream_t st, size_t growth_quarters = 5) {
     if (bytes <= b.cap) return MCRNG_OK;
     if (b.p) {
         HIP_TRY(hipStreamSynchronize(st));
@@ -268,7 +269,7 @@ static int ensure(DevBuf& b, size_t bytes, hipStream_t st) {
         b.p = nullptr;
         b.cap = 0;
     }
-    size_t want = std::max<size_t>(bytes + bytes / 4, 256);
+    size_t want = std::max<size_t>(bytes / 4 * growth_quarters + bytes % 4, 256);
     HIP_TRY(hipMalloc(&b.p, want));
     b.cap = want;
     return MCRNG_OK;
@@ -322,6 +323,7 @@ extern "C" int mcrng_ctx_destroy(mcrng_ctx* ctx) {
                       &ctx->pulse_stack};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
+    if (ctx->h_pinned) (void)hipHostFree(ctx->h_pinned);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
@@ -958,9 +960,11 @@ static PulseBankView carve_pulse_bank(void* base, uint64_t cap) {
     return v;
 }
 
-static int read_u64(const uint64_t* d, uint64_t* h, hipStream_t st) {
-    HIP_TRY(hipMemcpyAsync(h, d, sizeof *h, hipMemcpyDeviceToHost, st));
+static int read_u64(mcrng_ctx* ctx, const uint64_t* d, uint64_t* h, hipStream_t st) {
+    if (!ctx->h_pinned) HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&ctx->h_pinned), 64, hipHostMallocDefault));
+    HIP_TRY(hipMemcpyAsync(ctx->h_pinned, d, sizeof *h, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    *h = ctx->h_pinned[0];
     return MCRNG_OK;
 }
 
@@ -977,12 +981,12 @@ extern "C" int mcrng_run_pulse(mcrng_ctx* ctx, const mcrng_lcg* lcg, const mcrng
     for (uint32_t r : o.reserved)
         if (r) return fail(MCRNG_EINVAL, "opts.reserved must be 0");
     const bool hash = P->seeding.kind == MCRNG_SEED_HASH;
-    if (o.schedule == MCRNG_PULSE_AUTO) o.schedule = hash ? MCRNG_PULSE_BANK : MCRNG_PULSE_FAMILY;
-    if (o.schedule != MCRNG_PULSE_BANK && o.schedule != MCRNG_PULSE_FAMILY)
+    const uint64_t n_src = static_cast<uint64_t>(P->n_batches) * P->per_batch;
+    if (o.block == 0) o.block = 256;
+    if (o.schedule != MCRNG_PULSE_AUTO && o.schedule != MCRNG_PULSE_BANK && o.schedule != MCRNG_PULSE_FAMILY)
         return fail(MCRNG_EINVAL, "opts.schedule unknown");
     if (o.schedule == MCRNG_PULSE_BANK && !hash)
         return fail(MCRNG_EINVAL, "the bank schedule needs hash seeding (stride families share one stream)");
-    if (o.block == 0) o.block = 256;
     if (o.block != 64 && o.block != 128 && o.block != 256 && o.block != 512 && o.block != 1024)
         return fail(MCRNG_EINVAL, "opts.block = %u not in {64,128,256,512,1024}", o.block);
     if (o.stack_depth == 0) o.stack_depth = 128;
@@ -991,8 +995,14 @@ extern "C" int mcrng_run_pulse(mcrng_ctx* ctx, const mcrng_lcg* lcg, const mcrng
     if (!d_counts) return fail(MCRNG_EINVAL, "d_counts is NULL");
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t st = static_cast<hipStream_t>(stream);
+    if (o.schedule == MCRNG_PULSE_AUTO) {
+        // families need about one source per resident lane to fill the GPU
+        // and even out their sizes; with fewer sources only the particle
+        // bank (hash seeding) keeps the GPU busy
+        const uint64_t lanes = static_cast<uint64_t>(pulse_family_grid(static_cast<int>(o.block))) * o.block;
+        o.schedule = (hash && n_src < lanes) ? MCRNG_PULSE_BANK : MCRNG_PULSE_FAMILY;
+    }
 
-    const uint64_t n_src = static_cast<uint64_t>(P->n_batches) * P->per_batch;
     PulseParams pp;
     std::memset(&pp, 0, sizeof pp);
     pp.lcg = L;
@@ -1032,10 +1042,12 @@ extern "C" int mcrng_run_pulse(mcrng_ctx* ctx, const mcrng_lcg* lcg, const mcrng
     pp.t_edges = static_cast<const double*>(ctx->pulse_tedges.p);
     pp.counts = d_counts;
     pp.diag = static_cast<uint64_t*>(ctx->pulse_diag.p);
+    // misc words: out_count, item_counter (reset per bank launch), family_counter, overflow
     uint64_t* misc = static_cast<uint64_t*>(ctx->pulse_misc.p);
     pp.out_count = misc;
-    pp.family_counter = misc + 1;
-    pp.overflow = reinterpret_cast<uint32_t*>(misc + 2);
+    pp.item_counter = misc + 1;
+    pp.family_counter = misc + 2;
+    pp.overflow = reinterpret_cast<uint32_t*>(misc + 3);
     HIP_TRY(launch_fill_u64(misc, 8, 0ull, st));
     HIP_TRY(launch_fill_u64(pp.diag, kNDiag, 0ull, st));
     HIP_TRY(launch_fill_u64(d_counts, static_cast<uint64_t>(P->n_batches) * P->n_time_bins, 0ull, st));
@@ -1043,36 +1055,38 @@ extern "C" int mcrng_run_pulse(mcrng_ctx* ctx, const mcrng_lcg* lcg, const mcrng
     ctx->timing_valid = false;
 
     if (o.schedule == MCRNG_PULSE_BANK) {
-        // generations: every particle of a bank runs one flight; sources in
-        // chunks so that the banks stay within a few GB
-        const uint64_t chunk = 1ull << 22;
+        // generations: a launch runs the lines of descent of its input
+        // particles (their first emerging particles inline) and banks the
+        // siblings for the next launch.  Capacity per launch: the continue
+        // budget (2 per input particle), n_max per input particle, and one
+        // iteration's appends per wave.
+        // Sources go in chunks so that the banks stay within tens of GB.
+        const uint64_t chunk = 1ull << 23;
         for (uint64_t c0 = 0; c0 < n_src; c0 += chunk) {
             const uint64_t c1 = std::min(n_src, c0 + chunk);
-            int cur = 0;
-            uint64_t cap = std::max<uint64_t>(n_max * (c1 - c0), 1);
-            if ((rc = ensure(ctx->pulse_bank[cur], cap * 32, st)) < 0) return rc;
-            pp.src_begin = c0;
-            pp.src_end = c1;
-            pp.out = carve_pulse_bank(ctx->pulse_bank[cur].p, cap);
-            pp.out_cap = cap;
-            HIP_TRY(launch_fill_u64(pp.out_count, 1, 0ull, st));
-            HIP_TRY(launch_pulse_bank(pp, true, static_cast<int>(o.block), st));
-            uint64_t n = 0;
-            if ((rc = read_u64(pp.out_count, &n, st)) < 0) return rc;
-            uint64_t in_cap = cap;
+            int cur = 0, nxt = 1;
+            uint64_t n = c1 - c0, in_cap = 0;
+            bool sources = true;
             while (n > 0) {
-                const int nxt = 1 - cur;
-                const uint64_t ocap = n_max * n;
-                if ((rc = ensure(ctx->pulse_bank[nxt], ocap * 32, st)) < 0) return rc;
-                pp.in = carve_pulse_bank(ctx->pulse_bank[cur].p, in_cap);
-                pp.n_in = n;
+                const uint32_t grid = pulse_bank_grid(sources, static_cast<int>(o.block), n);
+                const uint64_t waves = static_cast<uint64_t>(grid) * o.block / 64;
+                const uint64_t budget = 2 * n;
+                const uint64_t slack = (waves + 1) * 64 * (n_max > 1 ? n_max - 1 : 0);
+                const uint64_t ocap = budget + static_cast<uint64_t>(n_max) * n + slack;
+                if ((rc = ensure(ctx->pulse_bank[nxt], ocap * 32, st, 8)) < 0) return rc;
+                pp.src_begin = c0;
+                pp.src_end = c1;
+                if (!sources) pp.in = carve_pulse_bank(ctx->pulse_bank[cur].p, in_cap);
+                pp.n_in = sources ? 0 : n;
                 pp.out = carve_pulse_bank(ctx->pulse_bank[nxt].p, ocap);
                 pp.out_cap = ocap;
-                HIP_TRY(launch_fill_u64(pp.out_count, 1, 0ull, st));
-                HIP_TRY(launch_pulse_bank(pp, false, static_cast<int>(o.block), st));
-                if ((rc = read_u64(pp.out_count, &n, st)) < 0) return rc;
-                cur = nxt;
+                pp.cont_budget = budget;
+                HIP_TRY(launch_fill_u64(misc, 2, 0ull, st));
+                HIP_TRY(launch_pulse_bank(pp, sources, static_cast<int>(o.block), grid, st));
+                if ((rc = read_u64(ctx, pp.out_count, &n, st)) < 0) return rc;
+                std::swap(cur, nxt);
                 in_cap = ocap;
+                sources = false;
             }
         }
     } else {
@@ -1090,7 +1104,7 @@ extern "C" int mcrng_run_pulse(mcrng_ctx* ctx, const mcrng_lcg* lcg, const mcrng
     if (d_diag)
         HIP_TRY(hipMemcpyAsync(d_diag, pp.diag, kNDiag * sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
     uint64_t flags = 0;
-    if ((rc = read_u64(misc + 2, &flags, st)) < 0) return rc;
+    if ((rc = read_u64(ctx, misc + 3, &flags, st)) < 0) return rc;
     if (flags & 0xffffffffull)
         return fail(MCRNG_ERANGE, "a family stack (opts.stack_depth = %u) or a bank ran out of room", o.stack_depth);
     return warn;

@@ -13,11 +13,17 @@
 //   stride seeding they continue the source's one stream, depth first.
 //
 // Two schedules:
-//   k_pulse_bank (hash only)  one launch per generation: every particle of
-//       the input bank (or every source) runs one flight; the particles
-//       emerging from it are appended to the output bank through one atomic
-//       per wave (wave prefix sum of the per-lane counts).  Output capacity
-//       is n_max per input particle, so no append can overflow.
+//   k_pulse_bank (hash only)  one launch per generation.  A wave takes 256
+//       input particles (or sources) at a time through one atomic and hands
+//       them to its idle lanes; a lane runs each one's line of descent: at a
+//       scattering it keeps the first emerging particle in registers and
+//       appends its siblings to the output bank (wave prefix sum, one atomic
+//       per wave, written one iteration later so that the next flight hides
+//       the atomic) while the wave's last view of the output count is within
+//       the launch's budget; past it, a scattering appends all n particles
+//       and ends the line.  Appends are thus at most budget + n_max per input
+//       particle + one iteration's appends per wave and one more (the view is
+//       one iteration old), which the output capacity covers.
 //   k_pulse_family            one source family per lane (taken from a
 //       global counter, one atomic per wave), walked depth first with a
 //       per-lane stack in HBM; a stack entry holds the siblings still to
@@ -42,13 +48,16 @@ struct PParticle {
     uint32_t batch;
 };
 
-// Runs the particle from its start to its end.  Returns the number of
-// particles emerging from it (0 unless it scattered); p then holds the
-// collision site and the state after the particle's draws.  *draws counts
-// the numbers drawn.
-__device__ __forceinline__ uint32_t pulse_particle(const PulseParams& P, PParticle& p, PulseLane& c,
-                                                   uint32_t* draws) {
+enum : uint32_t { PULSE_CENSUS = 0, PULSE_ABSORBED = 1, PULSE_SCATTERED = 2 };
+
+// Runs the particle from its start to its end.  Returns PULSE_CENSUS,
+// PULSE_ABSORBED or PULSE_SCATTERED, with *n the number of particles
+// emerging (0 unless it scattered); p then holds the collision site and the
+// state after the particle's draws.  *draws counts the numbers drawn.
+__device__ __forceinline__ uint32_t pulse_flight(const PulseParams& P, PParticle& p, PulseLane& c,
+                                                 uint32_t* draws, uint32_t* n) {
     const LcgDev& L = P.lcg;
+    *n = 0;
     p.X = lcg_next(L, p.X);
     const double mu = 2.0 * to_uniform(L, p.X) - 1.0;
     p.X = lcg_next(L, p.X);
@@ -56,10 +65,7 @@ __device__ __forceinline__ uint32_t pulse_particle(const PulseParams& P, PPartic
     *draws += 2;
     const double s = tau / P.sigma_t;
     const double tn = p.t + s;
-    if (!(tn < P.t_end)) {
-        c.census++;
-        return 0;
-    }
+    if (!(tn < P.t_end)) return PULSE_CENSUS;
     const double step = mu * s;
     p.x = p.x + step;
     p.t = tn;
@@ -73,14 +79,22 @@ __device__ __forceinline__ uint32_t pulse_particle(const PulseParams& P, PPartic
     }
     p.X = lcg_next(L, p.X);
     *draws += 1;
-    if (!(to_uniform(L, p.X) < P.scatter)) {
-        c.absorbed++;
-        return 0;
-    }
+    if (!(to_uniform(L, p.X) < P.scatter)) return PULSE_ABSORBED;
     p.X = lcg_next(L, p.X);
     *draws += 1;
-    const uint32_t n = P.n_floor + (to_uniform(L, p.X) < P.nu_frac ? 1u : 0u);
-    c.scatters++;
+    *n = P.n_floor + (to_uniform(L, p.X) < P.nu_frac ? 1u : 0u);
+    return PULSE_SCATTERED;
+}
+
+// pulse_flight plus the end counters (kept out of the branches above so that
+// the compiler does not fold them into an indexed array in scratch memory).
+__device__ __forceinline__ uint32_t pulse_particle(const PulseParams& P, PParticle& p, PulseLane& c,
+                                                   uint32_t* draws) {
+    uint32_t n = 0;
+    const uint32_t r = pulse_flight(P, p, c, draws, &n);
+    c.census += static_cast<uint64_t>(r == PULSE_CENSUS);
+    c.absorbed += static_cast<uint64_t>(r == PULSE_ABSORBED);
+    c.scatters += static_cast<uint64_t>(r == PULSE_SCATTERED);
     c.secondaries += n;
     return n;
 }
@@ -137,62 +151,142 @@ __device__ __forceinline__ uint32_t lane_prefix(uint64_t mask) {
 
 // ------------------------------------------------------------ bank schedule
 
+// Wave prefix sum of per-lane values v < 16 (one ballot per bit).
+__device__ __forceinline__ uint32_t wave_prefix16(uint32_t v, uint32_t* total) {
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int bit = 0; bit < 4; ++bit) {
+        const uint64_t m = __ballot((v >> bit) & 1u);
+        off += lane_prefix(m) << bit;
+        tot += static_cast<uint32_t>(__popcll(m)) << bit;
+    }
+    *total = tot;
+    return off;
+}
+
+// Appends of one lane waiting for the wave's atomic: keys k0..n of the
+// particles emerging at (x, t) from the parent state X_p.
+struct PendingAppend {
+    double x, t;
+    uint64_t Xp;
+    uint32_t batch;
+    int32_t tb;
+    uint32_t k0, n, off;
+};
+
+__device__ __forceinline__ void write_appends(const PulseParams& P, const PendingAppend& a, uint64_t base) {
+    for (uint32_t k = a.k0; k <= a.n; ++k) {
+        const uint64_t o = base + a.off + (k - a.k0);
+        if (o < P.out_cap) {
+            P.out.x[o] = a.x;
+            P.out.t[o] = a.t;
+            P.out.X[o] = murmur_hash(k, a.Xp) & P.lcg.mask;
+            P.out.batch[o] = a.batch;
+            P.out.tb[o] = a.tb;
+        } else {
+            atomicOr(P.overflow, 1u);
+        }
+    }
+}
+
 template <bool SOURCES, int BLOCK>
 __global__ void __launch_bounds__(BLOCK) k_pulse_bank(PulseParams P) {
+    constexpr uint32_t kChunk = 256;   // items a wave takes per atomic
     PulseLane c;
     const uint64_t n_items = SOURCES ? P.src_end - P.src_begin : P.n_in;
-    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * BLOCK;
     const uint32_t lane = threadIdx.x & 63u;
-    // every lane of a wave runs the same number of rounds (the ballots below need the whole wave)
-    const uint64_t first = static_cast<uint64_t>(blockIdx.x) * BLOCK + (threadIdx.x & ~63u);
-    for (uint64_t base = first; base < n_items; base += stride) {
-        const uint64_t item = base + lane;
-        uint32_t n = 0;
-        PParticle p;
-        if (item < n_items) {
+    uint64_t wnext = 0, wend = 0;      // wave-uniform: the wave's unassigned items [wnext, wend)
+    bool exhausted = false;            // wave-uniform
+    PParticle p;
+    p.x = p.t = 0.0;
+    p.X = 0;
+    p.tb = -1;
+    p.batch = 0;
+    bool active = false;
+    // the previous iteration's appends: written once its atomic has returned,
+    // after this iteration's flight (so the flight hides the atomic's latency)
+    PendingAppend pa;
+    pa.k0 = 1;
+    pa.n = 0;
+    pa.off = 0;
+    uint64_t pbase_l0 = 0;   // lane 0: the previous append atomic's result
+    uint32_t ptotal = 0;     // wave-uniform: slots the previous iteration appended
+    uint64_t seen = 0;       // wave-uniform: the output count as of this wave's last append
+    for (;;) {
+        const uint64_t need = __ballot(!active);
+        if (need != 0 && wnext == wend && !exhausted) {
+            uint64_t b = 0;
+            if (lane == 0) b = atomicAdd(reinterpret_cast<unsigned long long*>(P.item_counter), kChunk);
+            b = __shfl(b, 0);
+            if (b + kChunk >= n_items) exhausted = true;
+            wnext = b < n_items ? b : n_items;
+            wend = b + kChunk < n_items ? b + kChunk : n_items;
+        }
+        const uint64_t avail = wend - wnext;
+        const uint32_t nneed = static_cast<uint32_t>(__popcll(need));
+        const uint32_t take = avail < nneed ? static_cast<uint32_t>(avail) : nneed;
+        const uint32_t rank = lane_prefix(need);
+        const uint64_t mine = wnext + rank;
+        wnext += take;
+        if (!active && rank < take) {
+            const uint64_t j = mine;
             if (SOURCES) {
-                p.X = pulse_source_state(P, P.src_begin + item, &p.batch);
+                p.X = pulse_source_state(P, P.src_begin + j, &p.batch);
                 p.x = 0.0;
                 p.t = 0.0;
                 p.tb = P.tb0;
                 c.sources++;
             } else {
-                p.x = P.in.x[item];
-                p.t = P.in.t[item];
-                p.X = P.in.X[item];
-                p.batch = P.in.batch[item];
-                p.tb = P.in.tb[item];
+                p.x = P.in.x[j];
+                p.t = P.in.t[j];
+                p.X = P.in.X[j];
+                p.batch = P.in.batch[j];
+                p.tb = P.in.tb[j];
             }
+            active = true;
+        }
+        if (__ballot(active) == 0 && wnext == wend && exhausted) break;
+        uint32_t n = 0;
+        if (active) {
             uint32_t draws = 0;
             n = pulse_particle(P, p, c, &draws);
-            note_stream(P, c, draws);
+            note_stream(P, c, draws);   // every particle has its own stream
+            if (n == 0) active = false;
         }
-        // wave prefix sum of n (n < 16) from one ballot per bit
-        uint32_t off = 0, total = 0;
-#pragma unroll
-        for (int bit = 0; bit < 4; ++bit) {
-            const uint64_t m = __ballot((n >> bit) & 1u);
-            off += lane_prefix(m) << bit;
-            total += static_cast<uint32_t>(__popcll(m)) << bit;
+        if (ptotal != 0) {
+            const uint64_t pbase = __shfl(pbase_l0, 0);
+            write_appends(P, pa, pbase);
+            seen = pbase + ptotal;
         }
-        uint64_t wbase = 0;
-        if (total != 0) {
-            if (lane == 0) wbase = atomicAdd(reinterpret_cast<unsigned long long*>(P.out_count), total);
-            wbase = __shfl(wbase, 0);
-        }
-        for (uint32_t k = 1; k <= n; ++k) {
-            const uint64_t o = wbase + off + (k - 1);
-            if (o < P.out_cap) {
-                P.out.x[o] = p.x;
-                P.out.t[o] = p.t;
-                P.out.X[o] = murmur_hash(k, p.X) & P.lcg.mask;
-                P.out.batch[o] = p.batch;
-                P.out.tb[o] = p.tb;
-            } else {
-                atomicOr(P.overflow, 1u);
-            }
+        // siblings (keys 2..n) go to the output bank and the line runs on
+        // with key 1, while this wave's view of the output count is within
+        // the budget; past it, a scattering banks all n and ends the line
+        uint32_t sib_total = 0;
+        wave_prefix16(n > 1 ? n - 1 : 0, &sib_total);
+        const bool keep = seen + sib_total <= P.cont_budget;
+        const uint32_t k0 = keep ? 2u : 1u;
+        const uint32_t npush = n >= k0 ? n - k0 + 1 : 0;
+        uint32_t total = 0;
+        const uint32_t off = wave_prefix16(npush, &total);
+        pa.x = p.x;
+        pa.t = p.t;
+        pa.Xp = p.X;
+        pa.batch = p.batch;
+        pa.tb = p.tb;
+        pa.k0 = k0;
+        pa.n = npush ? n : 0;
+        pa.off = off;
+        ptotal = total;
+        if (total != 0 && lane == 0)
+            pbase_l0 = atomicAdd(reinterpret_cast<unsigned long long*>(P.out_count), total);
+        if (n > 0) {
+            if (keep)
+                p.X = murmur_hash(1ull, p.X) & P.lcg.mask;   // the first emerging particle runs on here
+            else
+                active = false;
         }
     }
+    if (ptotal != 0) write_appends(P, pa, __shfl(pbase_l0, 0));
     flush_lane_counters<BLOCK>(P, c);
 }
 
@@ -308,24 +402,45 @@ static int device_cus() {
 }
 
 template <bool SOURCES, int BLOCK>
-static hipError_t launch_bank_b(const PulseParams& p, uint64_t items, hipStream_t st) {
-    uint64_t blocks = (items + BLOCK - 1) / BLOCK;
-    const uint64_t cap = static_cast<uint64_t>(device_cus()) * (2048 / BLOCK) * 2;
+static uint32_t bank_grid_b(uint64_t items) {
+    // resident blocks only: waves keep taking 256-item chunks, so a launch
+    // ends with one tail instead of one per wave
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_pulse_bank<SOURCES, BLOCK>),
+                                                     BLOCK, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    uint64_t blocks = (items + 4 * BLOCK - 1) / (4 * BLOCK);   // a 256-item chunk per wave at least
+    const uint64_t cap = static_cast<uint64_t>(device_cus()) * static_cast<uint64_t>(per_cu);
     if (blocks > cap) blocks = cap;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL((k_pulse_bank<SOURCES, BLOCK>), dim3(static_cast<unsigned>(blocks)), dim3(BLOCK), 0, st, p);
+    return static_cast<uint32_t>(blocks);
+}
+
+uint32_t pulse_bank_grid(bool sources, int block, uint64_t items) {
+    switch (block) {
+        case 64: return sources ? bank_grid_b<true, 64>(items) : bank_grid_b<false, 64>(items);
+        case 128: return sources ? bank_grid_b<true, 128>(items) : bank_grid_b<false, 128>(items);
+        case 512: return sources ? bank_grid_b<true, 512>(items) : bank_grid_b<false, 512>(items);
+        case 1024: return sources ? bank_grid_b<true, 1024>(items) : bank_grid_b<false, 1024>(items);
+        default: return sources ? bank_grid_b<true, 256>(items) : bank_grid_b<false, 256>(items);
+    }
+}
+
+template <bool SOURCES, int BLOCK>
+static hipError_t launch_bank_b(const PulseParams& p, uint32_t grid, hipStream_t st) {
+    hipLaunchKernelGGL((k_pulse_bank<SOURCES, BLOCK>), dim3(grid), dim3(BLOCK), 0, st, p);
     return hipGetLastError();
 }
 
-hipError_t launch_pulse_bank(const PulseParams& p, bool sources, int block, hipStream_t st) {
+hipError_t launch_pulse_bank(const PulseParams& p, bool sources, int block, uint32_t grid, hipStream_t st) {
     const uint64_t items = sources ? p.src_end - p.src_begin : p.n_in;
     if (items == 0) return hipSuccess;
     switch (block) {
-        case 64: return sources ? launch_bank_b<true, 64>(p, items, st) : launch_bank_b<false, 64>(p, items, st);
-        case 128: return sources ? launch_bank_b<true, 128>(p, items, st) : launch_bank_b<false, 128>(p, items, st);
-        case 512: return sources ? launch_bank_b<true, 512>(p, items, st) : launch_bank_b<false, 512>(p, items, st);
-        case 1024: return sources ? launch_bank_b<true, 1024>(p, items, st) : launch_bank_b<false, 1024>(p, items, st);
-        default: return sources ? launch_bank_b<true, 256>(p, items, st) : launch_bank_b<false, 256>(p, items, st);
+        case 64: return sources ? launch_bank_b<true, 64>(p, grid, st) : launch_bank_b<false, 64>(p, grid, st);
+        case 128: return sources ? launch_bank_b<true, 128>(p, grid, st) : launch_bank_b<false, 128>(p, grid, st);
+        case 512: return sources ? launch_bank_b<true, 512>(p, grid, st) : launch_bank_b<false, 512>(p, grid, st);
+        case 1024: return sources ? launch_bank_b<true, 1024>(p, grid, st) : launch_bank_b<false, 1024>(p, grid, st);
+        default: return sources ? launch_bank_b<true, 256>(p, grid, st) : launch_bank_b<false, 256>(p, grid, st);
     }
 }
 

@@ -52,12 +52,17 @@ struct PulseParams {
     uint64_t n_in;
     uint64_t* out_count;
     uint64_t out_cap;
+    uint64_t* item_counter;  // bank schedule: next input particle (taken 256 per wave)
+    uint64_t cont_budget;    // bank schedule: appends of continuing lines stay within this
     uint32_t* overflow;      // set if an append or a stack push found no room
     uint64_t* family_counter;
     PulseStackEntry* stack;  // family schedule: stack_depth entries per lane
 };
 
-hipError_t launch_pulse_bank(const PulseParams& p, bool sources, int block, hipStream_t st);
+// Bank launches: the grid (resident blocks, at most one 256-item chunk per
+// wave) is chosen first, so that the caller can size the output for it.
+uint32_t pulse_bank_grid(bool sources, int block, uint64_t items);
+hipError_t launch_pulse_bank(const PulseParams& p, bool sources, int block, uint32_t grid, hipStream_t st);
 uint32_t pulse_family_grid(int block);
 hipError_t launch_pulse_family(const PulseParams& p, int block, uint32_t grid, hipStream_t st);
 hipError_t launch_pulse_flux(const PulseParams& p, double* flux, hipStream_t st);

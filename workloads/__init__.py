@@ -193,6 +193,15 @@ def pulse(seeding=None, n_batches=1000, per_batch=1000, first_batch=0):
                         seeding=seeding or hash_seeding())
 
 
+def pulse_few_sources(seeding=None, n_sources=4096, t_end=60):
+    """Few sources run long (one batch, unit time bins up to t_end): the
+    population grows about e^{0.1 t} (400-fold at t = 60), so a whole
+    source family per lane leaves most of the GPU idle while every
+    particle of a generation can run in parallel under hash seeding."""
+    return PulseProblem(time_edges=np.arange(t_end + 1, dtype=np.float64), n_batches=1,
+                        per_batch=n_sources, seeding=seeding or hash_seeding())
+
+
 CONFIG_NAMES = {
     "small_slab": "20 mfp slab, c=0.9, 20 bins, 1e4 histories, FP64",
     "draw_counts": "2^26 streams, geometric draw counts (mean 64, seed 42)",
