@@ -103,6 +103,7 @@ def lib():
             L.orc_init_streams.argtypes = [P(_Lcg), P(_Seeding), u64, C.c_void_p]
             L.orc_seed_and_draw.argtypes = [P(_Lcg), P(_Seeding), u64, C.c_void_p, C.c_void_p, C.c_void_p]
             L.orc_uniform.argtypes = [u64, u32]; L.orc_uniform.restype = dbl
+            L.orc_uniforms.argtypes = [P(_Lcg), P(_Seeding), u64, u32, C.c_void_p, C.c_void_p]
             L.orc_ln.argtypes = [dbl]; L.orc_ln.restype = dbl
             L.orc_transport.argtypes = [P(_Problem), C.c_int, u64, u64, C.c_void_p, C.c_void_p, C.c_void_p]
             L.orc_transport.restype = C.c_int
@@ -203,6 +204,21 @@ def seed_and_draw(lcg, seeding, counts, states=None, threads=1):
 
     _parallel_ranges(n, threads, part)
     return chk
+
+
+def uniforms(lcg, seeding, n, k, states=None):
+    """[k, n] float64: row j holds every stream's (j+1)-th uniform.  With
+    seeding None the start states come from `states` (uint64, updated in
+    place to the final states)."""
+    L = _lcg_struct(lcg)
+    out = np.zeros((k, n), np.float64)
+    if seeding is None:
+        assert states is not None and states.dtype == np.uint64 and states.size == n
+        lib().orc_uniforms(C.byref(L), None, n, k, states.ctypes.data, out.ctypes.data)
+    else:
+        sd = _seeding_struct(seeding)
+        lib().orc_uniforms(C.byref(L), C.byref(sd), n, k, None, out.ctypes.data)
+    return out
 
 
 def _parallel_ranges(n, threads, fn):

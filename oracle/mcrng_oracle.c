@@ -184,6 +184,24 @@ double orc_uniform(uint64_t x, uint32_t m)
     return (double)(top + 1) * 0x1p-53;
 }
 
+/* Uniforms of n streams: stream i takes k LCG steps from its start state
+ * and its j-th output X (j = 1..k) gives out[(j-1) n + i] = orc_uniform(X)
+ * (draw-major).  With S == NULL the start states are read from state_inout;
+ * the final states go back to state_inout when it is not NULL. */
+void orc_uniforms(const orc_lcg *L, const orc_seeding *S, uint64_t n, uint32_t k,
+                  uint64_t *state_inout, double *out)
+{
+    for (uint64_t i = 0; i < n; ++i) {
+        uint64_t x = S ? orc_stream_start(L, S, i) : state_inout[i];
+        for (uint32_t j = 0; j < k; ++j) {
+            x = orc_lcg_next(x, L->g, L->c, L->m);
+            out[(uint64_t)j * n + i] = orc_uniform(x, L->m);
+        }
+        if (state_inout)
+            state_inout[i] = x;
+    }
+}
+
 /* ------------------------------------------------------------------ */
 /* Natural logarithm with a fixed operation sequence (reading; the paper
  * does not fix the flight-sampling arithmetic, and bit-exact tallies need

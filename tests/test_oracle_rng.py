@@ -14,7 +14,10 @@
 * eqs. (3), (4): sharding and group-key composition of hash seeds.
 * logarithm: within 1.25 ulp of mpmath; exact at 1; powers of two.
 * u128 -> double: equals Python's correctly rounded int -> float.
+* uniforms: every stream's outputs recomputed with Python integers; range
+  and first two moments.
 """
+import math
 import random
 
 import mpmath
@@ -272,6 +275,42 @@ def test_uniform_mapping(orc):
     for _ in range(1000):
         x = rnd.getrandbits(63)
         assert orc.uniform(x) * 2.0 ** 53 == (x >> 10) + 1
+
+
+def test_uniforms_brute_force(orc):
+    """Row j of the uniforms is every stream's (j+1)-th output mapped to
+    (0, 1]: recomputed with Python integers from each stream's start state
+    (the LCG step written out as g x + 1 mod 2^63, the mapping as
+    ((x >> 10) + 1) 2^-53), for both seedings and the load mode."""
+    lcg = W.Lcg()
+    n, k = 37, 9
+    for sd in (W.hash_seeding(first_index=5), W.stride_seeding(first_index=11)):
+        u = orc.uniforms(lcg, sd, n, k)
+        assert u.shape == (k, n)
+        for i in range(n):
+            x = orc.stream_start(lcg, sd, i)
+            for j in range(k):
+                x = (G * x + 1) & MASK63
+                assert u[j, i] == ((x >> 10) + 1) * 2.0 ** -53
+    st = np.array([orc.stream_start(lcg, W.hash_seeding(), i) for i in range(n)], np.uint64)
+    st0 = st.copy()
+    u = orc.uniforms(lcg, None, n, k, st)
+    assert np.array_equal(u, orc.uniforms(lcg, W.hash_seeding(), n, k))
+    for i in range(n):
+        x = int(st0[i])
+        for _ in range(k):
+            x = (G * x + 1) & MASK63
+        assert int(st[i]) == x
+
+
+def test_uniforms_moments(orc):
+    """(0, 1], mean 1/2 and variance 1/12 within 5 standard errors over
+    2^16 x 8 values."""
+    u = orc.uniforms(W.Lcg(), W.hash_seeding(), 1 << 16, 8).ravel()
+    assert u.min() > 0.0 and u.max() <= 1.0
+    n = u.size
+    assert abs(u.mean() - 0.5) < 5 * math.sqrt(1 / 12 / n)
+    assert abs(u.var() - 1 / 12) < 5 * math.sqrt(1 / 180 / n)
 
 
 def test_ln_accuracy_vs_mpmath(orc):
