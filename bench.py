@@ -10,6 +10,8 @@ value = RNG draws per second (the draws of the whole step / step time).
 
 Also reported, each timed separately after the headline loop:
   stride        the same workload with stride seeding (X_0 = 1, Q = 152917)
+  uniforms      2^26 hash-seeded streams x 16 uniforms written to HBM (GB/s
+                against the 8 TB/s peak)
   transport     the 1e8-history long-chain slab (50 mfp, c = 0.99, 200 bins,
                 64 batches): histories/s, draws/s, events/s for hash FP64,
                 hash FP32-flight and stride FP64 (kernel time, HIP events)
@@ -78,6 +80,40 @@ def draw_workload(M, W, torch, dev, kind, steps, warmup, d_count, n, total_draws
     kern_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
     return {"ms_per_step": ms_step, "kernel_ms": kern_ms, "draws_per_s": total_draws / (ms_step * 1e-3),
             "chk": chk}
+
+
+def uniforms_leg(M, W, torch, dev, lcg, n, k, warmup, reps):
+    """mcrng_uniforms over n hash-seeded streams, k numbers each (draw-major
+    [k, n] float64): bound by the 8 bytes written per number."""
+    u = torch.empty((k, n), dtype=torch.float64, device=dev)
+    sd = W.hash_seeding()
+    for _ in range(warmup):
+        M.uniforms(lcg, sd, u)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        M.uniforms(lcg, sd, u)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = 8.0 * n * k
+    # write-only reference on the same buffer: torch's fill kernel
+    e0.record()
+    for _ in range(reps):
+        u.fill_(0.5)
+    e1.record()
+    torch.cuda.synchronize()
+    fill_ms = e0.elapsed_time(e1) / reps
+    M.uniforms(lcg, sd, u)
+    torch.cuda.synchronize()
+    out = {"streams": n, "numbers_per_stream": k, "ms": ms, "numbers_per_s": n * k / (ms * 1e-3),
+           "hbm_gb_per_s": nbytes / (ms * 1e-3) / 1e9, "frac_of_hbm_peak": nbytes / (ms * 1e-3) / 8e12,
+           "fill_reference_gb_per_s": nbytes / (fill_ms * 1e-3) / 1e9,
+           "range_ok": bool(float(u.min()) > 0.0 and float(u.max()) <= 1.0)}
+    del u
+    torch.cuda.empty_cache()
+    return out
 
 
 def spot_check(oracle, W, lcg, kind, counts, chk_np, k=256):
@@ -216,6 +252,9 @@ def main():
         torch.cuda.synchronize()
         del src_t, dst_t
 
+    log("uniforms: 2^26 streams x 16 numbers")
+    uni = uniforms_leg(M, W, torch, dev, lcg, n, 16, args.warmup, max(3, args.steps // 4))
+
     import oracle
     ok_h = spot_check(oracle, W, lcg, "hash", counts, hsh["chk"].view(torch.int64).cpu().numpy().view(np.uint64))
     ok_s = spot_check(oracle, W, lcg, "stride", counts, strd["chk"].view(torch.int64).cpu().numpy().view(np.uint64))
@@ -249,6 +288,7 @@ def main():
                            "int_valu_frac": ops_stride / (strd["kernel_ms"] * 1e-3) / INT_VALU_PEAK,
                            "hash_over_stride": strd["ms_per_step"] / hsh["ms_per_step"]},
         "verified_vs_oracle": {"hash_sampled_streams": ok_h, "stride_sampled_streams": ok_s},
+        "uniforms": uni,
         "roofline": roofline,
     }
 

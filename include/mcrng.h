@@ -95,6 +95,18 @@ int mcrng_init_streams(const mcrng_lcg *lcg, const mcrng_seeding *seeding, uint6
 int mcrng_draw(const mcrng_lcg *lcg, const mcrng_seeding *seeding, uint64_t n,
                const uint32_t *d_count, uint64_t *d_state, uint64_t *d_checksum, void *stream);
 
+/* Uniform random numbers.  Stream i takes k LCG steps (eq. (1)) and its
+ * j-th output X (j = 1..k) gives
+ *   d_u[(j - 1) n + i] = ((X >> (m - 53)) + 1) 2^-53,
+ * an exact double in (0, 1] (the mapping every transport draw uses).  The
+ * layout is draw-major: row j - 1 holds the j-th number of every stream.
+ * Start states as in mcrng_draw: from the seeding (d_state may be NULL,
+ * else it receives the final states) or, with seeding == NULL, from d_state
+ * (updated in place).  Requires m >= 53.  d_u: k x n doubles.  n = 0 or
+ * k = 0 is a no-op. */
+int mcrng_uniforms(const mcrng_lcg *lcg, const mcrng_seeding *seeding, uint64_t n, uint32_t k,
+                   uint64_t *d_state, double *d_u, void *stream);
+
 /* ------------------------------------------------------------------ */
 /* Slab transport                                                      */
 /* ------------------------------------------------------------------ */

@@ -4,7 +4,7 @@ transport: Python side of libmcrng.so (include/mcrng.h).
 Paper: Cuneo & Variansyah, "An Alternative to Stride-Based RNG for Monte
 Carlo Transport" (arXiv 2403.06362).
 
-The entry points mirror the C ABI: init_streams, draw, Context.run_histories,
+The entry points mirror the C ABI: init_streams, draw, uniforms, Context.run_histories,
 Context.reduce_tallies, Context.run_pulse (plus Context.autotune).  Tensors
 are torch device tensors; the library does all the arithmetic.
 `transport()` and `pulse()` are convenience wrappers that allocate the
@@ -13,10 +13,10 @@ output tensors.
 from ._binding import (  # noqa: F401
     DIAG_NAMES, EXPORTS, FP32, FP64, NDIAG, PULSE_AUTO, PULSE_BANK, PULSE_DIAG_NAMES, PULSE_FAMILY, SCHED_EVENT,
     SCHED_HISTORY, Context, McrngError, PulseOpts, RunOpts, draw, init_streams, lib, make_opts, make_pulse_opts,
-    tally_bins,
+    tally_bins, uniforms,
 )
 
-__all__ = ["init_streams", "draw", "Context", "RunOpts", "make_opts", "tally_bins", "transport", "pulse",
+__all__ = ["init_streams", "draw", "uniforms", "Context", "RunOpts", "make_opts", "tally_bins", "transport", "pulse",
            "PulseOpts", "make_pulse_opts", "McrngError", "lib", "FP64", "FP32", "SCHED_HISTORY", "SCHED_EVENT",
            "PULSE_AUTO", "PULSE_BANK", "PULSE_FAMILY", "NDIAG", "DIAG_NAMES", "PULSE_DIAG_NAMES"]
 

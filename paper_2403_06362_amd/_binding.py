@@ -30,7 +30,7 @@ PULSE_DIAG_NAMES = ("sources", "collisions", "tallied", "scatters", "absorbed", 
 # every symbol include/mcrng.h declares
 EXPORTS = ("mcrng_init_streams", "mcrng_draw", "mcrng_ctx_create", "mcrng_ctx_destroy",
            "mcrng_tally_bins", "mcrng_run_histories", "mcrng_reduce_tallies", "mcrng_autotune",
-           "mcrng_last_run_ms", "mcrng_last_error", "mcrng_version", "mcrng_run_pulse")
+           "mcrng_last_run_ms", "mcrng_last_error", "mcrng_version", "mcrng_run_pulse", "mcrng_uniforms")
 
 
 class McrngError(RuntimeError):
@@ -106,6 +106,7 @@ def lib():
         L.mcrng_last_error.restype = C.c_char_p
         L.mcrng_version.argtypes = []
         L.mcrng_run_pulse.argtypes = [vp, P(Lcg), P(PulseProblem), P(PulseOpts), vp, vp, vp, vp]
+        L.mcrng_uniforms.argtypes = [P(Lcg), P(Seeding), u64, u32, vp, vp, vp]
         for name in EXPORTS:
             if name not in ("mcrng_tally_bins", "mcrng_last_run_ms", "mcrng_last_error"):
                 getattr(L, name).restype = C.c_int
@@ -232,6 +233,19 @@ def make_pulse_opts(**kw):
         if v is not None:
             setattr(o, k, int(v))
     return o
+
+
+def uniforms(lcg, seeding, d_u, d_state=None, stream=None):
+    """mcrng_uniforms: d_u is a float64 tensor [k, n] (row j holds every
+    stream's (j+1)-th number)."""
+    import torch
+    if d_u.dim() != 2:
+        raise ValueError("d_u must be a [k, n] tensor")
+    k, n = int(d_u.shape[0]), int(d_u.shape[1])
+    L = make_lcg(lcg)
+    S = None if seeding is None else C.byref(make_seeding(seeding))
+    return _check(lib().mcrng_uniforms(C.byref(L), S, n, k, _ptr(d_state, torch.uint64, n, "d_state"),
+                                       _ptr(d_u, torch.float64, n * k, "d_u"), _stream(stream)))
 
 
 def tally_bins(problems):

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmcrng.so")
-SOURCES = ["rng_kernels.hip", "transport.hip", "events.hip", "pulse.hip", "api.hip"]
+SOURCES = ["rng_kernels.hip", "uniforms.hip", "transport.hip", "events.hip", "pulse.hip", "api.hip"]
 
 # -ffp-contract=off: no fused multiply-add anywhere (the transport arithmetic
 #   is a fixed sequence of separately rounded IEEE operations).

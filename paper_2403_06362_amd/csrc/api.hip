@@ -16,6 +16,7 @@
 
 #include "internal.hpp"
 #include "pulse.hpp"
+#include "uniforms.hpp"
 #include "mcrng.h"
 
 using namespace mcrng;
@@ -920,6 +921,29 @@ extern "C" int mcrng_autotune(mcrng_ctx* ctx, const mcrng_lcg* lcg, const mcrng_
     *best = cur;
     if (best_ms) *best_ms = cur_ms;
     return MCRNG_OK;
+}
+
+// ------------------------------------------------------------ uniforms
+
+extern "C" int mcrng_uniforms(const mcrng_lcg* lcg, const mcrng_seeding* seeding, uint64_t n, uint32_t k,
+                              uint64_t* d_state, double* d_u, void* stream) {
+    LcgDev L;
+    int rc = validate_lcg(lcg, 53, &L);
+    if (rc < 0) return rc;
+    if (n == 0 || k == 0) return MCRNG_OK;
+    if (!d_u) return fail(MCRNG_EINVAL, "d_u is NULL");
+    if (!seeding && !d_state) return fail(MCRNG_EINVAL, "d_state is required when seeding is NULL");
+    if (n >> 40) return fail(MCRNG_EINVAL, "n = %llu too large", (unsigned long long)n);
+    SeedDev S;
+    std::memset(&S, 0, sizeof S);
+    int mode = SEED_LOAD;
+    if (seeding) {
+        rc = build_seed(L, seeding, n, &S);
+        if (rc < 0) return rc;
+        mode = S.kind;
+    }
+    HIP_TRY(launch_uniforms(L, S, mode, n, k, d_state, d_u, static_cast<hipStream_t>(stream)));
+    return rc;
 }
 
 // ------------------------------------------------------------ pulse problem

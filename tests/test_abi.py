@@ -94,3 +94,17 @@ def test_pulse_host_validation_without_gpu(M):
     assert rc == B.EINVAL and "hash" in msg
     rc, msg = call(good, block=96)
     assert rc == B.EINVAL and "block" in msg
+
+
+def test_uniforms_host_validation_without_gpu(M):
+    from paper_2403_06362_amd import _binding as B
+    import workloads as W
+    lib = B.lib()
+    S = B.make_seeding(W.hash_seeding())
+    short = B.make_lcg(W.Lcg(m=40))
+    assert lib.mcrng_uniforms(C.byref(short), C.byref(S), 8, 2, None, C.c_void_p(16), None) == B.EINVAL
+    assert "m" in lib.mcrng_last_error().decode()
+    L = B.make_lcg(W.Lcg())
+    assert lib.mcrng_uniforms(C.byref(L), C.byref(S), 8, 2, None, None, None) == B.EINVAL
+    assert lib.mcrng_uniforms(C.byref(L), None, 8, 2, None, C.c_void_p(16), None) == B.EINVAL
+    assert lib.mcrng_uniforms(C.byref(L), C.byref(S), 0, 2, None, None, None) == B.OK

@@ -138,3 +138,62 @@ def test_stride_wrap_warning(M, orc):
     rc = M.init_streams(lcg, sd, 2000, out)
     assert rc == 1
     assert np.array_equal(u64_np(out), orc.init_streams(lcg, sd, 2000))
+
+
+# ------------------------------------------------------------ uniforms
+
+def _uniforms(M, sd, n, k, state=None):
+    import torch
+    u = torch.empty((k, n), dtype=torch.float64, device="cuda:0")
+    M.uniforms(LCG, sd, u, state)
+    torch.cuda.synchronize()
+    return u.cpu().numpy()
+
+
+@pytest.mark.parametrize("kind", ["hash", "stride"])
+@pytest.mark.parametrize("n,k", [(1, 1), (63, 7), (1000, 64), (4099, 3)])
+def test_uniforms_parity(M, orc, kind, n, k):
+    sd = W.hash_seeding(9) if kind == "hash" else W.stride_seeding(9)
+    say("uniforms", kind, n, k)
+    assert np.array_equal(_uniforms(M, sd, n, k), orc.uniforms(LCG, sd, n, k))
+
+
+def test_uniforms_load_mode_and_final_states(M, orc):
+    """Start states loaded from HBM give the seeded run's numbers; the final
+    states equal those mcrng_draw leaves after the same number of steps."""
+    n, k = 5003, 11
+    sd = W.stride_seeding()
+    st = _empty_u64(n)
+    M.init_streams(LCG, sd, n, st)
+    u = _uniforms(M, None, n, k, st)
+    assert np.array_equal(u, orc.uniforms(LCG, sd, n, k))
+    st2 = _empty_u64(n)
+    chk = _empty_u64(n)
+    M.draw(LCG, sd, to_dev_u32(np.full(n, k)), chk, st2)
+    assert np.array_equal(u64_np(st), u64_np(st2))
+
+
+def test_uniforms_full_size_sampled(M, orc):
+    """2^26 streams x 16 numbers (8.6 GB): sampled streams equal the oracle's,
+    and the range is (0, 1]."""
+    import torch
+    n, k = 1 << 26, 16
+    say("uniforms full", n, k)
+    u = torch.empty((k, n), dtype=torch.float64, device="cuda:0")
+    M.uniforms(LCG, W.hash_seeding(), u)
+    torch.cuda.synchronize()
+    assert float(u.min()) > 0.0 and float(u.max()) <= 1.0
+    idx = np.concatenate([np.arange(8), np.arange(n - 8, n), np.random.default_rng(3).integers(0, n, 300)])
+    got = u[:, torch.from_numpy(idx).to("cuda:0")].cpu().numpy()
+    for c, i in enumerate(idx):
+        ref = orc.uniforms(LCG, W.hash_seeding(int(i)), 1, k)[:, 0]
+        assert np.array_equal(got[:, c], ref), i
+    del u
+    torch.cuda.empty_cache()
+
+
+def test_uniforms_rejects_short_generators(M):
+    import torch
+    u = torch.empty((2, 8), dtype=torch.float64, device="cuda:0")
+    with pytest.raises(M.McrngError):
+        M.uniforms(W.Lcg(m=40), W.hash_seeding(), u)
