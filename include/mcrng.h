@@ -286,8 +286,7 @@ enum { MCRNG_PULSE_AUTO = 0, MCRNG_PULSE_BANK = 1, MCRNG_PULSE_FAMILY = 2 };
  *                flight per launch from a particle bank, in any order, the
  *                emerging particles going to the next generation's bank;
  *                MCRNG_PULSE_FAMILY: one source family per lane, depth
- *                first; AUTO: family, except for hash seeding with fewer
- *                sources than the GPU holds lanes (the bank keeps it busy)
+ *                first; AUTO: bank for hash seeding, family for stride
  *   block        threads per block: 64, 128, 256, 512 or 1024
  *   stack_depth  family schedule: stack entries per lane (default 128; an
  *                entry holds the siblings of one scattering on the current

@@ -1019,13 +1019,9 @@ extern "C" int mcrng_run_pulse(mcrng_ctx* ctx, const mcrng_lcg* lcg, const mcrng
     if (!d_counts) return fail(MCRNG_EINVAL, "d_counts is NULL");
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (o.schedule == MCRNG_PULSE_AUTO) {
-        // families need about one source per resident lane to fill the GPU
-        // and even out their sizes; with fewer sources only the particle
-        // bank (hash seeding) keeps the GPU busy
-        const uint64_t lanes = static_cast<uint64_t>(pulse_family_grid(static_cast<int>(o.block))) * o.block;
-        o.schedule = (hash && n_src < lanes) ? MCRNG_PULSE_BANK : MCRNG_PULSE_FAMILY;
-    }
+    // hash seeding lets every particle run anywhere: the bank; stride
+    // families must run depth first on one lane
+    if (o.schedule == MCRNG_PULSE_AUTO) o.schedule = hash ? MCRNG_PULSE_BANK : MCRNG_PULSE_FAMILY;
 
     PulseParams pp;
     std::memset(&pp, 0, sizeof pp);
@@ -1065,6 +1061,9 @@ extern "C" int mcrng_run_pulse(mcrng_ctx* ctx, const mcrng_lcg* lcg, const mcrng
     if ((rc = ensure(ctx->pulse_diag, kNDiag * sizeof(uint64_t), st)) < 0) return rc;
     pp.t_edges = static_cast<const double*>(ctx->pulse_tedges.p);
     pp.counts = d_counts;
+    const uint64_t n_counters = static_cast<uint64_t>(P->n_batches) * P->n_time_bins;
+    pp.n_counters = static_cast<uint32_t>(std::min<uint64_t>(n_counters, 0xffffffffu));
+    pp.lds_tally = n_counters <= kPulseLdsCounters ? 1u : 0u;
     pp.diag = static_cast<uint64_t*>(ctx->pulse_diag.p);
     // misc words: out_count, item_counter (reset per bank launch), family_counter, overflow
     uint64_t* misc = static_cast<uint64_t*>(ctx->pulse_misc.p);
@@ -1083,7 +1082,7 @@ extern "C" int mcrng_run_pulse(mcrng_ctx* ctx, const mcrng_lcg* lcg, const mcrng
         // particles (their first emerging particles inline) and banks the
         // siblings for the next launch.  Capacity per launch: the continue
         // budget (2 per input particle), n_max per input particle, and one
-        // iteration's appends per wave.
+        // LDS stage plus one iteration's appends per wave.
         // Sources go in chunks so that the banks stay within tens of GB.
         const uint64_t chunk = 1ull << 23;
         for (uint64_t c0 = 0; c0 < n_src; c0 += chunk) {
@@ -1092,10 +1091,10 @@ extern "C" int mcrng_run_pulse(mcrng_ctx* ctx, const mcrng_lcg* lcg, const mcrng
             uint64_t n = c1 - c0, in_cap = 0;
             bool sources = true;
             while (n > 0) {
-                const uint32_t grid = pulse_bank_grid(sources, static_cast<int>(o.block), n);
+                const uint32_t grid = pulse_bank_grid(pp, sources, static_cast<int>(o.block), n);
                 const uint64_t waves = static_cast<uint64_t>(grid) * o.block / 64;
                 const uint64_t budget = 2 * n;
-                const uint64_t slack = (waves + 1) * 64 * (n_max > 1 ? n_max - 1 : 0);
+                const uint64_t slack = (waves + 1) * (256 + 64 * static_cast<uint64_t>(n_max));
                 const uint64_t ocap = budget + static_cast<uint64_t>(n_max) * n + slack;
                 if ((rc = ensure(ctx->pulse_bank[nxt], ocap * 32, st, 8)) < 0) return rc;
                 pp.src_begin = c0;

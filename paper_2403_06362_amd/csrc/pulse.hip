@@ -17,13 +17,13 @@
 //       input particles (or sources) at a time through one atomic and hands
 //       them to its idle lanes; a lane runs each one's line of descent: at a
 //       scattering it keeps the first emerging particle in registers and
-//       appends its siblings to the output bank (wave prefix sum, one atomic
-//       per wave, written one iteration later so that the next flight hides
-//       the atomic) while the wave's last view of the output count is within
-//       the launch's budget; past it, a scattering appends all n particles
-//       and ends the line.  Appends are thus at most budget + n_max per input
-//       particle + one iteration's appends per wave and one more (the view is
-//       one iteration old), which the output capacity covers.
+//       banks its siblings (staged per wave in LDS, copied to the output bank
+//       with one atomic per flush) while the wave's view of the output count
+//       (its last flush plus its staged entries) is within the launch's
+//       budget; past it, a scattering banks all n particles and ends the
+//       line.  Appends are thus at most budget + n_max per input particle +
+//       one stage and one iteration's appends per wave (the view lags by at
+//       most a stage), which the output capacity covers.
 //   k_pulse_family            one source family per lane (taken from a
 //       global counter, one atomic per wave), walked depth first with a
 //       per-lane stack in HBM; a stack entry holds the siblings still to
@@ -53,9 +53,11 @@ enum : uint32_t { PULSE_CENSUS = 0, PULSE_ABSORBED = 1, PULSE_SCATTERED = 2 };
 // Runs the particle from its start to its end.  Returns PULSE_CENSUS,
 // PULSE_ABSORBED or PULSE_SCATTERED, with *n the number of particles
 // emerging (0 unless it scattered); p then holds the collision site and the
-// state after the particle's draws.  *draws counts the numbers drawn.
+// state after the particle's draws.  *draws counts the numbers drawn; a
+// scored collision sets *tally to its counter index (the caller adds it
+// with wave_tally).
 __device__ __forceinline__ uint32_t pulse_flight(const PulseParams& P, PParticle& p, PulseLane& c,
-                                                 uint32_t* draws, uint32_t* n) {
+                                                 uint32_t* draws, uint32_t* n, int64_t* tally) {
     const LcgDev& L = P.lcg;
     *n = 0;
     p.X = lcg_next(L, p.X);
@@ -72,9 +74,7 @@ __device__ __forceinline__ uint32_t pulse_flight(const PulseParams& P, PParticle
     while (p.tb + 1 < static_cast<int32_t>(P.n_time_bins) && P.t_edges[p.tb + 1] <= p.t) p.tb++;
     c.collisions++;
     if (p.tb >= 0 && P.x_lo <= p.x && p.x <= P.x_hi) {
-        atomicAdd(reinterpret_cast<unsigned long long*>(P.counts) +
-                      static_cast<size_t>(p.batch) * P.n_time_bins + p.tb,
-                  1ull);
+        *tally = static_cast<int64_t>(p.batch) * P.n_time_bins + p.tb;
         c.tallied++;
     }
     p.X = lcg_next(L, p.X);
@@ -89,9 +89,9 @@ __device__ __forceinline__ uint32_t pulse_flight(const PulseParams& P, PParticle
 // pulse_flight plus the end counters (kept out of the branches above so that
 // the compiler does not fold them into an indexed array in scratch memory).
 __device__ __forceinline__ uint32_t pulse_particle(const PulseParams& P, PParticle& p, PulseLane& c,
-                                                   uint32_t* draws) {
+                                                   uint32_t* draws, int64_t* tally) {
     uint32_t n = 0;
-    const uint32_t r = pulse_flight(P, p, c, draws, &n);
+    const uint32_t r = pulse_flight(P, p, c, draws, &n, tally);
     c.census += static_cast<uint64_t>(r == PULSE_CENSUS);
     c.absorbed += static_cast<uint64_t>(r == PULSE_ABSORBED);
     c.scatters += static_cast<uint64_t>(r == PULSE_SCATTERED);
@@ -115,6 +115,21 @@ __device__ __forceinline__ void note_stream(const PulseParams& P, PulseLane& c, 
     c.draws += draws;
     if (draws > c.max_draws) c.max_draws = draws;
     if (!P.hash && draws > P.stride_q) c.over_stride++;
+}
+
+template <int BLOCK>
+__device__ __forceinline__ void tally_lds_begin(const PulseParams& P, unsigned long long* lds_counts) {
+    if (P.lds_tally)
+        for (uint32_t i = threadIdx.x; i < P.n_counters; i += BLOCK) lds_counts[i] = 0;
+    __syncthreads();
+}
+
+template <int BLOCK>
+__device__ __forceinline__ void tally_lds_end(const PulseParams& P, const unsigned long long* lds_counts) {
+    if (!P.lds_tally) return;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < P.n_counters; i += BLOCK)
+        if (lds_counts[i] != 0) atomicAdd(reinterpret_cast<unsigned long long*>(P.counts) + i, lds_counts[i]);
 }
 
 // Block-level sum of the lane counters into P.diag (one atomic per word
@@ -149,6 +164,31 @@ __device__ __forceinline__ uint32_t lane_prefix(uint64_t mask) {
                                      __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
 }
 
+// Adds the wave's scored collisions (tally = counter index, or -1).  When
+// all counters fit in LDS (P.lds_tally) each block counts into its own copy
+// and adds it to HBM once at its end (tally_lds_begin / tally_lds_end);
+// otherwise one 64-bit HBM atomic per distinct counter of the wave.  Either
+// way same-address atomics from every wave of the GPU, which serialise, are
+// avoided.  Called by the whole wave.
+__device__ __forceinline__ void wave_tally(const PulseParams& P, int64_t tally, uint32_t lane,
+                                           unsigned long long* lds_counts) {
+    if (P.lds_tally) {
+        // the block's own copy of every counter (added to HBM at the end)
+        if (tally >= 0) atomicAdd(lds_counts + tally, 1ull);
+        return;
+    }
+    uint64_t pending = __ballot(tally >= 0);
+    while (pending != 0) {
+        const int leader = __ffsll(static_cast<long long>(pending)) - 1;
+        const int64_t key = __shfl(tally, leader);
+        const uint64_t same = __ballot(tally == key);
+        if (lane == static_cast<uint32_t>(leader))
+            atomicAdd(reinterpret_cast<unsigned long long*>(P.counts) + key,
+                      static_cast<unsigned long long>(__popcll(same)));
+        pending &= ~same;
+    }
+}
+
 // ------------------------------------------------------------ bank schedule
 
 // Wave prefix sum of per-lane values v < 16 (one ballot per bit).
@@ -164,54 +204,68 @@ __device__ __forceinline__ uint32_t wave_prefix16(uint32_t v, uint32_t* total) {
     return off;
 }
 
-// Appends of one lane waiting for the wave's atomic: keys k0..n of the
-// particles emerging at (x, t) from the parent state X_p.
-struct PendingAppend {
-    double x, t;
-    uint64_t Xp;
-    uint32_t batch;
-    int32_t tb;
-    uint32_t k0, n, off;
+// Per-wave staging of appends in LDS: a wave collects the particles it
+// banks here and copies them to the output bank with one atomic per
+// flush, so the output counter sees one atomic per few iterations of a
+// wave instead of one per iteration.
+template <int BLOCK>
+struct BankStage {
+    static constexpr uint32_t kCap = (BLOCK >= 1024) ? 128u : 256u;   // 32 B per entry; 64 KiB per block
+    double x[kCap];
+    double t[kCap];
+    uint64_t X[kCap];
+    uint32_t batch[kCap];
+    int32_t tb[kCap];
 };
 
-__device__ __forceinline__ void write_appends(const PulseParams& P, const PendingAppend& a, uint64_t base) {
-    for (uint32_t k = a.k0; k <= a.n; ++k) {
-        const uint64_t o = base + a.off + (k - a.k0);
-        if (o < P.out_cap) {
-            P.out.x[o] = a.x;
-            P.out.t[o] = a.t;
-            P.out.X[o] = murmur_hash(k, a.Xp) & P.lcg.mask;
-            P.out.batch[o] = a.batch;
-            P.out.tb[o] = a.tb;
-        } else {
-            atomicOr(P.overflow, 1u);
-        }
+__device__ __forceinline__ void bank_store(const PulseParams& P, uint64_t o, double x, double t, uint64_t X,
+                                           uint32_t batch, int32_t tb) {
+    if (o < P.out_cap) {
+        P.out.x[o] = x;
+        P.out.t[o] = t;
+        P.out.X[o] = X;
+        P.out.batch[o] = batch;
+        P.out.tb[o] = tb;
+    } else {
+        atomicOr(P.overflow, 1u);
     }
+}
+
+// Copies the wave's staged entries to the output bank (one atomic) and
+// returns the output count just after them.
+template <int BLOCK>
+__device__ __forceinline__ uint64_t bank_flush(const PulseParams& P, BankStage<BLOCK>& S, uint32_t count,
+                                               uint32_t lane) {
+    __builtin_amdgcn_wave_barrier();
+    uint64_t base = 0;
+    if (lane == 0) base = atomicAdd(reinterpret_cast<unsigned long long*>(P.out_count), count);
+    base = __shfl(base, 0);
+    for (uint32_t i = lane; i < count; i += 64) bank_store(P, base + i, S.x[i], S.t[i], S.X[i], S.batch[i], S.tb[i]);
+    __builtin_amdgcn_wave_barrier();
+    return base + count;
 }
 
 template <bool SOURCES, int BLOCK>
 __global__ void __launch_bounds__(BLOCK) k_pulse_bank(PulseParams P) {
     constexpr uint32_t kChunk = 256;   // items a wave takes per atomic
+    using Stage = BankStage<BLOCK>;
+    __shared__ Stage stage[BLOCK / 64];
+    extern __shared__ unsigned long long lds_counts[];
+    tally_lds_begin<BLOCK>(P, lds_counts);
     PulseLane c;
     const uint64_t n_items = SOURCES ? P.src_end - P.src_begin : P.n_in;
     const uint32_t lane = threadIdx.x & 63u;
+    Stage& S = stage[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)];
     uint64_t wnext = 0, wend = 0;      // wave-uniform: the wave's unassigned items [wnext, wend)
     bool exhausted = false;            // wave-uniform
+    uint32_t staged = 0;               // wave-uniform: entries in S
+    uint64_t seen = 0;                 // wave-uniform: output count after this wave's last flush
     PParticle p;
     p.x = p.t = 0.0;
     p.X = 0;
     p.tb = -1;
     p.batch = 0;
     bool active = false;
-    // the previous iteration's appends: written once its atomic has returned,
-    // after this iteration's flight (so the flight hides the atomic's latency)
-    PendingAppend pa;
-    pa.k0 = 1;
-    pa.n = 0;
-    pa.off = 0;
-    uint64_t pbase_l0 = 0;   // lane 0: the previous append atomic's result
-    uint32_t ptotal = 0;     // wave-uniform: slots the previous iteration appended
-    uint64_t seen = 0;       // wave-uniform: the output count as of this wave's last append
     for (;;) {
         const uint64_t need = __ballot(!active);
         if (need != 0 && wnext == wend && !exhausted) {
@@ -247,38 +301,50 @@ __global__ void __launch_bounds__(BLOCK) k_pulse_bank(PulseParams P) {
         }
         if (__ballot(active) == 0 && wnext == wend && exhausted) break;
         uint32_t n = 0;
+        int64_t tally = -1;
         if (active) {
             uint32_t draws = 0;
-            n = pulse_particle(P, p, c, &draws);
+            n = pulse_particle(P, p, c, &draws, &tally);
             note_stream(P, c, draws);   // every particle has its own stream
             if (n == 0) active = false;
         }
-        if (ptotal != 0) {
-            const uint64_t pbase = __shfl(pbase_l0, 0);
-            write_appends(P, pa, pbase);
-            seen = pbase + ptotal;
-        }
-        // siblings (keys 2..n) go to the output bank and the line runs on
-        // with key 1, while this wave's view of the output count is within
-        // the budget; past it, a scattering banks all n and ends the line
+        wave_tally(P, tally, lane, lds_counts);
+        // siblings (keys 2..n) are banked and the line runs on with key 1
+        // while this wave's view of the output count (last flush + staged)
+        // is within the budget; past it, a scattering banks all n and ends
+        // the line
         uint32_t sib_total = 0;
         wave_prefix16(n > 1 ? n - 1 : 0, &sib_total);
-        const bool keep = seen + sib_total <= P.cont_budget;
+        const bool keep = seen + staged + sib_total <= P.cont_budget;
         const uint32_t k0 = keep ? 2u : 1u;
         const uint32_t npush = n >= k0 ? n - k0 + 1 : 0;
         uint32_t total = 0;
         const uint32_t off = wave_prefix16(npush, &total);
-        pa.x = p.x;
-        pa.t = p.t;
-        pa.Xp = p.X;
-        pa.batch = p.batch;
-        pa.tb = p.tb;
-        pa.k0 = k0;
-        pa.n = npush ? n : 0;
-        pa.off = off;
-        ptotal = total;
-        if (total != 0 && lane == 0)
-            pbase_l0 = atomicAdd(reinterpret_cast<unsigned long long*>(P.out_count), total);
+        if (total != 0) {
+            if (staged + total > Stage::kCap) {
+                seen = bank_flush<BLOCK>(P, S, staged, lane);
+                staged = 0;
+            }
+            if (total <= Stage::kCap) {
+                for (uint32_t k = k0; k <= n; ++k) {
+                    const uint32_t e = staged + off + (k - k0);
+                    S.x[e] = p.x;
+                    S.t[e] = p.t;
+                    S.X[e] = murmur_hash(k, p.X) & P.lcg.mask;
+                    S.batch[e] = p.batch;
+                    S.tb[e] = p.tb;
+                }
+                staged += total;
+            } else {
+                // more than the stage holds (large multiplicities): straight to the bank
+                uint64_t base = 0;
+                if (lane == 0) base = atomicAdd(reinterpret_cast<unsigned long long*>(P.out_count), total);
+                base = __shfl(base, 0);
+                for (uint32_t k = k0; k <= n; ++k)
+                    bank_store(P, base + off + (k - k0), p.x, p.t, murmur_hash(k, p.X) & P.lcg.mask, p.batch, p.tb);
+                seen = base + total;
+            }
+        }
         if (n > 0) {
             if (keep)
                 p.X = murmur_hash(1ull, p.X) & P.lcg.mask;   // the first emerging particle runs on here
@@ -286,7 +352,8 @@ __global__ void __launch_bounds__(BLOCK) k_pulse_bank(PulseParams P) {
                 active = false;
         }
     }
-    if (ptotal != 0) write_appends(P, pa, __shfl(pbase_l0, 0));
+    if (staged != 0) bank_flush<BLOCK>(P, S, staged, lane);
+    tally_lds_end<BLOCK>(P, lds_counts);
     flush_lane_counters<BLOCK>(P, c);
 }
 
@@ -294,6 +361,8 @@ __global__ void __launch_bounds__(BLOCK) k_pulse_bank(PulseParams P) {
 
 template <bool HASH, int BLOCK>
 __global__ void __launch_bounds__(BLOCK) k_pulse_family(PulseParams P) {
+    extern __shared__ unsigned long long lds_counts[];
+    tally_lds_begin<BLOCK>(P, lds_counts);
     PulseLane c;
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t gl = static_cast<uint64_t>(blockIdx.x) * BLOCK + threadIdx.x;
@@ -334,8 +403,11 @@ __global__ void __launch_bounds__(BLOCK) k_pulse_family(PulseParams P) {
             }
         }
         if (__ballot(active) == 0) break;
+        uint32_t n = 0;
+        int64_t tally = -1;
+        if (active) n = pulse_particle(P, p, c, &pdraws, &tally);
+        wave_tally(P, tally, lane, lds_counts);
         if (!active) continue;
-        uint32_t n = pulse_particle(P, p, c, &pdraws);
         if (HASH) {
             // the particle's own stream ends here
             note_stream(P, c, pdraws);
@@ -374,6 +446,7 @@ __global__ void __launch_bounds__(BLOCK) k_pulse_family(PulseParams P) {
         else
             e.next++;
     }
+    tally_lds_end<BLOCK>(P, lds_counts);
     flush_lane_counters<BLOCK>(P, c);
 }
 
@@ -402,12 +475,12 @@ static int device_cus() {
 }
 
 template <bool SOURCES, int BLOCK>
-static uint32_t bank_grid_b(uint64_t items) {
+static uint32_t bank_grid_b(uint64_t items, size_t lds) {
     // resident blocks only: waves keep taking 256-item chunks, so a launch
     // ends with one tail instead of one per wave
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_pulse_bank<SOURCES, BLOCK>),
-                                                     BLOCK, 0) != hipSuccess || per_cu < 1)
+                                                     BLOCK, lds) != hipSuccess || per_cu < 1)
         per_cu = 1;
     uint64_t blocks = (items + 4 * BLOCK - 1) / (4 * BLOCK);   // a 256-item chunk per wave at least
     const uint64_t cap = static_cast<uint64_t>(device_cus()) * static_cast<uint64_t>(per_cu);
@@ -416,19 +489,22 @@ static uint32_t bank_grid_b(uint64_t items) {
     return static_cast<uint32_t>(blocks);
 }
 
-uint32_t pulse_bank_grid(bool sources, int block, uint64_t items) {
+size_t pulse_tally_lds_bytes(const PulseParams& p) { return p.lds_tally ? 8ull * p.n_counters : 0; }
+
+uint32_t pulse_bank_grid(const PulseParams& p, bool sources, int block, uint64_t items) {
+    const size_t lds = pulse_tally_lds_bytes(p);
     switch (block) {
-        case 64: return sources ? bank_grid_b<true, 64>(items) : bank_grid_b<false, 64>(items);
-        case 128: return sources ? bank_grid_b<true, 128>(items) : bank_grid_b<false, 128>(items);
-        case 512: return sources ? bank_grid_b<true, 512>(items) : bank_grid_b<false, 512>(items);
-        case 1024: return sources ? bank_grid_b<true, 1024>(items) : bank_grid_b<false, 1024>(items);
-        default: return sources ? bank_grid_b<true, 256>(items) : bank_grid_b<false, 256>(items);
+        case 64: return sources ? bank_grid_b<true, 64>(items, lds) : bank_grid_b<false, 64>(items, lds);
+        case 128: return sources ? bank_grid_b<true, 128>(items, lds) : bank_grid_b<false, 128>(items, lds);
+        case 512: return sources ? bank_grid_b<true, 512>(items, lds) : bank_grid_b<false, 512>(items, lds);
+        case 1024: return sources ? bank_grid_b<true, 1024>(items, lds) : bank_grid_b<false, 1024>(items, lds);
+        default: return sources ? bank_grid_b<true, 256>(items, lds) : bank_grid_b<false, 256>(items, lds);
     }
 }
 
 template <bool SOURCES, int BLOCK>
 static hipError_t launch_bank_b(const PulseParams& p, uint32_t grid, hipStream_t st) {
-    hipLaunchKernelGGL((k_pulse_bank<SOURCES, BLOCK>), dim3(grid), dim3(BLOCK), 0, st, p);
+    hipLaunchKernelGGL((k_pulse_bank<SOURCES, BLOCK>), dim3(grid), dim3(BLOCK), pulse_tally_lds_bytes(p), st, p);
     return hipGetLastError();
 }
 
@@ -446,7 +522,7 @@ hipError_t launch_pulse_bank(const PulseParams& p, bool sources, int block, uint
 
 template <bool HASH, int BLOCK>
 static hipError_t launch_family_b(const PulseParams& p, uint32_t grid, hipStream_t st) {
-    hipLaunchKernelGGL((k_pulse_family<HASH, BLOCK>), dim3(grid), dim3(BLOCK), 0, st, p);
+    hipLaunchKernelGGL((k_pulse_family<HASH, BLOCK>), dim3(grid), dim3(BLOCK), pulse_tally_lds_bytes(p), st, p);
     return hipGetLastError();
 }
 

@@ -45,6 +45,8 @@ struct PulseParams {
     uint32_t stack_depth;    // family schedule: entries per lane
     const double* t_edges;   // device, n_time_bins + 1
     uint64_t* counts;        // n_batches x n_time_bins
+    uint32_t n_counters;     // n_batches x n_time_bins
+    uint32_t lds_tally;      // 1: each block counts into an LDS copy of all counters
     uint64_t* diag;          // kNDiag words (PD_*)
     uint64_t stride_q;       // stride: Q (over-stride count)
     uint64_t src_begin, src_end;   // sources of this launch (0-based over the run)
@@ -61,7 +63,8 @@ struct PulseParams {
 
 // Bank launches: the grid (resident blocks, at most one 256-item chunk per
 // wave) is chosen first, so that the caller can size the output for it.
-uint32_t pulse_bank_grid(bool sources, int block, uint64_t items);
+uint32_t pulse_bank_grid(const PulseParams& p, bool sources, int block, uint64_t items);
+constexpr uint32_t kPulseLdsCounters = 2048;   // block-local tally copies up to this many counters (16 KiB)
 hipError_t launch_pulse_bank(const PulseParams& p, bool sources, int block, uint32_t grid, hipStream_t st);
 uint32_t pulse_family_grid(int block);
 hipError_t launch_pulse_family(const PulseParams& p, int block, uint32_t grid, hipStream_t st);
