@@ -444,6 +444,7 @@ def pulse_leg(M, W, torch, lcg, ctx, oracle):
                                "collisions_per_s": d["collisions"] / (ms * 1e-3),
                                "draws_per_s": d["draws"] / (ms * 1e-3),
                                "collisions_per_source": d["collisions"] / d["sources"], "max_draws": d["max_draws"]}
+    out["hash_bank_over_stride_family"] = out["stride_family"]["ms"] / out["hash_bank"]["ms"]
     out["few_sources_hash_bank_over_stride_family"] = (out["few_sources_stride_family"]["ms"] /
                                                        out["few_sources_hash_bank"]["ms"])
     out["hash_family_over_stride_family"] = out["stride_family"]["ms"] / out["hash_family"]["ms"]
@@ -455,7 +456,7 @@ def pulse_leg(M, W, torch, lcg, ctx, oracle):
     dt = time.perf_counter() - t0
     out["cpu_oracle"] = {"sources_per_s": sample.n_sources / dt, "threads": threads,
                          "sample": "64 batches x 1000 sources, hash seeding"}
-    out["gpu_over_cpu_oracle"] = out["hash_family"]["sources_per_s"] / out["cpu_oracle"]["sources_per_s"]
+    out["gpu_over_cpu_oracle"] = out["hash_bank"]["sources_per_s"] / out["cpu_oracle"]["sources_per_s"]
 
     study = {}
     for kind in ("hash", "stride"):
