@@ -30,8 +30,10 @@
 //       start of one scattering (stride: a count; hash: X_p and the next
 //       key), so the depth is at most the number of scatterings on the
 //       current line of descent.
-// Counts are 64-bit integer atomics, so every schedule, launch shape and
-// order gives the same counts.
+// Counts are integers added with 64-bit atomics (into a per-block LDS copy
+// of every counter when they fit, else one HBM atomic per distinct counter
+// of a wave), so every schedule, launch shape and order gives the same
+// counts.
 #include "pulse.hpp"
 
 namespace mcrng {
