@@ -738,6 +738,11 @@ static size_t bank_bytes(uint64_t cap) { return 17 * (((cap * 8) + 255) & ~stati
 // each launch advances every live particle by one event and compacts the
 // survivors into the other bank; the host reads the live count after each
 // launch.  Partial slots are zeroed and accumulated with integer atomics.
+namespace mcrng {
+hipError_t launch_event_finish(const EventParams& p, int f32, int timed, hipStream_t st);   // events.hip
+}
+
+
 static int run_event_schedule(mcrng_ctx* ctx, const LcgDev& L, const mcrng_run_opts& o, hipStream_t st) {
     const uint64_t total = ctx->h_rec_begin.back();
     if (total >> 32) return fail(MCRNG_EINVAL, "event schedule: more than 2^32 histories in one run");
@@ -768,12 +773,22 @@ static int run_event_schedule(mcrng_ctx* ctx, const LcgDev& L, const mcrng_run_o
         ep.out = B;
         ep.n_in = static_cast<uint32_t>(ctx->h_rec_begin[u1] - ctx->h_rec_begin[u0]);
         HIP_TRY(launch_event_init(ep, f32, timed, st));
+        // below 1/64 of the bank (64Ki live particles for the default bank) the
+        // slice's remaining particles run to their ends in one launch
+        const uint64_t finish_below = cap / 64;
         while (ep.n_in > 0) {
+            if (ep.n_in < finish_below) {
+                HIP_TRY(launch_event_finish(ep, f32, timed, st));
+                break;
+            }
             HIP_TRY(launch_fill_u32(ep.n_out, 1, 0u, st));
             HIP_TRY(launch_event_step(ep, f32, timed, st));
-            uint32_t live = 0;
-            HIP_TRY(hipMemcpyAsync(&live, ep.n_out, sizeof live, hipMemcpyDeviceToHost, st));
+            if (!ctx->h_pinned)
+                HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&ctx->h_pinned), 64, hipHostMallocDefault));
+            HIP_TRY(hipMemcpyAsync(ctx->h_pinned, ep.n_out, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
             HIP_TRY(hipStreamSynchronize(st));
+            uint32_t live = 0;
+            std::memcpy(&live, ctx->h_pinned, sizeof live);
             if (live > ep.n_in) return fail(MCRNG_EDEVICE, "event schedule: bank count grew");
             std::swap(ep.in, ep.out);
             ep.n_in = live;

@@ -3,13 +3,16 @@
 // The live particles sit in a structure-of-arrays bank in HBM.  One launch of
 // k_event_step advances every live particle by exactly one event (the same
 // step_particle as the history-based kernel, so the per-particle operation
-// sequence is identical); survivors are appended to the other bank through a
-// wave-aggregated atomic, so each launch compacts the bank.  Scores go to the
+// sequence is identical); survivors are appended to the other bank through
+// one atomic per 1024-thread block, so each launch compacts the bank.  Scores go to the
 // work unit's partial-tally slot with 64-bit global integer atomics (the
 // slots are zeroed first); the sums are exact, so the result is the same as
 // the history-based schedule's bit for bit.  A history that ends writes one
 // outcome record; k_event_unit_diag reduces the records of each unit in
-// history order into the unit's diagnostics slot.
+// history order into the unit's diagnostics slot.  Once a slice's bank is
+// small, k_event_finish runs its remaining particles to their ends (one per
+// thread, the same per-event calls), which saves a launch per remaining
+// event generation.
 #include "particle.hpp"
 
 namespace mcrng {
@@ -96,10 +99,16 @@ __global__ void __launch_bounds__(256) k_event_init(EventParams E) {
     store_particle<F32>(E.in, i, p, 0u, 0u, lo, static_cast<uint32_t>(r));
 }
 
+constexpr int kEventStepBlock = 1024;
+
 template <bool F32, bool TIMED>
-__global__ void __launch_bounds__(256) k_event_step(EventParams E) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(kEventStepBlock) k_event_step(EventParams E) {
+    constexpr int kWaves = kEventStepBlock / 64;
+    __shared__ uint32_t s_wave_count[kWaves];
+    __shared__ uint32_t s_base;
+    const uint32_t i = blockIdx.x * kEventStepBlock + threadIdx.x;
     const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wid = threadIdx.x >> 6;
     bool alive = false;
     Particle<F32> p;
     uint32_t unit = 0, rec = 0;
@@ -135,19 +144,64 @@ __global__ void __launch_bounds__(256) k_event_step(EventParams E) {
             alive = true;
         }
     }
-    // compaction: survivors of the wave go to consecutive slots of `out`
+    // compaction: the block's survivors go to consecutive slots of `out`
+    // through one atomic per block (a single counter hit once per wave by
+    // every wave of the GPU serialises)
     const uint64_t mask = __ballot(alive);
-    if (mask == 0) return;
-    const uint32_t cnt_alive = static_cast<uint32_t>(__popcll(mask));
-    const int leader = __ffsll(static_cast<unsigned long long>(mask)) - 1;
-    uint32_t base = 0;
-    if (static_cast<int>(lane) == leader) base = atomicAdd(E.n_out, cnt_alive);
-    base = __shfl(base, leader);
+    if (lane == 0) s_wave_count[wid] = static_cast<uint32_t>(__popcll(mask));
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t total = 0;
+        for (int w = 0; w < kWaves; ++w) {
+            const uint32_t c = s_wave_count[w];
+            s_wave_count[w] = total;
+            total += c;
+        }
+        s_base = total ? atomicAdd(E.n_out, total) : 0u;
+    }
+    __syncthreads();
     if (alive) {
         const uint32_t lt = static_cast<uint32_t>(__popcll(mask & ((lane == 0) ? 0ull : (~0ull >> (64 - lane)))));
-        store_particle<F32>(E.out, base + lt, p, static_cast<uint32_t>(cnt.events),
+        store_particle<F32>(E.out, s_base + s_wave_count[wid] + lt, p, static_cast<uint32_t>(cnt.events),
                             static_cast<uint32_t>(cnt.collisions), unit, rec);
     }
+}
+
+// The particles of a small bank run to the end of their histories, one per
+// thread (the same step_particle calls, event after event): the tail of a
+// slice without one launch per remaining event.
+template <bool F32, bool TIMED>
+__global__ void __launch_bounds__(256) k_event_finish(EventParams E) {
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= E.n_in) return;
+    BankView<F32> v = view<F32>(E.in);
+    Particle<F32> p;
+    LaneCounters cnt;
+    p.x = v.x[i];
+    p.mu = v.mu[i];
+    p.t = v.t[i];
+    p.tau = v.tau[i];
+    p.X = E.in.X[i];
+    p.cell = E.in.cell[i];
+    p.tb = E.in.tb[i];
+    p.hdraws = E.in.hdraws[i];
+    p.need_tau = (E.in.flags[i] & 1u) != 0;
+    cnt.events = E.in.events[i];
+    cnt.collisions = E.in.colls[i];
+    const uint32_t unit = E.in.unit[i];
+    const uint32_t rec = E.in.rec[i];
+    const WorkUnit U = E.tp.units[unit];
+    const DevProblem PR = E.tp.problems[U.problem];
+    const CellsLds<F32> C = global_cells<F32>(E.tp, PR);
+    uint64_t* tally = E.tp.partial + U.slot;
+    int end = END_NONE;
+    while (end == END_NONE) end = step_particle<F32, TIMED>(p, C, E.tp.lcg, tally, cnt);
+    HistoryRecord h;
+    h.events = static_cast<uint32_t>(cnt.events);
+    h.collisions = static_cast<uint32_t>(cnt.collisions);
+    h.draws = p.hdraws;
+    h.end = static_cast<uint32_t>(end);
+    E.records[rec] = h;
 }
 
 // One block per unit: the unit's records, in history order, into its
@@ -195,7 +249,8 @@ static hipError_t init_t(const EventParams& p, hipStream_t st) {
 
 template <bool F32, bool TIMED>
 static hipError_t step_t(const EventParams& p, hipStream_t st) {
-    hipLaunchKernelGGL((k_event_step<F32, TIMED>), dim3((p.n_in + 255) / 256), dim3(256), 0, st, p);
+    hipLaunchKernelGGL((k_event_step<F32, TIMED>), dim3((p.n_in + kEventStepBlock - 1) / kEventStepBlock),
+                       dim3(kEventStepBlock), 0, st, p);
     return hipGetLastError();
 }
 
@@ -209,6 +264,18 @@ hipError_t launch_event_step(const EventParams& p, int f32, int timed, hipStream
     if (p.n_in == 0) return hipSuccess;
     if (f32) return timed ? step_t<true, true>(p, st) : step_t<true, false>(p, st);
     return timed ? step_t<false, true>(p, st) : step_t<false, false>(p, st);
+}
+
+template <bool F32, bool TIMED>
+static hipError_t finish_t(const EventParams& p, hipStream_t st) {
+    hipLaunchKernelGGL((k_event_finish<F32, TIMED>), dim3((p.n_in + 255) / 256), dim3(256), 0, st, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_event_finish(const EventParams& p, int f32, int timed, hipStream_t st) {
+    if (p.n_in == 0) return hipSuccess;
+    if (f32) return timed ? finish_t<true, true>(p, st) : finish_t<true, false>(p, st);
+    return timed ? finish_t<false, true>(p, st) : finish_t<false, false>(p, st);
 }
 
 hipError_t launch_event_unit_diag(const EventParams& p, hipStream_t st) {
