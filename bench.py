@@ -218,9 +218,9 @@ def main():
                     help="also run one plain 512 MiB device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on exactly one GPU (--gpus 1); multi-GPU runs are not "
-              "part of it (the path would shard histories by first_index and all-reduce the "
-              "integer tallies).", file=sys.stderr)
+        print("bench.py runs on exactly one GPU (--gpus 1); several GPUs are not supported "
+              "(the path would shard histories by first_index and all-reduce the integer "
+              "tallies).", file=sys.stderr)
         sys.exit(2)
 
     import torch
