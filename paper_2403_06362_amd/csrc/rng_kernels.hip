@@ -39,18 +39,18 @@ __device__ __forceinline__ uint64_t queue_seed(const DrawParams& P, uint64_t j) 
 }
 
 // Persistent seed + draw kernel.  Each wave owns the streams [lo, hi)
-// (fewer than 2^32) and keeps the next 128 of them ready in two queues of 64:
-// lane l holds the start states of streams qbase + l (queue A) and
-// qbase + 64 + l (queue B), each queue seeded with all 64 lanes at once, and
-// the wave's 128-entry LDS ring holds their draw counts (loaded one queue
-// ahead).  Each lane carries one active stream; a round draws D steps (only
-// the checksum is masked by the remaining count); after a round, lanes whose
-// stream ended store its checksum and take the next queue entries in order
-// (ballot, prefix count, cross-lane reads of both queues, one LDS read).  Up
-// to 64 lanes are served per round without a loop, and the refill path never
-// waits on vector memory (one wait per 64 streams, when a queue is rebuilt).
+// (fewer than 2^32) and keeps the next streams ready in a 128-entry LDS ring
+// (start state and draw count at position j & 127 for stream j), seeded 64 at
+// a time by all 64 lanes at once, the counts loaded one batch ahead.  Each
+// lane carries one active stream; a round draws D steps (only the checksum is
+// masked by the remaining count); after a round, lanes whose stream ended
+// store its checksum and take the next ring entries in order (ballot, prefix
+// count, two LDS reads).  Up to 64 lanes are served per round without a
+// loop, and the refill path never waits on vector memory (one wait per 64
+// streams, when a batch is seeded).
 template <int MODE, int D, bool STORE_STATE, bool M63C1>
 __global__ void __launch_bounds__(256) k_draw(DrawParams P) {
+    __shared__ uint64_t s_state[4][128];
     __shared__ uint32_t s_count[4][128];
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave in block
@@ -59,20 +59,20 @@ __global__ void __launch_bounds__(256) k_draw(DrawParams P) {
     const uint64_t lo = wave * P.n / nwaves;
     const uint32_t nw = static_cast<uint32_t>((wave + 1) * P.n / nwaves - lo);   // streams of this wave
     const uint64_t g = P.lcg.g;
-    uint32_t* ring = s_count[wib];
+    uint64_t* rstate = s_state[wib];
+    uint32_t* rcount = s_count[wib];
 
-    // queue bookkeeping, wave-uniform: qbase = offset of queue A's first
-    // stream from lo; qhead = next entry (0..63 in A, 64..127 in B)
-    uint32_t qbase = 0, qhead = 0;
-    uint64_t qa = 0, qb = 0;
-    uint32_t qc_next = 0;
+    // ring bookkeeping, wave-uniform: streams [next, filled) are seeded and
+    // not yet handed out; c_next holds the counts of the batch after them
+    uint32_t next = 0, filled = 128;
+    uint32_t c_next = 0;
     {
         const uint32_t ja = lane, jb = 64u + lane, jn = 128u + lane;
-        ring[ja] = (ja < nw) ? P.count[lo + ja] : 0u;
-        ring[jb] = (jb < nw) ? P.count[lo + jb] : 0u;
-        if (ja < nw) qa = queue_seed<MODE>(P, lo + ja);
-        if (jb < nw) qb = queue_seed<MODE>(P, lo + jb);
-        if (jn < nw) qc_next = P.count[lo + jn];
+        rcount[ja] = (ja < nw) ? P.count[lo + ja] : 0u;
+        rcount[jb] = (jb < nw) ? P.count[lo + jb] : 0u;
+        rstate[ja] = (ja < nw) ? queue_seed<MODE>(P, lo + ja) : 0ull;
+        rstate[jb] = (jb < nw) ? queue_seed<MODE>(P, lo + jb) : 0ull;
+        if (jn < nw) c_next = P.count[lo + jn];
     }
 
     uint64_t x = 0, sum = 0;
@@ -85,33 +85,30 @@ __global__ void __launch_bounds__(256) k_draw(DrawParams P) {
             active = false;
         }
         const uint64_t need = __ballot(!active);
-        const uint32_t left = nw - (qbase + qhead);   // streams not yet handed out
+        const uint32_t left = nw - next;   // streams not yet handed out
         if (need != 0 && left != 0) {
             const uint32_t nneed = static_cast<uint32_t>(__popcll(need));
             const uint32_t take = __builtin_amdgcn_readfirstlane(nneed < left ? nneed : left);
             const uint32_t rank = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(need >> 32),
                                                             __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(need), 0u));
-            const uint32_t src = qhead + rank;               // < 128 for rank < take
-            const uint64_t va = __shfl(qa, static_cast<int>(src & 63u));
-            const uint64_t vb = __shfl(qb, static_cast<int>(src & 63u));
             if (!active && rank < take) {
-                x = (src < 64u) ? va : vb;
-                rem = ring[(qbase + src) & 127u];
-                sid = qbase + src;
+                const uint32_t e = (next + rank) & 127u;
+                x = rstate[e];
+                rem = rcount[e];
+                sid = next + rank;
                 sum = 0;
                 active = true;
             }
-            qhead = __builtin_amdgcn_readfirstlane(qhead + take);
-            if (qhead >= 64u) {
-                // queue A is used up: B becomes A, a new B is seeded
-                qbase += 64u;
-                qhead -= 64u;
-                qa = qb;
-                const uint32_t jb = qbase + 64u + lane;
-                ring[jb & 127u] = qc_next;   // the one wait on vector memory per 64 streams
-                if (jb < nw) qb = queue_seed<MODE>(P, lo + jb);
-                const uint32_t jn = jb + 64u;
-                qc_next = (jn < nw) ? P.count[lo + jn] : 0u;
+            next = __builtin_amdgcn_readfirstlane(next + take);
+            if (filled - next < 64u && filled < nw) {
+                // fewer than 64 ready: seed the next batch of 64 (its ring
+                // positions hold no stream that is still to be handed out)
+                const uint32_t j = filled + lane;
+                rstate[j & 127u] = (j < nw) ? queue_seed<MODE>(P, lo + j) : 0ull;
+                rcount[j & 127u] = c_next;   // the one wait on vector memory per 64 streams
+                const uint32_t jn = j + 64u;
+                c_next = (jn < nw) ? P.count[lo + jn] : 0u;
+                filled += 64u;
             }
         }
         if (__ballot(active) == 0) break;
