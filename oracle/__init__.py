@@ -73,7 +73,8 @@ class _Pulse(C.Structure):
                 ("x_lo", C.c_double), ("x_hi", C.c_double), ("n_time_bins", C.c_int32),
                 ("n_batches", C.c_uint32), ("t_edges", C.POINTER(C.c_double)),
                 ("per_batch", C.c_uint64), ("first_batch", C.c_uint64),
-                ("lcg", _Lcg), ("seeding", _Seeding)]
+                ("lcg", _Lcg), ("seeding", _Seeding),
+                ("census_every", C.c_uint32), ("pc_target", C.c_uint64), ("pc_seed", C.c_uint64)]
 
 
 class _PTrace(C.Structure):
@@ -118,6 +119,14 @@ def lib():
             L.orc_pulse_flux.argtypes = [P(_Pulse), C.c_void_p, C.c_void_p]
             L.orc_pulse_trace.argtypes = [P(_Pulse), u64, u64, C.c_void_p, C.c_void_p, C.c_void_p, u64, P(u64)]
             L.orc_pulse_trace.restype = C.c_int
+            L.orc_pulse_pc_run.argtypes = [P(_Pulse), u64, u64, C.c_void_p, C.c_void_p, C.c_void_p]
+            L.orc_pulse_pc_run.restype = C.c_int
+            L.orc_pulse_pc_flux.argtypes = [P(_Pulse), C.c_void_p, C.c_void_p, C.c_void_p]
+            L.orc_pulse_pc_scripted.argtypes = [P(_Pulse), C.c_void_p, u64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                                C.c_void_p, u64, P(u64)]
+            L.orc_pulse_pc_scripted.restype = C.c_int64
+            L.orc_pulse_pc_census.argtypes = [P(_Pulse), u64, u32, C.c_void_p, C.c_void_p, u64, P(u64), P(u64)]
+            L.orc_pulse_pc_census.restype = C.c_int
             _lib = L
     return _lib
 
@@ -426,6 +435,9 @@ def _pulse_struct(prob, lcg):
     st.first_batch = int(prob.first_batch)
     st.lcg = _lcg_struct(lcg)
     st.seeding = _seeding_struct(prob.seeding)
+    st.census_every = int(getattr(prob, "census_every", 0))
+    st.pc_target = int(getattr(prob, "pc_target", 0))
+    st.pc_seed = int(getattr(prob, "pc_seed", 0))
     k.st = st
     return k
 
@@ -434,6 +446,7 @@ def _pulse_struct(prob, lcg):
 class PulseTally:
     counts: np.ndarray   # uint64, (n_batches, n_time_bins)
     diag: dict
+    pop: np.ndarray = None   # population control: uint64 (n_batches, n_census, 2): arrivals, copies
 
 
 def pulse(prob, lcg, b0=0, b1=None, threads=1) -> PulseTally:
@@ -498,3 +511,89 @@ def pulse_trace(prob, lcg, b, i, cap=1 << 16):
     recs = [(int(log[k].start), int(log[k].end), float(log[k].x0), float(log[k].t0), int(log[k].n_out),
              int(log[k].draws)) for k in range(min(n.value, cap))]
     return [int(v) for v in cnt], dict(zip(PULSE_DIAG_NAMES, (int(v) for v in dg))), recs
+
+
+# ---------------------------------------------------------------- population control
+
+def pc_n_census(prob):
+    """Census points of a population-controlled pulse problem: T[(c+1) K]
+    for every (c+1) K < n_time_bins."""
+    k = int(prob.census_every)
+    return 0 if k == 0 else (prob.n_time_bins - 1) // k
+
+
+def pulse_pc(prob, lcg, b0=0, b1=None, threads=1) -> PulseTally:
+    """The pulse problem with population control at census times (hash
+    seeding): counts of batches b0 .. b1-1, diagnostics, and the census
+    populations pop[b, c] = (arrivals, copies)."""
+    b1 = prob.n_batches if b1 is None else b1
+    keep = _pulse_struct(prob, lcg)
+    nt = keep.st.n_time_bins
+    nc = pc_n_census(prob)
+
+    def part(lo, hi):
+        cnt = np.zeros(prob.n_batches * nt, np.uint64)
+        dg = np.zeros(NDIAG, np.uint64)
+        pop = np.zeros(max(prob.n_batches * nc * 2, 1), np.uint64)
+        if lib().orc_pulse_pc_run(C.byref(keep.st), lo, hi, cnt.ctypes.data, dg.ctypes.data, pop.ctypes.data) != 0:
+            raise ValueError("orc_pulse_pc_run rejected the problem")
+        return cnt, dg, pop
+
+    n = b1 - b0
+    threads = max(1, min(int(threads), max(n, 1)))
+    cuts = [b0 + n * i // threads for i in range(threads + 1)]
+    with ThreadPoolExecutor(threads) as ex:
+        parts = list(ex.map(lambda i: part(cuts[i], cuts[i + 1]), range(threads)))
+    cnt = np.zeros(prob.n_batches * nt, np.uint64)
+    dg = np.zeros(NDIAG, np.uint64)
+    pop = np.zeros(max(prob.n_batches * nc * 2, 1), np.uint64)
+    for c, d, pp in parts:
+        cnt += c
+        pop += pp
+        mx = max(dg[8], d[8])
+        dg += d
+        dg[8] = mx
+    return PulseTally(cnt.reshape(prob.n_batches, nt), dict(zip(PULSE_DIAG_NAMES, (int(v) for v in dg))),
+                      pop[:prob.n_batches * nc * 2].reshape(prob.n_batches, nc, 2))
+
+
+def pulse_pc_flux(prob, lcg, counts, pop):
+    keep = _pulse_struct(prob, lcg)
+    c = np.ascontiguousarray(counts, dtype=np.uint64).reshape(-1)
+    pp = np.ascontiguousarray(pop, dtype=np.uint64).reshape(-1)
+    if pp.size == 0:
+        pp = np.zeros(1, np.uint64)
+    out = np.zeros(c.size, np.float64)
+    lib().orc_pulse_pc_flux(C.byref(keep.st), c.ctypes.data, pp.ctypes.data, out.ctypes.data)
+    return out.reshape(prob.n_batches, keep.st.n_time_bins)
+
+
+def pulse_pc_scripted(prob, lcg, uniforms, cap=1024):
+    """One source family driven by the given uniforms (stride semantics) up
+    to the first census.  Returns (counts, diag, uniforms used, list of
+    census arrivals (x, mu))."""
+    keep = _pulse_struct(prob, lcg)
+    u = np.ascontiguousarray(uniforms, dtype=np.float64)
+    cnt = np.zeros(keep.st.n_time_bins, np.uint64)
+    dg = np.zeros(NDIAG, np.uint64)
+    cx = np.zeros(cap, np.float64)
+    cmu = np.zeros(cap, np.float64)
+    n = C.c_uint64()
+    used = lib().orc_pulse_pc_scripted(C.byref(keep.st), u.ctypes.data, u.size, cnt.ctypes.data, dg.ctypes.data,
+                                       cx.ctypes.data, cmu.ctypes.data, cap, C.byref(n))
+    arr = [(float(cx[i]), float(cmu[i])) for i in range(min(n.value, cap))]
+    return [int(v) for v in cnt], dict(zip(PULSE_DIAG_NAMES, (int(v) for v in dg))), int(used), arr
+
+
+def pulse_pc_census(prob, lcg, b, c, cap=1 << 20):
+    """Batch b at census c: the arrivals' stream states (in the oracle's
+    order) and the start states of the copies leaving it (copy k of
+    arrival i after the copies of arrivals 0 .. i-1)."""
+    keep = _pulse_struct(prob, lcg)
+    arr = np.zeros(cap, np.uint64)
+    cop = np.zeros(cap, np.uint64)
+    na, nc = C.c_uint64(), C.c_uint64()
+    if lib().orc_pulse_pc_census(C.byref(keep.st), b, c, arr.ctypes.data, cop.ctypes.data, cap, C.byref(na),
+                                 C.byref(nc)) != 0:
+        raise ValueError("orc_pulse_pc_census rejected the problem")
+    return [int(v) for v in arr[:min(na.value, cap)]], [int(v) for v in cop[:min(nc.value, cap)]]

@@ -21,6 +21,8 @@
  *   hierarchical seeds .. Sec. "Hierarchical Seed Splitting", eq. (4)
  *   secondary seeds ..... Sec. "On-Demand Seed Splitting", eq. (5)
  *   pulse problem ....... Sec. "Implementation and Results" (the test problem)
+ *   population control .. Sec. "Hierarchical Seed Splitting": one-off hashed
+ *                          values from a per-phase seed
  * The transport loop, the uniform mapping, the logarithm and the fixed-point
  * tally are readings of points the paper leaves open; each is stated where
  * it is implemented.
@@ -691,6 +693,12 @@ typedef struct {
     uint64_t first_batch;       /* global id of batch 0 */
     orc_lcg lcg;
     orc_seeding seeding;        /* kind, base, stride used */
+    /* population control (orc_pulse_pc_run only): census every census_every
+     * time bins, pc_target particles per batch after each census, one-off
+     * values from the global seed pc_seed */
+    uint32_t census_every;
+    uint64_t pc_target;
+    uint64_t pc_seed;
 } orc_pulse;
 
 enum {
@@ -734,23 +742,47 @@ static int32_t advance_tbin(const orc_pulse *P, int32_t tb, double t)
     return tb;
 }
 
-/* Runs one particle from its start to its end with random numbers from R.
- * Adds its scores to cnt (the batch's n_time_bins counters) and its counts
- * to d.  On a scattering, *n_out receives the number of emerging particles,
- * and *xo, *to, *tbo their start; otherwise *n_out = 0. */
-static void pulse_particle(const orc_pulse *P, orc_rng *R, double x, double t, int32_t tb,
-                           uint64_t *cnt, uint64_t *d, uint32_t *n_out,
-                           double *xo, double *to, int32_t *tbo)
+/* a particle at its start: position, time, time bin; a census copy keeps
+ * its direction (has_mu), every other particle draws one first */
+typedef struct {
+    double x, t;
+    int32_t tb;
+    int has_mu;
+    double mu;
+} orc_start;
+
+enum { ORC_END_CENSUS = 0, ORC_END_ABSORBED = 1, ORC_END_SCATTERED = 2 };
+
+/* Runs one particle from its start s0 to its end with random numbers from
+ * R; t_cen is the census time (the last time edge, or the next census of a
+ * population-controlled run).  Adds its scores to cnt (the batch's
+ * n_time_bins counters) and its counts to d.  Returns the outcome;
+ * *n_out receives the number of emerging particles (0 unless it scattered)
+ * and *at the end point: the collision site (scattered), or the census
+ * point x + mu (t_cen - t), t_cen with the particle's direction (census). */
+static int pulse_particle(const orc_pulse *P, orc_rng *R, const orc_start *s0, double t_cen,
+                          uint64_t *cnt, uint64_t *d, uint32_t *n_out, orc_start *at)
 {
-    const double t_end = P->t_edges[P->n_time_bins];
     const double nu_floor = floor(P->nu);
     const double nu_frac = P->nu - nu_floor;
+    double x = s0->x, t = s0->t;
+    int32_t tb = s0->tb;
     *n_out = 0;
-    double mu = 2.0 * rng_draw(R) - 1.0;
+    double mu = s0->has_mu ? s0->mu : 2.0 * rng_draw(R) - 1.0;
     double tau = -orc_ln(rng_draw(R));
     double s = tau / P->sigma_t;
     double tn = t + s;
-    if (!(tn < t_end)) { d[ORC_P_CENSUS]++; return; }
+    if (!(tn < t_cen)) {
+        double rest = t_cen - t;
+        double step = mu * rest;
+        at->x = x + step;
+        at->t = t_cen;
+        at->tb = tb;
+        at->has_mu = 1;
+        at->mu = mu;
+        d[ORC_P_CENSUS]++;
+        return ORC_END_CENSUS;
+    }
     double step = mu * s;
     x = x + step;
     t = tn;
@@ -761,15 +793,18 @@ static void pulse_particle(const orc_pulse *P, orc_rng *R, double x, double t, i
         d[ORC_P_TALLIED]++;
     }
     double u1 = rng_draw(R);
-    if (!(u1 < P->scatter)) { d[ORC_P_ABSORBED]++; return; }
+    if (!(u1 < P->scatter)) { d[ORC_P_ABSORBED]++; return ORC_END_ABSORBED; }
     double u2 = rng_draw(R);
     uint32_t n = (uint32_t)nu_floor + (u2 < nu_frac ? 1u : 0u);
     d[ORC_P_SCATTERS]++;
     d[ORC_P_SECONDARIES] += n;
     *n_out = n;
-    *xo = x;
-    *to = t;
-    *tbo = tb;
+    at->x = x;
+    at->t = t;
+    at->tb = tb;
+    at->has_mu = 0;
+    at->mu = 0.0;
+    return ORC_END_SCATTERED;
 }
 
 static void note_stream(const orc_pulse *P, uint64_t *d, uint64_t draws)
@@ -792,49 +827,81 @@ typedef struct {
     uint64_t cap, n;
 } orc_plog;
 
-/* One source and everything it gives rise to.  Stride seeding: one stream
+/* a census arrival of a population-controlled run: position at the census
+ * time, direction, and the stream state after the particle's draws */
+typedef struct {
+    double x, mu;
+    uint64_t X;
+} orc_cpoint;
+
+typedef struct {
+    orc_cpoint *a;
+    size_t n, cap;
+} orc_clist;
+
+static int clist_push(orc_clist *L, orc_cpoint e)
+{
+    if (L->n == L->cap) {
+        size_t nc = L->cap ? 2 * L->cap : 256;
+        orc_cpoint *na = (orc_cpoint *)realloc(L->a, nc * sizeof *na);
+        if (!na) return -1;
+        L->a = na;
+        L->cap = nc;
+    }
+    L->a[L->n++] = e;
+    return 0;
+}
+
+/* One starting particle (a source, or a census copy) and everything it
+ * gives rise to, up to the census time t_cen.  Stride seeding: one stream
  * for the whole family (R), depth first.  Hash seeding: each particle its
  * own stream; the family is walked depth first too, which for hash seeding
- * is only one of many orders that give the same counts. */
-static int pulse_family(const orc_pulse *P, orc_rng *R, uint64_t *cnt, uint64_t *d, orc_stack *S,
-                        orc_plog *lg)
+ * is only one of many orders that give the same counts.  With `census`
+ * given, particles reaching t_cen are appended to it (population control);
+ * otherwise they end there. */
+static int pulse_family(const orc_pulse *P, orc_rng *R, const orc_start *first, double t_cen,
+                        uint64_t *cnt, uint64_t *d, orc_stack *S, orc_plog *lg, orc_clist *census)
 {
     const int hash = P->seeding.kind == ORC_SEED_HASH;
     const uint64_t msk = mask_of(P->lcg.m);
-    double x = 0.0, t = 0.0;
-    int32_t tb = advance_tbin(P, -1, 0.0);
+    orc_start cur = *first;
     S->n = 0;
-    d[ORC_P_SOURCES]++;
     for (;;) {
         uint32_t n = 0;
-        double xo = 0, to = 0;
-        int32_t tbo = -1;
+        orc_start at;
+        memset(&at, 0, sizeof at);
         const uint64_t start = R->x, draws0 = R->draws;
-        pulse_particle(P, R, x, t, tb, cnt, d, &n, &xo, &to, &tbo);
+        const int end = pulse_particle(P, R, &cur, t_cen, cnt, d, &n, &at);
         if (lg && lg->a) {
             if (lg->n < lg->cap) {
                 orc_ptrace *e = &lg->a[lg->n];
-                e->start = start; e->end = R->x; e->x0 = x; e->t0 = t;
+                e->start = start; e->end = R->x; e->x0 = cur.x; e->t0 = cur.t;
                 e->n_out = n; e->draws = (uint32_t)(R->draws - draws0);
             }
             lg->n++;
+        }
+        if (end == ORC_END_CENSUS && census) {
+            orc_cpoint cp = { at.x, at.mu, R->x };
+            if (clist_push(census, cp)) return -1;
         }
         if (hash) {
             /* this particle's stream ends here */
             note_stream(P, d, R->draws);
             for (uint32_t k = n; k >= 1; --k) {   /* k = 1 ends on top */
-                orc_pending e = { xo, to, tbo, 1, orc_hash(k, R->x) & msk };
+                orc_pending e = { at.x, at.t, at.tb, 1, orc_hash(k, R->x) & msk };
                 if (stack_push(S, e)) return -1;
             }
         } else if (n > 0) {
-            orc_pending e = { xo, to, tbo, n, 0 };
+            orc_pending e = { at.x, at.t, at.tb, n, 0 };
             if (stack_push(S, e)) return -1;
         }
         if (S->n == 0) break;
         orc_pending *top = &S->a[S->n - 1];
-        x = top->x;
-        t = top->t;
-        tb = top->tb;
+        cur.x = top->x;
+        cur.t = top->t;
+        cur.tb = top->tb;
+        cur.has_mu = 0;
+        cur.mu = 0.0;
         if (hash) {
             R->x = top->seed;
             R->draws = 0;
@@ -845,6 +912,12 @@ static int pulse_family(const orc_pulse *P, orc_rng *R, uint64_t *cnt, uint64_t 
     }
     if (!hash) note_stream(P, d, R->draws);
     return 0;
+}
+
+static orc_start source_start(const orc_pulse *P)
+{
+    orc_start s = { 0.0, 0.0, advance_tbin(P, -1, 0.0), 0, 0.0 };
+    return s;
 }
 
 static int pulse_check(const orc_pulse *P)
@@ -875,7 +948,10 @@ int orc_pulse_run(const orc_pulse *P, uint64_t b0, uint64_t b1, uint64_t *counts
             else
                 R.x = orc_skip(P->seeding.base & mask_of(P->lcg.m), P->seeding.stride * (B * P->per_batch + i),
                                P->lcg.g, P->lcg.c, P->lcg.m);
-            rc = pulse_family(P, &R, counts + b * (uint64_t)P->n_time_bins, diag, &S, NULL);
+            const orc_start s0 = source_start(P);
+            diag[ORC_P_SOURCES]++;
+            rc = pulse_family(P, &R, &s0, P->t_edges[P->n_time_bins], counts + b * (uint64_t)P->n_time_bins,
+                              diag, &S, NULL, NULL);
         }
     }
     free(S.a);
@@ -897,7 +973,9 @@ int64_t orc_pulse_scripted(const orc_pulse *P, const double *u, uint64_t n_u, ui
     R.lcg = &P->lcg;
     R.script = u;
     R.n_script = n_u;
-    int rc = pulse_family(P, &R, counts, diag, &S, NULL);
+    const orc_start s0 = source_start(P);
+    diag[ORC_P_SOURCES]++;
+    int rc = pulse_family(P, &R, &s0, P->t_edges[P->n_time_bins], counts, diag, &S, NULL, NULL);
     free(S.a);
     if (rc || R.exhausted) return -1;
     return (int64_t)R.pos;
@@ -922,7 +1000,9 @@ int orc_pulse_trace(const orc_pulse *P, uint64_t b, uint64_t i, uint64_t *counts
                        P->lcg.g, P->lcg.c, P->lcg.m);
     orc_stack S = { NULL, 0, 0 };
     orc_plog lg = { log, cap, 0 };
-    int rc = pulse_family(P, &R, counts, diag, &S, &lg);
+    const orc_start s0 = source_start(P);
+    diag[ORC_P_SOURCES]++;
+    int rc = pulse_family(P, &R, &s0, P->t_edges[P->n_time_bins], counts, diag, &S, &lg, NULL);
     free(S.a);
     if (n) *n = lg.n;
     return rc;
@@ -938,6 +1018,280 @@ void orc_pulse_flux(const orc_pulse *P, const uint64_t *counts, double *flux)
             const double den = ((P->sigma_t * (double)P->per_batch) * dx) * dt;
             flux[(size_t)b * P->n_time_bins + k] = (double)counts[(size_t)b * P->n_time_bins + k] / den;
         }
+}
+
+/* ------------------------------------------------------------------ */
+/* Population control at census times with one-off hashed values (Sec.
+ * "Hierarchical Seed Splitting": where a full stream is not needed, as for
+ * population control, a hash of a per-phase seed gives one-off values, each
+ * under its own key).  Hash seeding only.
+ *
+ * Readings (the paper names the use, not the scheme):
+ *   census:    with K = census_every, census c (0-based) is at the time edge
+ *              T[(c+1) K], for every (c+1) K < n_time_bins; epoch e runs from
+ *              the previous census (or t = 0) to the next census (or the
+ *              last edge).  A particle whose flight reaches the census time
+ *              C stops there at x + mu (C - t) (x = x + (mu * (C - t))) with
+ *              its direction and stream state; its remaining flight is not
+ *              kept (exponential flights are memoryless);
+ *   control:   per batch, N particles reach census c; M = pc_target.  With
+ *              q = floor(M / N), r = M mod N, particle i (state X_i) leaves
+ *              n_i = q + [u_i < r / N] copies, so E[sum n_i] = M, where
+ *                u_i = U(hash(X_i, Phi) mod 2^m),
+ *                Phi = hash(c + 1, hash(B + 1, pc_seed))   (B the batch id)
+ *              is the one-off value: the per-phase seed Phi is the parent,
+ *              the particle's own state its key.  U is the uniform mapping
+ *              ((S >> (m-53)) + 1) 2^-53, and the test is the exact integer
+ *              comparison ((S >> (m-53)) + 1) N < r 2^53;
+ *   copies:    copy k (k = 1..n_i) starts at the census point with the
+ *              particle's direction (no direction draw) and the stream
+ *              hash(k, X_i) mod 2^m (eq. 5: the copies are the particle's
+ *              children at the census);
+ *   weights:   every particle of a batch carries the same weight in an
+ *              epoch: 1 in epoch 0 and w_{c+1} = (w_c N_c) / M after census
+ *              c, so the counts stay integers and the flux of a time bin
+ *              of epoch e is ((double)count w_e) / den, den as in the plain
+ *              problem.
+ * The batches are independent, so a batch is run whole, epoch by epoch. */
+/* ------------------------------------------------------------------ */
+
+static uint32_t pc_n_census(const orc_pulse *P)
+{
+    if (P->census_every == 0) return 0;
+    return (uint32_t)((uint32_t)(P->n_time_bins - 1) / P->census_every);
+}
+
+/* a census copy waiting to start: census point, direction, stream start */
+typedef struct {
+    double x, mu;
+    uint64_t seed;
+} orc_copy;
+
+/* number of copies particle X leaves at a census of N particles */
+static uint64_t pc_copies(const orc_pulse *P, uint64_t phi, uint64_t X, uint64_t N)
+{
+    const uint64_t M = P->pc_target;
+    const uint64_t q = M / N, r = M % N;
+    const uint64_t S = orc_hash(X, phi) & mask_of(P->lcg.m);
+    const u128 j1 = (u128)((S >> (P->lcg.m - 53)) + 1);
+    const int extra = j1 * (u128)N < ((u128)r << 53);
+    return q + (uint64_t)extra;
+}
+
+/* Runs batches b0 .. b1-1 of a population-controlled problem and ADDS their
+ * scores into counts, their counts into diag (as orc_pulse_run) and writes
+ * pop[b][c][0] = particles of batch b reaching census c, pop[b][c][1] =
+ * copies leaving it (pop: n_batches x n_census x 2, may be NULL).  Returns
+ * 0, or -1 for a bad argument or an allocation failure. */
+int orc_pulse_pc_run(const orc_pulse *P, uint64_t b0, uint64_t b1, uint64_t *counts, uint64_t *diag,
+                     uint64_t *pop)
+{
+    if (pulse_check(P) || !counts || !diag || b1 > P->n_batches) return -1;
+    if (P->seeding.kind != ORC_SEED_HASH || P->census_every == 0 || P->pc_target == 0) return -1;
+    const uint32_t nc = pc_n_census(P);
+    const uint64_t msk = mask_of(P->lcg.m);
+    orc_stack S = { NULL, 0, 0 };
+    orc_clist cl = { NULL, 0, 0 };
+    orc_copy *items = NULL, *next = NULL;
+    size_t cap_items = 0, cap_next = 0;
+    int rc = 0;
+    for (uint64_t b = b0; b < b1 && rc == 0; ++b) {
+        const uint64_t B = P->first_batch + b;
+        uint64_t *cnt = counts + b * (uint64_t)P->n_time_bins;
+        const uint64_t parent = orc_hash(B + 1, P->seeding.base);
+        size_t n_items = 0;
+        for (uint32_t e = 0; e <= nc && rc == 0; ++e) {
+            const double t_cen = (e < nc) ? P->t_edges[(size_t)(e + 1) * P->census_every]
+                                          : P->t_edges[P->n_time_bins];
+            cl.n = 0;
+            const uint64_t n_start = (e == 0) ? P->per_batch : n_items;
+            for (uint64_t i = 0; i < n_start && rc == 0; ++i) {
+                orc_rng R;
+                memset(&R, 0, sizeof R);
+                R.lcg = &P->lcg;
+                orc_start s0;
+                if (e == 0) {
+                    s0 = source_start(P);
+                    R.x = orc_hash(i + 1, parent) & msk;
+                    diag[ORC_P_SOURCES]++;
+                } else {
+                    s0.x = items[i].x;
+                    s0.t = P->t_edges[(size_t)e * P->census_every];
+                    s0.tb = (int32_t)(e * P->census_every);
+                    s0.has_mu = 1;
+                    s0.mu = items[i].mu;
+                    R.x = items[i].seed;
+                }
+                rc = pulse_family(P, &R, &s0, t_cen, cnt, diag, &S, NULL, (e < nc) ? &cl : NULL);
+            }
+            if (rc || e == nc) break;
+            /* population control at census e */
+            const uint64_t N = cl.n;
+            const uint64_t phi = orc_hash((uint64_t)e + 1, orc_hash(B + 1, P->pc_seed));
+            size_t n_next = 0;
+            for (size_t i = 0; i < cl.n && rc == 0; ++i) {
+                const uint64_t n = pc_copies(P, phi, cl.a[i].X, N);
+                for (uint64_t k = 1; k <= n; ++k) {
+                    if (n_next == cap_next) {
+                        size_t ncap = cap_next ? 2 * cap_next : 1024;
+                        orc_copy *na = (orc_copy *)realloc(next, ncap * sizeof *na);
+                        if (!na) { rc = -1; break; }
+                        next = na;
+                        cap_next = ncap;
+                    }
+                    orc_copy cp = { cl.a[i].x, cl.a[i].mu, orc_hash(k, cl.a[i].X) & msk };
+                    next[n_next++] = cp;
+                }
+            }
+            if (pop) {
+                pop[(b * nc + e) * 2] = N;
+                pop[(b * nc + e) * 2 + 1] = n_next;
+            }
+            orc_copy *tmp = items; items = next; next = tmp;
+            size_t tc = cap_items; cap_items = cap_next; cap_next = tc;
+            n_items = n_next;
+        }
+    }
+    free(S.a);
+    free(cl.a);
+    free(items);
+    free(next);
+    return rc;
+}
+
+/* Flux of a population-controlled run: epoch weights from the census
+ * populations (pop as written by orc_pulse_pc_run). */
+void orc_pulse_pc_flux(const orc_pulse *P, const uint64_t *counts, const uint64_t *pop, double *flux)
+{
+    const uint32_t nc = pc_n_census(P);
+    const double dx = P->x_hi - P->x_lo;
+    for (uint32_t b = 0; b < P->n_batches; ++b) {
+        double w = 1.0;
+        uint32_t e = 0;
+        for (int32_t k = 0; k < P->n_time_bins; ++k) {
+            while (e < nc && (uint32_t)k >= (e + 1) * P->census_every) {
+                w = (w * (double)pop[((size_t)b * nc + e) * 2]) / (double)P->pc_target;
+                ++e;
+            }
+            const double dt = P->t_edges[k + 1] - P->t_edges[k];
+            const double den = ((P->sigma_t * (double)P->per_batch) * dx) * dt;
+            flux[(size_t)b * P->n_time_bins + k] = ((double)counts[(size_t)b * P->n_time_bins + k] * w) / den;
+        }
+    }
+}
+
+/* One source family driven by a list of uniforms (stride semantics) up to
+ * the first census T[census_every]: scores into counts (n_time_bins,
+ * overwritten) and the census arrivals (x, mu) into cx, cmu (up to cap;
+ * *n_census receives their number).  Returns the uniforms used, or -1. */
+int64_t orc_pulse_pc_scripted(const orc_pulse *P, const double *u, uint64_t n_u, uint64_t *counts,
+                              uint64_t *diag, double *cx, double *cmu, uint64_t cap, uint64_t *n_census)
+{
+    if (pulse_check(P) || !u || !counts || !diag || P->seeding.kind != ORC_SEED_STRIDE) return -1;
+    if (P->census_every == 0 || (int32_t)P->census_every >= P->n_time_bins) return -1;
+    memset(counts, 0, (size_t)P->n_time_bins * sizeof *counts);
+    orc_stack S = { NULL, 0, 0 };
+    orc_clist cl = { NULL, 0, 0 };
+    orc_rng R;
+    memset(&R, 0, sizeof R);
+    R.lcg = &P->lcg;
+    R.script = u;
+    R.n_script = n_u;
+    const orc_start s0 = source_start(P);
+    diag[ORC_P_SOURCES]++;
+    int rc = pulse_family(P, &R, &s0, P->t_edges[P->census_every], counts, diag, &S, NULL, &cl);
+    for (size_t i = 0; i < cl.n && i < cap; ++i) {
+        cx[i] = cl.a[i].x;
+        cmu[i] = cl.a[i].mu;
+    }
+    if (n_census) *n_census = cl.n;
+    free(S.a);
+    free(cl.a);
+    if (rc || R.exhausted) return -1;
+    return (int64_t)R.pos;
+}
+
+/* The census arrivals of batch b at census c of a population-controlled
+ * run, and the copies leaving it (tests): states X (up to cap) and the
+ * copies' start states in arrival order, copy k of arrival i at
+ * position sum_{i' < i} n_i' + k - 1 (up to cap); *n_arr and *n_cop receive
+ * the full numbers.  Returns 0 or -1. */
+int orc_pulse_pc_census(const orc_pulse *P, uint64_t b, uint32_t c, uint64_t *arr, uint64_t *cop, uint64_t cap,
+                        uint64_t *n_arr, uint64_t *n_cop)
+{
+    if (pulse_check(P) || b >= P->n_batches || P->seeding.kind != ORC_SEED_HASH || P->pc_target == 0) return -1;
+    const uint32_t nc = pc_n_census(P);
+    if (c >= nc) return -1;
+    const uint64_t msk = mask_of(P->lcg.m);
+    const uint64_t B = P->first_batch + b;
+    const uint64_t parent = orc_hash(B + 1, P->seeding.base);
+    uint64_t *cnt = (uint64_t *)calloc((size_t)P->n_time_bins, sizeof *cnt);
+    uint64_t d[ORC_P_NDIAG];
+    memset(d, 0, sizeof d);
+    orc_stack S = { NULL, 0, 0 };
+    orc_clist cl = { NULL, 0, 0 };
+    orc_copy *items = NULL;
+    size_t n_items = 0, cap_items = 0;
+    int rc = cnt ? 0 : -1;
+    for (uint32_t e = 0; e <= c && rc == 0; ++e) {
+        const double t_cen = P->t_edges[(size_t)(e + 1) * P->census_every];
+        cl.n = 0;
+        const uint64_t n_start = (e == 0) ? P->per_batch : n_items;
+        for (uint64_t i = 0; i < n_start && rc == 0; ++i) {
+            orc_rng R;
+            memset(&R, 0, sizeof R);
+            R.lcg = &P->lcg;
+            orc_start s0;
+            if (e == 0) {
+                s0 = source_start(P);
+                R.x = orc_hash(i + 1, parent) & msk;
+            } else {
+                s0.x = items[i].x;
+                s0.t = P->t_edges[(size_t)e * P->census_every];
+                s0.tb = (int32_t)(e * P->census_every);
+                s0.has_mu = 1;
+                s0.mu = items[i].mu;
+                R.x = items[i].seed;
+            }
+            rc = pulse_family(P, &R, &s0, t_cen, cnt, d, &S, NULL, &cl);
+        }
+        if (rc) break;
+        const uint64_t N = cl.n;
+        const uint64_t phi = orc_hash((uint64_t)e + 1, orc_hash(B + 1, P->pc_seed));
+        size_t n_new = 0;
+        orc_copy *nw = NULL;
+        size_t cap_new = 0;
+        for (size_t i = 0; i < cl.n && rc == 0; ++i) {
+            const uint64_t n = pc_copies(P, phi, cl.a[i].X, N);
+            for (uint64_t k = 1; k <= n; ++k) {
+                if (n_new == cap_new) {
+                    size_t ncap = cap_new ? 2 * cap_new : 1024;
+                    orc_copy *na = (orc_copy *)realloc(nw, ncap * sizeof *na);
+                    if (!na) { rc = -1; break; }
+                    nw = na;
+                    cap_new = ncap;
+                }
+                orc_copy cp = { cl.a[i].x, cl.a[i].mu, orc_hash(k, cl.a[i].X) & msk };
+                nw[n_new++] = cp;
+            }
+        }
+        if (e == c) {
+            for (size_t i = 0; i < cl.n && i < cap; ++i) arr[i] = cl.a[i].X;
+            for (size_t i = 0; i < n_new && i < cap; ++i) cop[i] = nw[i].seed;
+            *n_arr = cl.n;
+            *n_cop = n_new;
+        }
+        free(items);
+        items = nw;
+        n_items = n_new;
+        cap_items = cap_new;
+    }
+    (void)cap_items;
+    free(cnt);
+    free(S.a);
+    free(cl.a);
+    free(items);
+    return rc;
 }
 
 /* 128-bit unsigned integer to double, rounded to nearest, ties to even:

@@ -172,6 +172,12 @@ class PulseProblem:
     per_batch: int = 1000
     first_batch: int = 0
     seeding: Seeding = field(default_factory=lambda: hash_seeding())
+    # population control (hash seeding): a census every `census_every` time
+    # bins (0: none), `pc_target` particles per batch after each census,
+    # one-off values from the seed `pc_seed`
+    census_every: int = 0
+    pc_target: int = 0
+    pc_seed: int = 2
 
     @property
     def n_time_bins(self) -> int:
@@ -200,6 +206,15 @@ def pulse_few_sources(seeding=None, n_sources=4096, t_end=60):
     particle of a generation can run in parallel under hash seeding."""
     return PulseProblem(time_edges=np.arange(t_end + 1, dtype=np.float64), n_batches=1,
                         per_batch=n_sources, seeding=seeding or hash_seeding())
+
+
+def pulse_pc(seeding=None, n_batches=1000, per_batch=1000, census_every=5, target=None, t_end=20):
+    """The pulse problem with population control: a census every
+    `census_every` unit time bins, after which each batch again holds
+    `target` (default: per_batch) particles on average."""
+    return PulseProblem(time_edges=np.arange(t_end + 1, dtype=np.float64), n_batches=n_batches,
+                        per_batch=per_batch, seeding=seeding or hash_seeding(), census_every=census_every,
+                        pc_target=per_batch if target is None else target)
 
 
 CONFIG_NAMES = {
