@@ -29,7 +29,7 @@
 extern "C" {
 #endif
 
-#define MCRNG_ABI_VERSION 1
+#define MCRNG_ABI_VERSION 2
 
 enum {
     MCRNG_OK = 0,
@@ -323,6 +323,48 @@ enum {
 int mcrng_run_pulse(mcrng_ctx *ctx, const mcrng_lcg *lcg, const mcrng_pulse_problem *problem,
                     const mcrng_pulse_opts *opts, uint64_t *d_counts, double *d_flux,
                     uint64_t *d_diag, void *stream);
+
+/* Population control of the pulse problem at census times, with one-off
+ * hashed values (Sec. "Hierarchical Seed Splitting": where a full stream
+ * is not needed, as for population control, hashing a per-phase seed gives
+ * one-off values, one per key).  Hash seeding only.
+ * With K = census_every, census c (0-based) is at time_edges[(c+1) K], for
+ * every (c+1) K < n_time_bins; n_census is the number of such points.  A
+ * particle whose flight reaches a census time C stops at x + mu (C - t),
+ * keeping its direction and stream state (exponential flights are
+ * memoryless, so the rest of its flight is not kept).  Per batch, N
+ * particles reach census c; with M = target, q = floor(M / N),
+ * r = M mod N, the particle with state X leaves q + [u < r / N] copies,
+ *   u = U(hash(X, hash(c + 1, hash(B + 1, seed))) mod 2^m),
+ * U(S) = ((S >> (m - 53)) + 1) 2^-53 and the comparison exact in integers:
+ * the phase seed of (batch, census) is the parent and the particle's own
+ * state the key, so no ordering of the particles is needed.  Copy k
+ * (k = 1..) starts at the census point with the particle's direction (no
+ * direction draw) and the stream hash(k, X) mod 2^m (eq. 5).  All particles
+ * of a batch carry one weight per epoch, 1 before the first census and
+ * w_{c+1} = (w_c N_c) / M after census c, so the counts stay integers;
+ * the flux of a time bin of epoch e is ((double)count w_e) / den, den as
+ * for mcrng_run_pulse.  A batch that no particle reaches a census with
+ * scores nothing afterwards. */
+typedef struct {
+    uint32_t census_every;       /* K >= 1 */
+    uint32_t reserved0;          /* must be 0 */
+    uint64_t target;             /* M, 1 .. 2^40 */
+    uint64_t seed;               /* the population-control seed */
+    uint64_t reserved[2];        /* must be 0 */
+} mcrng_pulse_pc;
+
+/* Runs a pulse problem with population control: as mcrng_run_pulse (the
+ * bank schedule; opts.schedule AUTO or BANK), plus
+ *   d_pop  n_batches x n_census x 2 uint64 (may be NULL): the particles of
+ *          each batch reaching each census, and the copies leaving it.
+ * Diagnostics: CENSUS counts every census arrival; copies are neither
+ * sources nor secondaries (their number is the sum of the copies in
+ * d_pop).  Returns after the run.  Errors: MCRNG_EINVAL (arguments, stride
+ * seeding, the family schedule), MCRNG_ENOMEM. */
+int mcrng_run_pulse_pc(mcrng_ctx *ctx, const mcrng_lcg *lcg, const mcrng_pulse_problem *problem,
+                       const mcrng_pulse_pc *pc, const mcrng_pulse_opts *opts, uint64_t *d_counts,
+                       double *d_flux, uint64_t *d_diag, uint64_t *d_pop, void *stream);
 
 /* Thread-local text of the last failure (never NULL). */
 const char *mcrng_last_error(void);

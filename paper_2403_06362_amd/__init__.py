@@ -5,19 +5,19 @@ Paper: Cuneo & Variansyah, "An Alternative to Stride-Based RNG for Monte
 Carlo Transport" (arXiv 2403.06362).
 
 The entry points mirror the C ABI: init_streams, draw, uniforms, Context.run_histories,
-Context.reduce_tallies, Context.run_pulse (plus Context.autotune).  Tensors
+Context.reduce_tallies, Context.run_pulse, Context.run_pulse_pc (plus Context.autotune).  Tensors
 are torch device tensors; the library does all the arithmetic.
-`transport()` and `pulse()` are convenience wrappers that allocate the
+`transport()`, `pulse()` and `pulse_pc()` are convenience wrappers that allocate the
 output tensors.
 """
 from ._binding import (  # noqa: F401
     DIAG_NAMES, EXPORTS, FP32, FP64, NDIAG, PULSE_AUTO, PULSE_BANK, PULSE_DIAG_NAMES, PULSE_FAMILY, SCHED_EVENT,
-    SCHED_HISTORY, Context, McrngError, PulseOpts, RunOpts, draw, init_streams, lib, make_opts, make_pulse_opts,
-    tally_bins, uniforms,
+    SCHED_HISTORY, Context, McrngError, PulseOpts, PulsePc, RunOpts, draw, init_streams, lib, make_opts,
+    make_pulse_opts, make_pulse_pc, pulse_n_census, tally_bins, uniforms,
 )
 
 __all__ = ["init_streams", "draw", "uniforms", "Context", "RunOpts", "make_opts", "tally_bins", "transport", "pulse",
-           "PulseOpts", "make_pulse_opts", "McrngError", "lib", "FP64", "FP32", "SCHED_HISTORY", "SCHED_EVENT",
+           "PulseOpts", "make_pulse_opts", "pulse_pc", "PulsePc", "make_pulse_pc", "pulse_n_census", "McrngError", "lib", "FP64", "FP32", "SCHED_HISTORY", "SCHED_EVENT",
            "PULSE_AUTO", "PULSE_BANK", "PULSE_FAMILY", "NDIAG", "DIAG_NAMES", "PULSE_DIAG_NAMES"]
 
 
@@ -57,6 +57,28 @@ def pulse(problem, lcg, ctx=None, opts=None, stream=None, device="cuda:0"):
         diag = torch.empty(NDIAG, dtype=torch.uint64, device=device)
         ctx.run_pulse(lcg, problem, counts, flux, diag, opts, stream)
         return counts, flux, diag
+    finally:
+        if own:
+            torch.cuda.synchronize()
+            ctx.close()
+
+
+def pulse_pc(problem, lcg, ctx=None, opts=None, stream=None, device="cuda:0"):
+    """Runs a pulse problem with population control (problem.census_every,
+    pc_target, pc_seed; hash seeding).  Returns (counts, flux, diag, pop):
+    pop a uint64 tensor [n_batches, n_census, 2] (arrivals, copies)."""
+    import torch
+    own = ctx is None
+    ctx = ctx or Context(torch.device(device).index or 0)
+    try:
+        nt = len(problem.time_edges) - 1
+        nc = pulse_n_census(problem)
+        counts = torch.empty((problem.n_batches, nt), dtype=torch.uint64, device=device)
+        flux = torch.empty((problem.n_batches, nt), dtype=torch.float64, device=device)
+        diag = torch.empty(NDIAG, dtype=torch.uint64, device=device)
+        pop = torch.empty((problem.n_batches, max(nc, 1), 2), dtype=torch.uint64, device=device)
+        ctx.run_pulse_pc(lcg, problem, counts, flux, diag, pop if nc else None, opts, stream)
+        return counts, flux, diag, pop[:, :nc]
     finally:
         if own:
             torch.cuda.synchronize()

@@ -30,7 +30,8 @@ PULSE_DIAG_NAMES = ("sources", "collisions", "tallied", "scatters", "absorbed", 
 # every symbol include/mcrng.h declares
 EXPORTS = ("mcrng_init_streams", "mcrng_draw", "mcrng_ctx_create", "mcrng_ctx_destroy",
            "mcrng_tally_bins", "mcrng_run_histories", "mcrng_reduce_tallies", "mcrng_autotune",
-           "mcrng_last_run_ms", "mcrng_last_error", "mcrng_version", "mcrng_run_pulse", "mcrng_uniforms")
+           "mcrng_last_run_ms", "mcrng_last_error", "mcrng_version", "mcrng_run_pulse", "mcrng_uniforms",
+           "mcrng_run_pulse_pc")
 
 
 class McrngError(RuntimeError):
@@ -73,6 +74,11 @@ class PulseProblem(C.Structure):
                 ("per_batch", C.c_uint64), ("first_batch", C.c_uint64), ("seeding", Seeding)]
 
 
+class PulsePc(C.Structure):
+    _fields_ = [("census_every", C.c_uint32), ("reserved0", C.c_uint32), ("target", C.c_uint64),
+                ("seed", C.c_uint64), ("reserved", C.c_uint64 * 2)]
+
+
 class PulseOpts(C.Structure):
     _fields_ = [("schedule", C.c_uint32), ("block", C.c_uint32), ("stack_depth", C.c_uint32),
                 ("reserved", C.c_uint32 * 5)]
@@ -107,6 +113,7 @@ def lib():
         L.mcrng_version.argtypes = []
         L.mcrng_run_pulse.argtypes = [vp, P(Lcg), P(PulseProblem), P(PulseOpts), vp, vp, vp, vp]
         L.mcrng_uniforms.argtypes = [P(Lcg), P(Seeding), u64, u32, vp, vp, vp]
+        L.mcrng_run_pulse_pc.argtypes = [vp, P(Lcg), P(PulseProblem), P(PulsePc), P(PulseOpts), vp, vp, vp, vp, vp]
         for name in EXPORTS:
             if name not in ("mcrng_tally_bins", "mcrng_last_run_ms", "mcrng_last_error"):
                 getattr(L, name).restype = C.c_int
@@ -227,6 +234,17 @@ def make_pulse_problem(pr):
     return st, te
 
 
+def make_pulse_pc(pr):
+    """mcrng_pulse_pc of a workloads.PulseProblem-like object (census_every,
+    pc_target, pc_seed)."""
+    return PulsePc(int(pr.census_every), 0, int(pr.pc_target), int(pr.pc_seed))
+
+
+def pulse_n_census(pr):
+    k = int(pr.census_every)
+    return 0 if k == 0 else (len(pr.time_edges) - 2) // k
+
+
 def make_pulse_opts(**kw):
     o = PulseOpts()
     for k, v in kw.items():
@@ -305,6 +323,23 @@ class Context:
                                             _ptr(d_counts, torch.uint64, n, "d_counts"),
                                             _ptr(d_flux, torch.float64, n, "d_flux"),
                                             _ptr(d_diag, torch.uint64, NDIAG, "d_diag"), _stream(stream)))
+
+    def run_pulse_pc(self, lcg, problem, d_counts, d_flux=None, d_diag=None, d_pop=None, opts=None, stream=None):
+        """mcrng_run_pulse_pc: the pulse problem with population control
+        (problem.census_every, pc_target, pc_seed); d_pop is a uint64 tensor
+        [n_batches, n_census, 2] or None.  Returns after the run."""
+        import torch
+        st, _te = make_pulse_problem(problem)
+        L = make_lcg(lcg)
+        pc = make_pulse_pc(problem)
+        o = opts if opts is not None else PulseOpts()
+        n = int(problem.n_batches) * (len(_te) - 1)
+        npop = int(problem.n_batches) * pulse_n_census(problem) * 2
+        return _check(lib().mcrng_run_pulse_pc(self._h, C.byref(L), C.byref(st), C.byref(pc), C.byref(o),
+                                               _ptr(d_counts, torch.uint64, n, "d_counts"),
+                                               _ptr(d_flux, torch.float64, n, "d_flux"),
+                                               _ptr(d_diag, torch.uint64, NDIAG, "d_diag"),
+                                               _ptr(d_pop, torch.uint64, npop, "d_pop"), _stream(stream)))
 
     def last_run_ms(self):
         return float(lib().mcrng_last_run_ms(self._h))

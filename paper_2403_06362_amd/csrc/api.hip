@@ -238,6 +238,7 @@ struct mcrng_ctx {
     DevBuf units, order, partial, unit_diag, counter, groups, dx, dt, pu_begin;
     DevBuf bank_a, bank_b, records, rec_begin;   // event schedule
     DevBuf pulse_tedges, pulse_misc, pulse_diag, pulse_bank[2], pulse_stack;   // pulse problem
+    DevBuf pulse_census, pulse_copies, pulse_pop;                             // population control
     std::vector<double> h_pulse_tedges;
     uint64_t* h_pinned = nullptr;   // pinned host words for per-generation readbacks
     std::vector<uint64_t> h_rec_begin;
@@ -321,7 +322,7 @@ extern "C" int mcrng_ctx_destroy(mcrng_ctx* ctx) {
                       &ctx->unit_diag, &ctx->counter, &ctx->groups, &ctx->dx, &ctx->dt, &ctx->pu_begin,
                       &ctx->bank_a, &ctx->bank_b, &ctx->records, &ctx->rec_begin, &ctx->pulse_tedges,
                       &ctx->pulse_misc, &ctx->pulse_diag, &ctx->pulse_bank[0], &ctx->pulse_bank[1],
-                      &ctx->pulse_stack};
+                      &ctx->pulse_stack, &ctx->pulse_census, &ctx->pulse_copies, &ctx->pulse_pop};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (ctx->h_pinned) (void)hipHostFree(ctx->h_pinned);
@@ -999,21 +1000,50 @@ static PulseBankView carve_pulse_bank(void* base, uint64_t cap) {
     return v;
 }
 
-static int read_u64(mcrng_ctx* ctx, const uint64_t* d, uint64_t* h, hipStream_t st) {
+// Reads n <= 8 device words (through a pinned host buffer) after the work
+// queued on st.
+static int read_words(mcrng_ctx* ctx, const uint64_t* d, uint32_t n, uint64_t* h, hipStream_t st) {
     if (!ctx->h_pinned) HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&ctx->h_pinned), 64, hipHostMallocDefault));
-    HIP_TRY(hipMemcpyAsync(ctx->h_pinned, d, sizeof *h, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(ctx->h_pinned, d, n * sizeof *h, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    *h = ctx->h_pinned[0];
+    for (uint32_t i = 0; i < n; ++i) h[i] = ctx->h_pinned[i];
     return MCRNG_OK;
 }
 
-extern "C" int mcrng_run_pulse(mcrng_ctx* ctx, const mcrng_lcg* lcg, const mcrng_pulse_problem* P,
-                               const mcrng_pulse_opts* opts, uint64_t* d_counts, double* d_flux, uint64_t* d_diag,
-                               void* stream) {
+static int read_u64(mcrng_ctx* ctx, const uint64_t* d, uint64_t* h, hipStream_t st) {
+    return read_words(ctx, d, 1, h, st);
+}
+
+// Grows b to at least `bytes`, keeping its first `used` bytes.
+static int ensure_keep(DevBuf& b, size_t used, size_t bytes, hipStream_t st) {
+    if (bytes <= b.cap) return MCRNG_OK;
+    const size_t want = std::max<size_t>(std::max<size_t>(bytes + bytes / 4, 2 * b.cap), 256);
+    void* np = nullptr;
+    HIP_TRY(hipMalloc(&np, want));
+    if (used) HIP_TRY(hipMemcpyAsync(np, b.p, used, hipMemcpyDeviceToDevice, st));
+    if (b.p) {
+        HIP_TRY(hipStreamSynchronize(st));
+        HIP_TRY(hipFree(b.p));
+    }
+    b.p = np;
+    b.cap = want;
+    return MCRNG_OK;
+}
+
+static int run_pulse(mcrng_ctx* ctx, const mcrng_lcg* lcg, const mcrng_pulse_problem* P, const mcrng_pulse_pc* pc,
+                     const mcrng_pulse_opts* opts, uint64_t* d_counts, double* d_flux, uint64_t* d_diag,
+                     uint64_t* d_pop, void* stream) {
     LcgDev L;
     int rc = validate_lcg(lcg, 53, &L);
     if (rc < 0) return rc;
     if ((rc = validate_pulse(P)) < 0) return rc;
+    if (pc) {
+        if (pc->census_every == 0) return fail(MCRNG_EINVAL, "pc.census_every must be >= 1");
+        if (pc->target == 0 || pc->target > (1ull << 40)) return fail(MCRNG_EINVAL, "pc.target must be in 1..2^40");
+        if (pc->reserved0 || pc->reserved[0] || pc->reserved[1]) return fail(MCRNG_EINVAL, "pc.reserved must be 0");
+        if (P->seeding.kind != MCRNG_SEED_HASH)
+            return fail(MCRNG_EINVAL, "population control needs hash seeding (census copies are seeded by eq. 5)");
+    }
     mcrng_pulse_opts o;
     std::memset(&o, 0, sizeof o);
     if (opts) o = *opts;
@@ -1026,6 +1056,8 @@ extern "C" int mcrng_run_pulse(mcrng_ctx* ctx, const mcrng_lcg* lcg, const mcrng
         return fail(MCRNG_EINVAL, "opts.schedule unknown");
     if (o.schedule == MCRNG_PULSE_BANK && !hash)
         return fail(MCRNG_EINVAL, "the bank schedule needs hash seeding (stride families share one stream)");
+    if (pc && o.schedule == MCRNG_PULSE_FAMILY)
+        return fail(MCRNG_EINVAL, "population control runs on the bank schedule");
     if (o.block != 64 && o.block != 128 && o.block != 256 && o.block != 512 && o.block != 1024)
         return fail(MCRNG_EINVAL, "opts.block = %u not in {64,128,256,512,1024}", o.block);
     if (o.stack_depth == 0) o.stack_depth = 128;
@@ -1080,52 +1112,130 @@ extern "C" int mcrng_run_pulse(mcrng_ctx* ctx, const mcrng_lcg* lcg, const mcrng
     pp.n_counters = static_cast<uint32_t>(std::min<uint64_t>(n_counters, 0xffffffffu));
     pp.lds_tally = n_counters <= kPulseLdsCounters ? 1u : 0u;
     pp.diag = static_cast<uint64_t*>(ctx->pulse_diag.p);
-    // misc words: out_count, item_counter (reset per bank launch), family_counter, overflow
+    // misc words: out_count, item_counter (reset per bank launch), family_counter, overflow,
+    // census arrivals, census copies
     uint64_t* misc = static_cast<uint64_t*>(ctx->pulse_misc.p);
     pp.out_count = misc;
     pp.item_counter = misc + 1;
     pp.family_counter = misc + 2;
     pp.overflow = reinterpret_cast<uint32_t*>(misc + 3);
+    pp.cen_count = misc + 4;
+    pp.copy_count = misc + 5;
+    const uint32_t K = pc ? pc->census_every : 0;
+    const uint32_t n_census = pc ? (P->n_time_bins - 1) / K : 0;
+    const uint64_t n_pop = static_cast<uint64_t>(P->n_batches) * n_census * 2;
+    if (pc) {
+        pp.census_every = K;
+        pp.n_census = n_census;
+        pp.pc_target = pc->target;
+        pp.pc_seed = pc->seed;
+        if ((rc = ensure(ctx->pulse_pop, std::max<uint64_t>(n_pop, 1) * 8, st)) < 0) return rc;
+        pp.pop = static_cast<uint64_t*>(ctx->pulse_pop.p);
+        if (n_pop) HIP_TRY(launch_fill_u64(pp.pop, n_pop, 0ull, st));
+    }
     HIP_TRY(launch_fill_u64(misc, 8, 0ull, st));
     HIP_TRY(launch_fill_u64(pp.diag, kNDiag, 0ull, st));
     HIP_TRY(launch_fill_u64(d_counts, static_cast<uint64_t>(P->n_batches) * P->n_time_bins, 0ull, st));
     HIP_TRY(hipEventRecord(ctx->ev0, st));
     ctx->timing_valid = false;
 
-    if (o.schedule == MCRNG_PULSE_BANK) {
-        // generations: a launch runs the lines of descent of its input
-        // particles (their first emerging particles inline) and banks the
-        // siblings for the next launch.  Capacity per launch: the continue
-        // budget (2 per input particle), n_max per input particle, and one
-        // LDS stage plus one iteration's appends per wave.
+    // Generations: a launch runs the lines of descent of its input items
+    // (their first emerging particles inline) and banks the siblings for
+    // the next launch.  Capacity per launch: the continue budget (2 per
+    // input item), n_max per input item, and one LDS stage plus one
+    // iteration's appends per wave.  With `pcen` (a census of population
+    // control ends the epoch) every line ends at most once at the census, so
+    // the census bank grows by at most the launch's items.
+    auto generations = [&](int kind, uint64_t n, bool pcen, uint64_t* cen_used) -> int {
+        int cur = 0, nxt = 1;
+        uint64_t in_cap = 0;
+        while (n > 0) {
+            const uint32_t grid = pulse_bank_grid(pp, kind, pcen, static_cast<int>(o.block), n);
+            const uint64_t waves = static_cast<uint64_t>(grid) * o.block / 64;
+            const uint64_t budget = 2 * n;
+            const uint64_t slack = (waves + 1) * (256 + 64 * static_cast<uint64_t>(n_max));
+            const uint64_t ocap = budget + static_cast<uint64_t>(n_max) * n + slack;
+            int r = ensure(ctx->pulse_bank[nxt], ocap * 32, st, 8);
+            if (r < 0) return r;
+            if (pcen) {
+                r = ensure_keep(ctx->pulse_census, *cen_used * sizeof(PulseCensusEntry),
+                                (*cen_used + n) * sizeof(PulseCensusEntry), st);
+                if (r < 0) return r;
+                pp.cen = static_cast<PulseCensusEntry*>(ctx->pulse_census.p);
+                pp.cen_cap = ctx->pulse_census.cap / sizeof(PulseCensusEntry);
+            }
+            if (kind == PULSE_ITEMS_BANK) pp.in = carve_pulse_bank(ctx->pulse_bank[cur].p, in_cap);
+            pp.n_in = kind == PULSE_ITEMS_SOURCES ? 0 : n;
+            pp.out = carve_pulse_bank(ctx->pulse_bank[nxt].p, ocap);
+            pp.out_cap = ocap;
+            pp.cont_budget = budget;
+            HIP_TRY(launch_fill_u64(misc, 2, 0ull, st));
+            HIP_TRY(launch_pulse_bank(pp, kind, pcen, static_cast<int>(o.block), grid, st));
+            uint64_t w[5];
+            if ((r = read_words(ctx, misc, 5, w, st)) < 0) return r;
+            // a bank that ran out of room (never, by the capacities above)
+            // ends the run before any launch reads past it
+            if (w[3] & 0xffffffffull) return fail(MCRNG_ERANGE, "a particle bank ran out of room");
+            n = w[0];
+            if (pcen) *cen_used = w[4];
+            std::swap(cur, nxt);
+            in_cap = ocap;
+            kind = PULSE_ITEMS_BANK;
+        }
+        return MCRNG_OK;
+    };
+
+    if (pc) {
+        // Epochs between census times, chunk by chunk of whole batches
+        // (population control is per batch).  After each census: arrivals
+        // per batch, then the copies, which start the next epoch.
+        const uint64_t chunk_b = std::max<uint64_t>(
+            1, std::min<uint64_t>(kPulsePcChunkBatches, (1ull << 23) / P->per_batch));
+        for (uint64_t b0 = 0; b0 < P->n_batches; b0 += chunk_b) {
+            const uint64_t b1 = std::min<uint64_t>(P->n_batches, b0 + chunk_b);
+            pp.src_begin = b0 * P->per_batch;
+            pp.src_end = b1 * P->per_batch;
+            pp.batch_lo = static_cast<uint32_t>(b0);
+            pp.n_chunk_batches = static_cast<uint32_t>(b1 - b0);
+            uint64_t n_copies = 0;
+            for (uint32_t e = 0; e <= n_census; ++e) {
+                const bool pcen = e < n_census;
+                pp.t_end = pcen ? P->time_edges[static_cast<size_t>(e + 1) * K] : P->time_edges[P->n_time_bins];
+                uint64_t cen_used = 0;
+                HIP_TRY(launch_fill_u64(pp.cen_count, 1, 0ull, st));
+                if (e == 0) {
+                    rc = generations(PULSE_ITEMS_SOURCES, pp.src_end - pp.src_begin, pcen, &cen_used);
+                } else {
+                    pp.copies = static_cast<const PulseCensusEntry*>(ctx->pulse_copies.p);
+                    pp.t_start = P->time_edges[static_cast<size_t>(e) * K];
+                    pp.tb_start = static_cast<int32_t>(e * K);
+                    rc = generations(PULSE_ITEMS_COPIES, n_copies, pcen, &cen_used);
+                }
+                if (rc < 0) return rc;
+                if (!pcen) break;
+                pp.census = e;
+                HIP_TRY(launch_pulse_census_count(pp, cen_used, st));
+                // copies: at most M + N per batch
+                const uint64_t ccap = (b1 - b0) * pc->target + cen_used;
+                if ((rc = ensure(ctx->pulse_copies, std::max<uint64_t>(ccap, 1) * sizeof(PulseCensusEntry), st)) < 0)
+                    return rc;
+                pp.copies_out = static_cast<PulseCensusEntry*>(ctx->pulse_copies.p);
+                pp.copy_cap = ccap;
+                HIP_TRY(launch_fill_u64(pp.copy_count, 1, 0ull, st));
+                HIP_TRY(launch_pulse_split(pp, cen_used, st));
+                uint64_t w[6];
+                if ((rc = read_words(ctx, misc, 6, w, st)) < 0) return rc;
+                if (w[3] & 0xffffffffull) return fail(MCRNG_ERANGE, "the census copies ran out of room");
+                n_copies = w[5];
+            }
+        }
+    } else if (o.schedule == MCRNG_PULSE_BANK) {
         // Sources go in chunks so that the banks stay within tens of GB.
         const uint64_t chunk = 1ull << 23;
         for (uint64_t c0 = 0; c0 < n_src; c0 += chunk) {
-            const uint64_t c1 = std::min(n_src, c0 + chunk);
-            int cur = 0, nxt = 1;
-            uint64_t n = c1 - c0, in_cap = 0;
-            bool sources = true;
-            while (n > 0) {
-                const uint32_t grid = pulse_bank_grid(pp, sources, static_cast<int>(o.block), n);
-                const uint64_t waves = static_cast<uint64_t>(grid) * o.block / 64;
-                const uint64_t budget = 2 * n;
-                const uint64_t slack = (waves + 1) * (256 + 64 * static_cast<uint64_t>(n_max));
-                const uint64_t ocap = budget + static_cast<uint64_t>(n_max) * n + slack;
-                if ((rc = ensure(ctx->pulse_bank[nxt], ocap * 32, st, 8)) < 0) return rc;
-                pp.src_begin = c0;
-                pp.src_end = c1;
-                if (!sources) pp.in = carve_pulse_bank(ctx->pulse_bank[cur].p, in_cap);
-                pp.n_in = sources ? 0 : n;
-                pp.out = carve_pulse_bank(ctx->pulse_bank[nxt].p, ocap);
-                pp.out_cap = ocap;
-                pp.cont_budget = budget;
-                HIP_TRY(launch_fill_u64(misc, 2, 0ull, st));
-                HIP_TRY(launch_pulse_bank(pp, sources, static_cast<int>(o.block), grid, st));
-                if ((rc = read_u64(ctx, pp.out_count, &n, st)) < 0) return rc;
-                std::swap(cur, nxt);
-                in_cap = ocap;
-                sources = false;
-            }
+            pp.src_begin = c0;
+            pp.src_end = std::min(n_src, c0 + chunk);
+            if ((rc = generations(PULSE_ITEMS_SOURCES, pp.src_end - pp.src_begin, false, nullptr)) < 0) return rc;
         }
     } else {
         const uint32_t grid = pulse_family_grid(static_cast<int>(o.block));
@@ -1141,9 +1251,24 @@ extern "C" int mcrng_run_pulse(mcrng_ctx* ctx, const mcrng_lcg* lcg, const mcrng
     if (d_flux) HIP_TRY(launch_pulse_flux(pp, d_flux, st));
     if (d_diag)
         HIP_TRY(hipMemcpyAsync(d_diag, pp.diag, kNDiag * sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
+    if (d_pop && n_pop)
+        HIP_TRY(hipMemcpyAsync(d_pop, pp.pop, n_pop * sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
     uint64_t flags = 0;
     if ((rc = read_u64(ctx, misc + 3, &flags, st)) < 0) return rc;
     if (flags & 0xffffffffull)
         return fail(MCRNG_ERANGE, "a family stack (opts.stack_depth = %u) or a bank ran out of room", o.stack_depth);
     return warn;
+}
+
+extern "C" int mcrng_run_pulse(mcrng_ctx* ctx, const mcrng_lcg* lcg, const mcrng_pulse_problem* P,
+                               const mcrng_pulse_opts* opts, uint64_t* d_counts, double* d_flux, uint64_t* d_diag,
+                               void* stream) {
+    return run_pulse(ctx, lcg, P, nullptr, opts, d_counts, d_flux, d_diag, nullptr, stream);
+}
+
+extern "C" int mcrng_run_pulse_pc(mcrng_ctx* ctx, const mcrng_lcg* lcg, const mcrng_pulse_problem* P,
+                                  const mcrng_pulse_pc* pc, const mcrng_pulse_opts* opts, uint64_t* d_counts,
+                                  double* d_flux, uint64_t* d_diag, uint64_t* d_pop, void* stream) {
+    if (!pc) return fail(MCRNG_EINVAL, "pc is NULL");
+    return run_pulse(ctx, lcg, P, pc, opts, d_counts, d_flux, d_diag, d_pop, stream);
 }

@@ -34,6 +34,18 @@
 // of every counter when they fit, else one HBM atomic per distinct counter
 // of a wave), so every schedule, launch shape and order gives the same
 // counts.
+//
+// Population control (hash seeding, bank schedule; Sec. "Hierarchical Seed
+// Splitting": one-off hashed values where no full stream is needed): the
+// run is cut into epochs at census times T[(c+1) K].  A particle whose
+// flight reaches the census stops at x + mu (C - t) with its direction and
+// state (staged per wave in LDS like the appends).  Per batch, N particles
+// arrive and M = target leave: arrival X leaves q + [u < r/N] copies
+// (q = floor(M/N), r = M mod N) with the one-off value
+// u = U(hash(X, hash(c+1, hash(B+1, pc_seed)))) compared exactly in
+// integers, and copy k starts the stream hash(k, X) (eq. 5).  All
+// particles of a batch share the epoch's weight, so counts stay integers
+// and the flux applies the weights.
 #include "pulse.hpp"
 
 namespace mcrng {
@@ -48,6 +60,8 @@ struct PParticle {
     uint64_t X;        // stream state
     int32_t tb;        // time bin of t (-1 before the first time edge)
     uint32_t batch;
+    double mu;         // direction: a census copy's, or the last flight's
+    bool has_mu;       // a census copy keeps its direction; others draw it first
 };
 
 enum : uint32_t { PULSE_CENSUS = 0, PULSE_ABSORBED = 1, PULSE_SCATTERED = 2 };
@@ -55,21 +69,32 @@ enum : uint32_t { PULSE_CENSUS = 0, PULSE_ABSORBED = 1, PULSE_SCATTERED = 2 };
 // Runs the particle from its start to its end.  Returns PULSE_CENSUS,
 // PULSE_ABSORBED or PULSE_SCATTERED, with *n the number of particles
 // emerging (0 unless it scattered); p then holds the collision site and the
-// state after the particle's draws.  *draws counts the numbers drawn; a
+// state after the particle's draws (at a census: its start, its state and,
+// with DIR, its direction in p.mu).  *draws counts the numbers drawn; a
 // scored collision sets *tally to its counter index (the caller adds it
-// with wave_tally).
+// with wave_tally).  DIR: the particle may carry a direction (census copies).
+template <bool DIR>
 __device__ __forceinline__ uint32_t pulse_flight(const PulseParams& P, PParticle& p, PulseLane& c,
                                                  uint32_t* draws, uint32_t* n, int64_t* tally) {
     const LcgDev& L = P.lcg;
     *n = 0;
-    p.X = lcg_next(L, p.X);
-    const double mu = 2.0 * to_uniform(L, p.X) - 1.0;
+    double mu;
+    if (DIR && p.has_mu) {
+        mu = p.mu;
+    } else {
+        p.X = lcg_next(L, p.X);
+        mu = 2.0 * to_uniform(L, p.X) - 1.0;
+        *draws += 1;
+    }
     p.X = lcg_next(L, p.X);
     const double tau = -fixed_log(to_uniform(L, p.X));
-    *draws += 2;
+    *draws += 1;
     const double s = tau / P.sigma_t;
     const double tn = p.t + s;
-    if (!(tn < P.t_end)) return PULSE_CENSUS;
+    if (!(tn < P.t_end)) {
+        if (DIR) p.mu = mu;
+        return PULSE_CENSUS;
+    }
     const double step = mu * s;
     p.x = p.x + step;
     p.t = tn;
@@ -90,10 +115,13 @@ __device__ __forceinline__ uint32_t pulse_flight(const PulseParams& P, PParticle
 
 // pulse_flight plus the end counters (kept out of the branches above so that
 // the compiler does not fold them into an indexed array in scratch memory).
+// *census is set when the particle reached the census.
+template <bool DIR = false>
 __device__ __forceinline__ uint32_t pulse_particle(const PulseParams& P, PParticle& p, PulseLane& c,
-                                                   uint32_t* draws, int64_t* tally) {
+                                                   uint32_t* draws, int64_t* tally, bool* census = nullptr) {
     uint32_t n = 0;
-    const uint32_t r = pulse_flight(P, p, c, draws, &n, tally);
+    const uint32_t r = pulse_flight<DIR>(P, p, c, draws, &n, tally);
+    if (census) *census = r == PULSE_CENSUS;
     c.census += static_cast<uint64_t>(r == PULSE_CENSUS);
     c.absorbed += static_cast<uint64_t>(r == PULSE_ABSORBED);
     c.scatters += static_cast<uint64_t>(r == PULSE_SCATTERED);
@@ -247,17 +275,58 @@ __device__ __forceinline__ uint64_t bank_flush(const PulseParams& P, BankStage<B
     return base + count;
 }
 
-template <bool SOURCES, int BLOCK>
+// Per-wave staging of census arrivals (population control), flushed to
+// P.cen with one atomic per flush.
+struct CensusStage {
+    static constexpr uint32_t kCap = 128;   // 28 B per entry
+    double x[kCap];
+    double mu[kCap];
+    uint64_t X[kCap];
+    uint32_t batch[kCap];
+};
+
+__device__ __forceinline__ void census_flush(const PulseParams& P, CensusStage& S, uint32_t count, uint32_t lane) {
+    __builtin_amdgcn_wave_barrier();
+    uint64_t base = 0;
+    if (lane == 0) base = atomicAdd(reinterpret_cast<unsigned long long*>(P.cen_count), count);
+    base = __shfl(base, 0);
+    for (uint32_t i = lane; i < count; i += 64) {
+        const uint64_t o = base + i;
+        if (o < P.cen_cap) {
+            PulseCensusEntry e;
+            e.x = S.x[i];
+            e.mu = S.mu[i];
+            e.X = S.X[i];
+            e.batch = S.batch[i];
+            e.pad = 0;
+            P.cen[o] = e;
+        } else {
+            atomicOr(P.overflow, 1u);
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+// ITEMS: what a launch takes as input (sources, a generation bank, or the
+// census copies starting an epoch).  PC: the launch's census (P.t_end) is a
+// census of population control, whose arrivals go to P.cen.
+template <int ITEMS, bool PC, int BLOCK>
 __global__ void __launch_bounds__(BLOCK) k_pulse_bank(PulseParams P) {
+    constexpr bool SOURCES = ITEMS == PULSE_ITEMS_SOURCES;
+    constexpr bool COPIES = ITEMS == PULSE_ITEMS_COPIES;
+    constexpr bool DIR = PC || COPIES;   // particles may carry a direction
     constexpr uint32_t kChunk = 256;   // items a wave takes per atomic
     using Stage = BankStage<BLOCK>;
     __shared__ Stage stage[BLOCK / 64];
+    __shared__ CensusStage cstage[PC ? BLOCK / 64 : 1];
     extern __shared__ unsigned long long lds_counts[];
     tally_lds_begin<BLOCK>(P, lds_counts);
     PulseLane c;
     const uint64_t n_items = SOURCES ? P.src_end - P.src_begin : P.n_in;
     const uint32_t lane = threadIdx.x & 63u;
     Stage& S = stage[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)];
+    CensusStage& CS = cstage[PC ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0];
+    uint32_t cstaged = 0;              // wave-uniform: entries in CS
     uint64_t wnext = 0, wend = 0;      // wave-uniform: the wave's unassigned items [wnext, wend)
     bool exhausted = false;            // wave-uniform
     uint32_t staged = 0;               // wave-uniform: entries in S
@@ -267,6 +336,8 @@ __global__ void __launch_bounds__(BLOCK) k_pulse_bank(PulseParams P) {
     p.X = 0;
     p.tb = -1;
     p.batch = 0;
+    p.mu = 0.0;
+    p.has_mu = false;
     bool active = false;
     for (;;) {
         const uint64_t need = __ballot(!active);
@@ -292,25 +363,57 @@ __global__ void __launch_bounds__(BLOCK) k_pulse_bank(PulseParams P) {
                 p.t = 0.0;
                 p.tb = P.tb0;
                 c.sources++;
+            } else if (COPIES) {
+                const PulseCensusEntry e = P.copies[j];
+                p.x = e.x;
+                p.mu = e.mu;
+                p.has_mu = true;
+                p.X = e.X;
+                p.batch = e.batch;
+                p.t = P.t_start;
+                p.tb = P.tb_start;
             } else {
                 p.x = P.in.x[j];
                 p.t = P.in.t[j];
                 p.X = P.in.X[j];
                 p.batch = P.in.batch[j];
                 p.tb = P.in.tb[j];
+                p.has_mu = false;
             }
             active = true;
         }
         if (__ballot(active) == 0 && wnext == wend && exhausted) break;
         uint32_t n = 0;
         int64_t tally = -1;
+        bool at_census = false;
         if (active) {
             uint32_t draws = 0;
-            n = pulse_particle(P, p, c, &draws, &tally);
+            n = pulse_particle<DIR>(P, p, c, &draws, &tally, &at_census);
             note_stream(P, c, draws);   // every particle has its own stream
             if (n == 0) active = false;
         }
         wave_tally(P, tally, lane, lds_counts);
+        if (PC) {
+            // census arrivals: the point x + mu (C - t), the direction and the state
+            const uint64_t cm = __ballot(at_census);
+            if (cm != 0) {
+                const uint32_t cnt = static_cast<uint32_t>(__popcll(cm));
+                if (cstaged + cnt > CensusStage::kCap) {
+                    census_flush(P, CS, cstaged, lane);
+                    cstaged = 0;
+                }
+                if (at_census) {
+                    const uint32_t e = cstaged + lane_prefix(cm);
+                    const double rest = P.t_end - p.t;
+                    const double step = p.mu * rest;
+                    CS.x[e] = p.x + step;
+                    CS.mu[e] = p.mu;
+                    CS.X[e] = p.X;
+                    CS.batch[e] = p.batch;
+                }
+                cstaged += cnt;
+            }
+        }
         // siblings (keys 2..n) are banked and the line runs on with key 1
         // while this wave's view of the output count (last flush + staged)
         // is within the budget; past it, a scattering banks all n and ends
@@ -348,13 +451,16 @@ __global__ void __launch_bounds__(BLOCK) k_pulse_bank(PulseParams P) {
             }
         }
         if (n > 0) {
-            if (keep)
+            if (keep) {
                 p.X = murmur_hash(1ull, p.X) & P.lcg.mask;   // the first emerging particle runs on here
-            else
+                p.has_mu = false;
+            } else {
                 active = false;
+            }
         }
     }
     if (staged != 0) bank_flush<BLOCK>(P, S, staged, lane);
+    if (PC && cstaged != 0) census_flush(P, CS, cstaged, lane);
     tally_lds_end<BLOCK>(P, lds_counts);
     flush_lane_counters<BLOCK>(P, c);
 }
@@ -452,8 +558,130 @@ __global__ void __launch_bounds__(BLOCK) k_pulse_family(PulseParams P) {
     flush_lane_counters<BLOCK>(P, c);
 }
 
+// ------------------------------------------------------------ population control
+
+// Arrivals per batch at census P.census: a block-local histogram over the
+// chunk's batches, added to P.pop once per block.
+__global__ void __launch_bounds__(256) k_pulse_census_count(PulseParams P, uint64_t n) {
+    __shared__ uint32_t hist[kPulsePcChunkBatches];
+    for (uint32_t i = threadIdx.x; i < P.n_chunk_batches; i += 256) hist[i] = 0;
+    __syncthreads();
+    for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * 256 + threadIdx.x; i < n;
+         i += static_cast<uint64_t>(gridDim.x) * 256) {
+        const uint32_t k = P.cen[i].batch - P.batch_lo;
+        if (k < P.n_chunk_batches)
+            atomicAdd(&hist[k], 1u);
+        else
+            atomicOr(P.overflow, 2u);
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < P.n_chunk_batches; i += 256)
+        if (hist[i] != 0)
+            atomicAdd(reinterpret_cast<unsigned long long*>(P.pop) +
+                          (static_cast<uint64_t>(P.batch_lo + i) * P.n_census + P.census) * 2,
+                      static_cast<unsigned long long>(hist[i]));
+}
+
+// Copies left by arrival a: q + [u < r/N] with u the one-off value of the
+// arrival's state under the phase seed of (batch, census); the comparison
+// ((S >> (m-53)) + 1) N < r 2^53 is exact in 128 bits.
+__device__ __forceinline__ uint64_t split_copies(const PulseParams& P, const PulseCensusEntry& a) {
+    const LcgDev& L = P.lcg;
+    const uint64_t N = P.pop[(static_cast<uint64_t>(a.batch) * P.n_census + P.census) * 2];
+    const uint64_t M = P.pc_target;
+    const uint64_t q = M / N, r = M - q * N;
+    const uint64_t phase = murmur_hash(P.census + 1ull, murmur_hash(P.first_batch + a.batch + 1ull, P.pc_seed));
+    const uint64_t S = murmur_hash(a.X, phase) & L.mask;
+    const uint64_t j1 = (S >> L.shift53) + 1ull;
+    const uint64_t lo = j1 * N, hi = __umul64hi(j1, N);
+    const uint64_t rlo = r << 53, rhi = r >> 11;
+    const bool extra = hi < rhi || (hi == rhi && lo < rlo);
+    return q + (extra ? 1ull : 0ull);
+}
+
+// Block exclusive scan of one value per thread (BLOCK = 256).
+__device__ __forceinline__ uint64_t block_scan256(uint64_t v, uint64_t* total, uint64_t* s_wave) {
+    const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+    uint64_t incl = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint64_t o = __shfl_up(incl, off);
+        if (lane >= static_cast<uint32_t>(off)) incl += o;
+    }
+    if (lane == 63) s_wave[w] = incl;
+    __syncthreads();
+    uint64_t before = 0, all = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < 4; ++i) {
+        if (i < w) before += s_wave[i];
+        all += s_wave[i];
+    }
+    __syncthreads();
+    *total = all;
+    return before + incl - v;
+}
+
+// The copies of every arrival of census P.census.  A block takes a tile of
+// 256 x 16 arrivals, counts their copies, reserves room for all of them with
+// one atomic, and writes copy k of arrival X as (x, mu, hash(k, X), batch).
+__global__ void __launch_bounds__(256) k_pulse_split(PulseParams P, uint64_t n) {
+    constexpr uint32_t kPer = 16;
+    __shared__ unsigned long long hist[kPulsePcChunkBatches];
+    __shared__ uint64_t s_wave[4];
+    __shared__ uint64_t s_base;
+    for (uint32_t i = threadIdx.x; i < P.n_chunk_batches; i += 256) hist[i] = 0;
+    __syncthreads();
+    const uint64_t tile = 256ull * kPer;
+    for (uint64_t t0 = static_cast<uint64_t>(blockIdx.x) * tile; t0 < n; t0 += static_cast<uint64_t>(gridDim.x) * tile) {
+        uint64_t mine = 0;
+        for (uint32_t t = 0; t < kPer; ++t) {
+            const uint64_t i = t0 + t * 256ull + threadIdx.x;
+            if (i < n) mine += split_copies(P, P.cen[i]);
+        }
+        uint64_t total = 0;
+        uint64_t o = block_scan256(mine, &total, s_wave);
+        if (threadIdx.x == 0) s_base = atomicAdd(reinterpret_cast<unsigned long long*>(P.copy_count), total);
+        __syncthreads();
+        o += s_base;
+        for (uint32_t t = 0; t < kPer; ++t) {
+            const uint64_t i = t0 + t * 256ull + threadIdx.x;
+            if (i >= n) continue;
+            const PulseCensusEntry a = P.cen[i];
+            const uint64_t nk = split_copies(P, a);
+            for (uint64_t k = 1; k <= nk; ++k, ++o) {
+                if (o < P.copy_cap) {
+                    PulseCensusEntry e;
+                    e.x = a.x;
+                    e.mu = a.mu;
+                    e.X = murmur_hash(k, a.X) & P.lcg.mask;
+                    e.batch = a.batch;
+                    e.pad = 0;
+                    P.copies_out[o] = e;
+                } else {
+                    atomicOr(P.overflow, 1u);
+                }
+            }
+            const uint32_t kb = a.batch - P.batch_lo;
+            if (kb < P.n_chunk_batches)
+                atomicAdd(&hist[kb], static_cast<unsigned long long>(nk));
+            else
+                atomicOr(P.overflow, 2u);
+        }
+        __syncthreads();   // s_base and s_wave are reused by the next tile
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < P.n_chunk_batches; i += 256)
+        if (hist[i] != 0)
+            atomicAdd(reinterpret_cast<unsigned long long*>(P.pop) +
+                          (static_cast<uint64_t>(P.batch_lo + i) * P.n_census + P.census) * 2 + 1,
+                      hist[i]);
+}
+
 // ------------------------------------------------------------ flux
 
+// count / (((sigma_t N_b) dx) dt); with population control the count is
+// first multiplied by its epoch's weight w_e (w_0 = 1,
+// w_{c+1} = (w_c N_c) / M, N_c the batch's arrivals at census c).
 __global__ void __launch_bounds__(256) k_pulse_flux(PulseParams P, double* flux) {
     const uint64_t n = static_cast<uint64_t>(P.n_batches) * P.n_time_bins;
     const double dx = P.x_hi - P.x_lo;
@@ -463,7 +691,15 @@ __global__ void __launch_bounds__(256) k_pulse_flux(PulseParams P, double* flux)
         const uint32_t k = static_cast<uint32_t>(i % P.n_time_bins);
         const double dt = P.t_edges[k + 1] - P.t_edges[k];
         const double den = ((P.sigma_t * nb) * dx) * dt;
-        flux[i] = static_cast<double>(P.counts[i]) / den;
+        if (P.n_census == 0) {
+            flux[i] = static_cast<double>(P.counts[i]) / den;
+        } else {
+            const uint64_t b = i / P.n_time_bins;
+            double w = 1.0;
+            for (uint32_t e = 0; e < P.n_census && k >= (e + 1) * P.census_every; ++e)
+                w = (w * static_cast<double>(P.pop[(b * P.n_census + e) * 2])) / static_cast<double>(P.pc_target);
+            flux[i] = (static_cast<double>(P.counts[i]) * w) / den;
+        }
     }
 }
 
@@ -476,50 +712,86 @@ static int device_cus() {
     return cus > 0 ? cus : 256;
 }
 
-template <bool SOURCES, int BLOCK>
-static uint32_t bank_grid_b(uint64_t items, size_t lds) {
+template <int BLOCK>
+static const void* bank_kernel_b(int items, bool pc) {
+    switch (items) {
+        case PULSE_ITEMS_SOURCES:
+            return pc ? reinterpret_cast<const void*>(k_pulse_bank<PULSE_ITEMS_SOURCES, true, BLOCK>)
+                      : reinterpret_cast<const void*>(k_pulse_bank<PULSE_ITEMS_SOURCES, false, BLOCK>);
+        case PULSE_ITEMS_COPIES:
+            return pc ? reinterpret_cast<const void*>(k_pulse_bank<PULSE_ITEMS_COPIES, true, BLOCK>)
+                      : reinterpret_cast<const void*>(k_pulse_bank<PULSE_ITEMS_COPIES, false, BLOCK>);
+        default:
+            return pc ? reinterpret_cast<const void*>(k_pulse_bank<PULSE_ITEMS_BANK, true, BLOCK>)
+                      : reinterpret_cast<const void*>(k_pulse_bank<PULSE_ITEMS_BANK, false, BLOCK>);
+    }
+}
+
+static const void* bank_kernel(int block, int items, bool pc) {
+    switch (block) {
+        case 64: return bank_kernel_b<64>(items, pc);
+        case 128: return bank_kernel_b<128>(items, pc);
+        case 512: return bank_kernel_b<512>(items, pc);
+        case 1024: return bank_kernel_b<1024>(items, pc);
+        default: return bank_kernel_b<256>(items, pc);
+    }
+}
+
+static int bank_block(int block) {
+    return (block == 64 || block == 128 || block == 512 || block == 1024) ? block : 256;
+}
+
+size_t pulse_tally_lds_bytes(const PulseParams& p) { return p.lds_tally ? 8ull * p.n_counters : 0; }
+
+static uint64_t bank_items(const PulseParams& p, int items_kind) {
+    return items_kind == PULSE_ITEMS_SOURCES ? p.src_end - p.src_begin : p.n_in;
+}
+
+uint32_t pulse_bank_grid(const PulseParams& p, int items_kind, bool pc, int block, uint64_t items) {
     // resident blocks only: waves keep taking 256-item chunks, so a launch
     // ends with one tail instead of one per wave
+    block = bank_block(block);
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_pulse_bank<SOURCES, BLOCK>),
-                                                     BLOCK, lds) != hipSuccess || per_cu < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bank_kernel(block, items_kind, pc), block,
+                                                     pulse_tally_lds_bytes(p)) != hipSuccess ||
+        per_cu < 1)
         per_cu = 1;
-    uint64_t blocks = (items + 4 * BLOCK - 1) / (4 * BLOCK);   // a 256-item chunk per wave at least
+    uint64_t blocks = (items + 4ull * block - 1) / (4ull * block);   // a 256-item chunk per wave at least
     const uint64_t cap = static_cast<uint64_t>(device_cus()) * static_cast<uint64_t>(per_cu);
     if (blocks > cap) blocks = cap;
     if (blocks < 1) blocks = 1;
     return static_cast<uint32_t>(blocks);
 }
 
-size_t pulse_tally_lds_bytes(const PulseParams& p) { return p.lds_tally ? 8ull * p.n_counters : 0; }
-
-uint32_t pulse_bank_grid(const PulseParams& p, bool sources, int block, uint64_t items) {
-    const size_t lds = pulse_tally_lds_bytes(p);
-    switch (block) {
-        case 64: return sources ? bank_grid_b<true, 64>(items, lds) : bank_grid_b<false, 64>(items, lds);
-        case 128: return sources ? bank_grid_b<true, 128>(items, lds) : bank_grid_b<false, 128>(items, lds);
-        case 512: return sources ? bank_grid_b<true, 512>(items, lds) : bank_grid_b<false, 512>(items, lds);
-        case 1024: return sources ? bank_grid_b<true, 1024>(items, lds) : bank_grid_b<false, 1024>(items, lds);
-        default: return sources ? bank_grid_b<true, 256>(items, lds) : bank_grid_b<false, 256>(items, lds);
-    }
+hipError_t launch_pulse_bank(const PulseParams& p, int items_kind, bool pc, int block, uint32_t grid,
+                             hipStream_t st) {
+    if (bank_items(p, items_kind) == 0) return hipSuccess;
+    block = bank_block(block);
+    PulseParams arg = p;
+    void* args[] = {&arg};
+    return hipLaunchKernel(bank_kernel(block, items_kind, pc), dim3(grid), dim3(block), args,
+                           pulse_tally_lds_bytes(p), st);
 }
 
-template <bool SOURCES, int BLOCK>
-static hipError_t launch_bank_b(const PulseParams& p, uint32_t grid, hipStream_t st) {
-    hipLaunchKernelGGL((k_pulse_bank<SOURCES, BLOCK>), dim3(grid), dim3(BLOCK), pulse_tally_lds_bytes(p), st, p);
+static uint32_t stream_grid(uint64_t work, uint64_t per_block) {
+    uint64_t blocks = (work + per_block - 1) / per_block;
+    const uint64_t cap = static_cast<uint64_t>(device_cus()) * 8;
+    if (blocks > cap) blocks = cap;
+    if (blocks < 1) blocks = 1;
+    return static_cast<uint32_t>(blocks);
+}
+
+hipError_t launch_pulse_census_count(const PulseParams& p, uint64_t n_arrivals, hipStream_t st) {
+    if (n_arrivals == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pulse_census_count, dim3(stream_grid(n_arrivals, 256ull * 16)), dim3(256), 0, st, p,
+                       n_arrivals);
     return hipGetLastError();
 }
 
-hipError_t launch_pulse_bank(const PulseParams& p, bool sources, int block, uint32_t grid, hipStream_t st) {
-    const uint64_t items = sources ? p.src_end - p.src_begin : p.n_in;
-    if (items == 0) return hipSuccess;
-    switch (block) {
-        case 64: return sources ? launch_bank_b<true, 64>(p, grid, st) : launch_bank_b<false, 64>(p, grid, st);
-        case 128: return sources ? launch_bank_b<true, 128>(p, grid, st) : launch_bank_b<false, 128>(p, grid, st);
-        case 512: return sources ? launch_bank_b<true, 512>(p, grid, st) : launch_bank_b<false, 512>(p, grid, st);
-        case 1024: return sources ? launch_bank_b<true, 1024>(p, grid, st) : launch_bank_b<false, 1024>(p, grid, st);
-        default: return sources ? launch_bank_b<true, 256>(p, grid, st) : launch_bank_b<false, 256>(p, grid, st);
-    }
+hipError_t launch_pulse_split(const PulseParams& p, uint64_t n_arrivals, hipStream_t st) {
+    if (n_arrivals == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pulse_split, dim3(stream_grid(n_arrivals, 256ull * 16)), dim3(256), 0, st, p, n_arrivals);
+    return hipGetLastError();
 }
 
 template <bool HASH, int BLOCK>

@@ -30,6 +30,14 @@ struct PulseStackEntry {
     uint16_t next, n;
 };
 
+// A census arrival, or a census copy, of a population-controlled run (32 B).
+struct PulseCensusEntry {
+    double x, mu;        // census point and direction
+    uint64_t X;          // arrival: stream state after its draws; copy: its start state
+    uint32_t batch;      // batch of the run (0-based)
+    uint32_t pad;
+};
+
 struct PulseParams {
     LcgDev lcg;
     SeedDev seed;            // hash: base = the global seed s; stride: skip table etc.
@@ -59,13 +67,40 @@ struct PulseParams {
     uint32_t* overflow;      // set if an append or a stack push found no room
     uint64_t* family_counter;
     PulseStackEntry* stack;  // family schedule: stack_depth entries per lane
+    // population control (t_end is then the census time of the epoch)
+    PulseCensusEntry* cen;   // census arrivals of the epoch
+    uint64_t* cen_count;
+    uint64_t cen_cap;
+    const PulseCensusEntry* copies;   // copies starting the epoch (taken as items)
+    double t_start;          // the census time the copies start at
+    int32_t tb_start;        // its time bin
+    uint32_t census;         // split: census index c
+    uint32_t n_census;       // census points of the run
+    uint32_t census_every;   // time bins per epoch (census c at edge (c+1) census_every)
+    uint32_t batch_lo;       // split / count: first batch of the chunk (LDS histogram base)
+    uint32_t n_chunk_batches;
+    uint64_t pc_target, pc_seed;
+    uint64_t* pop;           // n_batches x n_census x 2: arrivals, copies
+    uint64_t* copy_count;
+    uint64_t copy_cap;
+    PulseCensusEntry* copies_out;
 };
+
+enum PulseItems : int { PULSE_ITEMS_SOURCES = 0, PULSE_ITEMS_BANK = 1, PULSE_ITEMS_COPIES = 2 };
+constexpr uint32_t kPulsePcChunkBatches = 4096;   // batches per chunk of a population-controlled run
 
 // Bank launches: the grid (resident blocks, at most one 256-item chunk per
 // wave) is chosen first, so that the caller can size the output for it.
-uint32_t pulse_bank_grid(const PulseParams& p, bool sources, int block, uint64_t items);
+// `items` is a PulseItems value; `pc`: the launch's census is a census of
+// population control (arrivals are banked in p.cen).
+uint32_t pulse_bank_grid(const PulseParams& p, int items_kind, bool pc, int block, uint64_t items);
 constexpr uint32_t kPulseLdsCounters = 2048;   // block-local tally copies up to this many counters (16 KiB)
-hipError_t launch_pulse_bank(const PulseParams& p, bool sources, int block, uint32_t grid, hipStream_t st);
+hipError_t launch_pulse_bank(const PulseParams& p, int items_kind, bool pc, int block, uint32_t grid,
+                             hipStream_t st);
+// Population control at census p.census: arrival counts per batch into
+// p.pop, then the copies of every arrival into p.copies_out.
+hipError_t launch_pulse_census_count(const PulseParams& p, uint64_t n_arrivals, hipStream_t st);
+hipError_t launch_pulse_split(const PulseParams& p, uint64_t n_arrivals, hipStream_t st);
 uint32_t pulse_family_grid(int block);
 hipError_t launch_pulse_family(const PulseParams& p, int block, uint32_t grid, hipStream_t st);
 hipError_t launch_pulse_flux(const PulseParams& p, double* flux, hipStream_t st);

@@ -34,7 +34,7 @@ def test_exports_every_declared_symbol(M):
     lib = M.lib()
     for s in syms:
         assert hasattr(lib, s), s
-    assert lib.mcrng_version() == 1
+    assert lib.mcrng_version() == 2
 
 
 def test_host_validation_without_gpu(M):
@@ -94,6 +94,40 @@ def test_pulse_host_validation_without_gpu(M):
     assert rc == B.EINVAL and "hash" in msg
     rc, msg = call(good, block=96)
     assert rc == B.EINVAL and "block" in msg
+
+
+def test_pulse_pc_host_validation_without_gpu(M):
+    """mcrng_run_pulse_pc checks the population-control settings (hash
+    seeding, the bank schedule, a target, a census interval) before it
+    touches a context or the GPU."""
+    import workloads as W
+    from paper_2403_06362_amd import _binding as B
+    lib = B.lib()
+    L = B.make_lcg(W.Lcg())
+
+    def call(prob, pc=True, **opts):
+        st, keep = B.make_pulse_problem(prob)
+        p = C.byref(B.make_pulse_pc(prob)) if pc else None
+        o = B.make_pulse_opts(**opts)
+        rc = lib.mcrng_run_pulse_pc(None, C.byref(L), C.byref(st), p, C.byref(o), None, None, None, None, None)
+        return rc, lib.mcrng_last_error().decode()
+
+    good = W.pulse_pc(n_batches=2, per_batch=3)
+    assert call(good) == (B.EINVAL, "ctx is NULL")
+    for bad, word in ((good.with_(census_every=0), "census_every"), (good.with_(pc_target=0), "target"),
+                      (good.with_(pc_target=(1 << 40) + 1), "target"),
+                      (good.with_(seeding=W.stride_seeding()), "hash")):
+        rc, msg = call(bad)
+        assert rc == B.EINVAL and word in msg, (word, msg)
+    rc, msg = call(good, pc=False)
+    assert rc == B.EINVAL and "pc" in msg
+    rc, msg = call(good, schedule=B.PULSE_FAMILY)
+    assert rc == B.EINVAL and "bank" in msg
+    pc = B.make_pulse_pc(good)
+    pc.reserved[1] = 7
+    st, keep = B.make_pulse_problem(good)
+    rc = lib.mcrng_run_pulse_pc(None, C.byref(L), C.byref(st), C.byref(pc), None, None, None, None, None, None)
+    assert rc == B.EINVAL and "reserved" in lib.mcrng_last_error().decode()
 
 
 def test_uniforms_host_validation_without_gpu(M):
