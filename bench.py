@@ -19,14 +19,22 @@ Also reported, each timed separately after the headline loop:
                 medium, secondaries seeded on demand), 1000 x 1000 sources:
                 hash-seeded particle banks vs depth-first families, and the
                 paper's normality study at full size (30 x 1000 batches)
+  pulse_population_control
+                the same problem with a census every 5 time units that
+                brings each batch back to its source count (one-off hashed
+                values, copies seeded by eq. 5), against the uncontrolled
+                run: time, agreement, figure of merit per time bin
   roofline      of the draw kernel: integer VALU lane-ops per launch over the
                 average kernel duration (HIP events on the launch stream)
-  cpu_baseline  the CPU oracle on the host cores, same workload
+  cpu_baseline  the CPU oracle on the host cores: the same draw workload,
+                256 sampled streams of the GPU checksums recomputed, and
+                64-batch samples of the pulse problems (the only part of
+                the benchmark that uses the oracle)
 With --full, the 512-problem batched set (persistent + graph, FP64 and
 FP32, against one launch per problem) and the 2e8-history multi-region
 slab are added.
 
-Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--full]
+Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 10] [--full] [--no-cpu]
 """
 from __future__ import annotations
 
@@ -255,9 +263,8 @@ def main():
     log("uniforms: 2^26 streams x 16 numbers")
     uni = uniforms_leg(M, W, torch, dev, lcg, n, 16, args.warmup, max(3, args.steps // 4))
 
-    import oracle
-    ok_h = spot_check(oracle, W, lcg, "hash", counts, hsh["chk"].view(torch.int64).cpu().numpy().view(np.uint64))
-    ok_s = spot_check(oracle, W, lcg, "stride", counts, strd["chk"].view(torch.int64).cpu().numpy().view(np.uint64))
+    chk_hash = hsh["chk"].view(torch.int64).cpu().numpy().view(np.uint64)
+    chk_stride = strd["chk"].view(torch.int64).cpu().numpy().view(np.uint64)
 
     digits = max(1, int(np.ceil(np.log2(n) / 4)))
     ops_hash = OPS_PER_DRAW * total_draws + OPS_PER_HASH_SEED * n
@@ -287,7 +294,6 @@ def main():
                            "kernel_ms": strd["kernel_ms"],
                            "int_valu_frac": ops_stride / (strd["kernel_ms"] * 1e-3) / INT_VALU_PEAK,
                            "hash_over_stride": strd["ms_per_step"] / hsh["ms_per_step"]},
-        "verified_vs_oracle": {"hash_sampled_streams": ok_h, "stride_sampled_streams": ok_s},
         "uniforms": uni,
         "roofline": roofline,
     }
@@ -311,14 +317,17 @@ def main():
         tr["hash_over_stride"] = legs["stride_fp64"]["ms"] / legs["hash_fp64"]["ms"]
         out["histories_per_s"] = legs["hash_fp64"]["histories_per_s"]
         out["transport"] = tr
-        out["pulse"] = pulse_leg(M, W, torch, lcg, ctx, oracle)
+        out["pulse"] = pulse_leg(M, W, torch, lcg, ctx)
+        out["pulse_population_control"] = pulse_pc_leg(M, W, torch, lcg, ctx)
         if args.full:
             out["batched"] = batched_leg(M, W, torch, lcg, ctx)
             out["multi_region"] = multi_region_leg(M, W, torch, lcg, ctx)
         ctx.close()
 
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(oracle, W, lcg, counts)
+        # the only place the benchmark touches the CPU oracle
+        import oracle
+        out["cpu_baseline"] = cpu_baseline(oracle, W, lcg, counts, chk_hash, chk_stride, out)
 
     print(json.dumps(out), flush=True)
 
@@ -420,7 +429,63 @@ def pulse_run(M, torch, lcg, ctx, prob, schedule, reps):
     return float(np.median(times)), flux.cpu().numpy(), d
 
 
-def pulse_leg(M, W, torch, lcg, ctx, oracle):
+def pulse_pc_run(M, torch, lcg, ctx, prob, reps):
+    nt = len(prob.time_edges) - 1
+    nc = M.pulse_n_census(prob)
+    counts = torch.empty((prob.n_batches, nt), dtype=torch.uint64, device="cuda:0")
+    flux = torch.empty((prob.n_batches, nt), dtype=torch.float64, device="cuda:0")
+    diag = torch.empty(M.NDIAG, dtype=torch.uint64, device="cuda:0")
+    pop = torch.empty((prob.n_batches, nc, 2), dtype=torch.uint64, device="cuda:0")
+    times = []
+    for _ in range(reps):
+        ctx.run_pulse_pc(lcg, prob, counts, flux, diag, pop)
+        times.append(ctx.last_run_ms())
+    d = dict(zip(M.PULSE_DIAG_NAMES, (int(v) for v in diag.view(torch.int64).cpu().numpy())))
+    return float(np.median(times)), flux.cpu().numpy(), d, pop.view(torch.int64).cpu().numpy()
+
+
+def pulse_pc_leg(M, W, torch, lcg, ctx):
+    """Population control with one-off hashed values: the pulse problem with
+    a census every 5 time units after which each batch again holds its
+    source count on average (copies seeded by eq. 5).  Timed against the
+    uncontrolled run; the flux of the two agrees in distribution, and the
+    figure of merit 1 / (variance x time) of the batch-mean flux compares
+    them per time bin."""
+    out = {"workload": "pulse problem (1000 x 1000 sources, census t=20) with population control at t=5,10,15 "
+                       "to 1000 particles per batch",
+           "few_sources_workload": "4096 sources to t=60 with population control every 5 time units to 4096"}
+    p = W.pulse_pc(census_every=5)
+    log("pulse population control")
+    ms_pc, f_pc, d, pop = pulse_pc_run(M, torch, lcg, ctx, p, 3)
+    ms_an, f_an, d_an = pulse_run(M, torch, lcg, ctx, W.pulse(W.hash_seeding()), M.PULSE_BANK, 3)
+    copies = int(pop[:, :, 1].sum())
+    particles = d["sources"] + d["secondaries"] + copies
+    m_pc, m_an = f_pc.mean(0), f_an.mean(0)
+    v_pc, v_an = f_pc.var(0, ddof=1) / f_pc.shape[0], f_an.var(0, ddof=1) / f_an.shape[0]
+    z = (m_pc - m_an) / np.sqrt(v_pc + v_an)
+    fom = (v_an * ms_an) / (v_pc * ms_pc)
+    out["paper_problem"] = {
+        "ms": ms_pc, "uncontrolled_ms": ms_an, "particles": particles,
+        "uncontrolled_particles": d_an["sources"] + d_an["secondaries"],
+        "particles_per_s": particles / (ms_pc * 1e-3), "collisions_per_s": d["collisions"] / (ms_pc * 1e-3),
+        "arrivals_per_batch_at_census": [float(v) for v in pop[:, :, 0].mean(0)],
+        "copies_per_batch_at_census": [float(v) for v in pop[:, :, 1].mean(0)],
+        "max_abs_z_vs_uncontrolled": float(np.max(np.abs(z))),
+        "fom_ratio_per_time_bin": [float(v) for v in fom]}
+    few = W.pulse_few_sources().with_(census_every=5, pc_target=4096)
+    log("pulse population control, few sources")
+    ms_f, _, d_f, pop_f = pulse_pc_run(M, torch, lcg, ctx, few, 3)
+    ms_fa, _, d_fa = pulse_run(M, torch, lcg, ctx, W.pulse_few_sources(), M.PULSE_BANK, 3)
+    out["few_sources"] = {
+        "ms": ms_f, "uncontrolled_ms": ms_fa,
+        "particles": d_f["sources"] + d_f["secondaries"] + int(pop_f[:, :, 1].sum()),
+        "uncontrolled_particles": d_fa["sources"] + d_fa["secondaries"],
+        "arrivals_at_census": [int(v) for v in pop_f[0, :, 0]]}
+    out["sources_per_s"] = p.n_sources / (ms_pc * 1e-3)
+    return out
+
+
+def pulse_leg(M, W, torch, lcg, ctx):
     """The paper's test problem: a pulse in an infinite medium (c = 0.4,
     nu = 2.75, census t = 20), 1000 batches x 1000 sources; secondaries
     seeded on demand by hashing (eq. 5) or drawing from their source's
@@ -448,15 +513,6 @@ def pulse_leg(M, W, torch, lcg, ctx, oracle):
     out["few_sources_hash_bank_over_stride_family"] = (out["few_sources_stride_family"]["ms"] /
                                                        out["few_sources_hash_bank"]["ms"])
     out["hash_family_over_stride_family"] = out["stride_family"]["ms"] / out["hash_family"]["ms"]
-    # CPU oracle on a sample of the same problem (threads over batches)
-    threads = min(16, os.cpu_count() or 1)
-    sample = p.with_(n_batches=64)
-    t0 = time.perf_counter()
-    oracle.pulse(sample, lcg, threads=threads)
-    dt = time.perf_counter() - t0
-    out["cpu_oracle"] = {"sources_per_s": sample.n_sources / dt, "threads": threads,
-                         "sample": "64 batches x 1000 sources, hash seeding"}
-    out["gpu_over_cpu_oracle"] = out["hash_bank"]["sources_per_s"] / out["cpu_oracle"]["sources_per_s"]
 
     study = {}
     for kind in ("hash", "stride"):
@@ -475,9 +531,14 @@ def pulse_leg(M, W, torch, lcg, ctx, oracle):
     return out
 
 
-def cpu_baseline(oracle, W, lcg, counts):
+def cpu_baseline(oracle, W, lcg, counts, chk_hash, chk_stride, out):
+    """The CPU oracle on the host cores: the headline draw workload (timed),
+    sampled streams of the GPU's checksums recomputed, and bounded samples
+    of the pulse problems (timed, beside the GPU's rates)."""
     threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     threads = max(1, min(threads, 16))
+    ok_h = spot_check(oracle, W, lcg, "hash", counts, chk_hash)
+    ok_s = spot_check(oracle, W, lcg, "stride", counts, chk_stride)
     ns = counts.size
     sample = counts[:ns]
     draws = int(sample.sum(dtype=np.uint64))
@@ -488,9 +549,27 @@ def cpu_baseline(oracle, W, lcg, counts):
         oracle.seed_and_draw(lcg, W.hash_seeding(), sample, threads=threads)
         walls.append(time.perf_counter() - t0)
     dt = float(np.median(walls))
-    return {"value": draws / dt, "unit": "draws/s", "cores": threads, "kind": "oracle",
-            "sample": "the whole workload (%d streams, %d draws), hash seeding, 3 passes, median %.2f s wall "
-                      "(%.0f s of CPU work in total)" % (ns, draws, dt, sum(walls) * threads)}
+    res = {"value": draws / dt, "unit": "draws/s", "cores": threads, "kind": "oracle",
+           "sample": "the whole workload (%d streams, %d draws), hash seeding, 3 passes, median %.2f s wall "
+                     "(%.0f s of CPU work in total)" % (ns, draws, dt, sum(walls) * threads),
+           "gpu_checksums_match_on_256_sampled_streams": {"hash": ok_h, "stride": ok_s}}
+    if "pulse" in out:
+        sample = W.pulse(W.hash_seeding(), n_batches=64)
+        log("cpu baseline: oracle pulse problem, 64 batches")
+        t0 = time.perf_counter()
+        oracle.pulse(sample, lcg, threads=threads)
+        rate = sample.n_sources / (time.perf_counter() - t0)
+        res["pulse"] = {"sources_per_s": rate, "threads": threads, "sample": "64 batches x 1000 sources, hash seeding",
+                        "gpu_bank_over_cpu": out["pulse"]["hash_bank"]["sources_per_s"] / rate}
+        sample = W.pulse_pc(n_batches=64, census_every=5)
+        log("cpu baseline: oracle pulse problem with population control, 64 batches")
+        t0 = time.perf_counter()
+        oracle.pulse_pc(sample, lcg, threads=threads)
+        rate = sample.n_sources / (time.perf_counter() - t0)
+        res["pulse_population_control"] = {
+            "sources_per_s": rate, "threads": threads, "sample": "64 batches x 1000 sources, census every 5",
+            "gpu_over_cpu": out["pulse_population_control"]["sources_per_s"] / rate}
+    return res
 
 
 if __name__ == "__main__":
