@@ -282,20 +282,28 @@ enum { MCRNG_PULSE_AUTO = 0, MCRNG_PULSE_BANK = 1, MCRNG_PULSE_FAMILY = 2 };
 
 /* Options (zero = default).  No option changes a result bit: counts are
  * integers.
- *   schedule     MCRNG_PULSE_BANK (hash seeding only): particles run one
- *                flight per launch from a particle bank, in any order, the
- *                emerging particles going to the next generation's bank;
+ *   schedule     MCRNG_PULSE_BANK (hash seeding only): generations; a
+ *                launch runs the lines of descent of its input particles
+ *                (the first particle emerging from a scattering at once) in
+ *                any order and banks the siblings for the next launch;
  *                MCRNG_PULSE_FAMILY: one source family per lane, depth
  *                first; AUTO: bank for hash seeding, family for stride
  *   block        threads per block: 64, 128, 256, 512 or 1024
  *   stack_depth  family schedule: stack entries per lane (default 128; an
  *                entry holds the siblings of one scattering on the current
- *                line of descent) */
+ *                line of descent)
+ *   finish_div   bank schedule: once a generation is smaller than the one
+ *                before it, at most 1/finish_div of the largest of its chain
+ *                and at most 65536 particles, one launch runs the rest depth
+ *                first per lane, up to 64 particles per banked particle
+ *                (default 1: the first shrinking generation of that size;
+ *                0xffffffff: never) */
 typedef struct {
     uint32_t schedule;
     uint32_t block;
     uint32_t stack_depth;
-    uint32_t reserved[5];        /* must be 0 */
+    uint32_t finish_div;
+    uint32_t reserved[4];        /* must be 0 */
 } mcrng_pulse_opts;
 
 /* Diagnostics of a pulse run, MCRNG_NDIAG uint64 words in this order; sums

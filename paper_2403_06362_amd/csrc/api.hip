@@ -1049,6 +1049,7 @@ static int run_pulse(mcrng_ctx* ctx, const mcrng_lcg* lcg, const mcrng_pulse_pro
     if (opts) o = *opts;
     for (uint32_t r : o.reserved)
         if (r) return fail(MCRNG_EINVAL, "opts.reserved must be 0");
+    if (o.finish_div == 0) o.finish_div = 1;
     const bool hash = P->seeding.kind == MCRNG_SEED_HASH;
     const uint64_t n_src = static_cast<uint64_t>(P->n_batches) * P->per_batch;
     if (o.block == 0) o.block = 256;
@@ -1146,10 +1147,52 @@ static int run_pulse(mcrng_ctx* ctx, const mcrng_lcg* lcg, const mcrng_pulse_pro
     // iteration's appends per wave.  With `pcen` (a census of population
     // control ends the epoch) every line ends at most once at the census, so
     // the census bank grows by at most the launch's items.
+    // The tail of a chain (a generation that shrank to at most 1/finish_div
+    // of the largest, and to at most kFinishItems) is finished by one launch
+    // that runs each particle's descendants depth first (up to kFinishBudget
+    // particles each; the rest, if any, is the next generation).
+    constexpr uint64_t kFinishItems = 65536;
+    constexpr uint32_t kFinishBudget = 64, kFinishDepth = 32;
     auto generations = [&](int kind, uint64_t n, bool pcen, uint64_t* cen_used) -> int {
         int cur = 0, nxt = 1;
-        uint64_t in_cap = 0;
+        uint64_t in_cap = 0, peak = 0, prev = ~0ull;
         while (n > 0) {
+            peak = std::max(peak, n);
+            const bool fin = kind == PULSE_ITEMS_BANK && o.finish_div != 0xffffffffu && n <= kFinishItems &&
+                             n < prev && n * o.finish_div <= peak;
+            prev = n;
+            if (fin) {
+                const uint32_t grid = pulse_finish_grid(n);
+                const uint64_t lanes = static_cast<uint64_t>(grid) * 256;
+                int r = ensure(ctx->pulse_stack, lanes * kFinishDepth * sizeof(PulseStackEntry), st);
+                if (r < 0) return r;
+                const uint64_t ocap = n * (kFinishBudget + kFinishDepth + 1) * static_cast<uint64_t>(n_max) + 64;
+                if ((r = ensure(ctx->pulse_bank[nxt], ocap * 32, st, 8)) < 0) return r;
+                if (pcen) {
+                    r = ensure_keep(ctx->pulse_census, *cen_used * sizeof(PulseCensusEntry),
+                                    (*cen_used + n * kFinishBudget) * sizeof(PulseCensusEntry), st);
+                    if (r < 0) return r;
+                    pp.cen = static_cast<PulseCensusEntry*>(ctx->pulse_census.p);
+                    pp.cen_cap = ctx->pulse_census.cap / sizeof(PulseCensusEntry);
+                }
+                pp.in = carve_pulse_bank(ctx->pulse_bank[cur].p, in_cap);
+                pp.n_in = n;
+                pp.out = carve_pulse_bank(ctx->pulse_bank[nxt].p, ocap);
+                pp.out_cap = ocap;
+                pp.stack = static_cast<PulseStackEntry*>(ctx->pulse_stack.p);
+                pp.stack_depth = kFinishDepth;
+                pp.lane_budget = kFinishBudget;
+                HIP_TRY(launch_fill_u64(misc, 3, 0ull, st));
+                HIP_TRY(launch_pulse_finish(pp, pcen, grid, st));
+                uint64_t w[5];
+                if ((r = read_words(ctx, misc, 5, w, st)) < 0) return r;
+                if (w[3] & 0xffffffffull) return fail(MCRNG_ERANGE, "a particle bank ran out of room");
+                n = w[0];
+                if (pcen) *cen_used = w[4];
+                std::swap(cur, nxt);
+                in_cap = ocap;
+                continue;
+            }
             const uint32_t grid = pulse_bank_grid(pp, kind, pcen, static_cast<int>(o.block), n);
             const uint64_t waves = static_cast<uint64_t>(grid) * o.block / 64;
             const uint64_t budget = 2 * n;

@@ -307,6 +307,51 @@ __device__ __forceinline__ void census_flush(const PulseParams& P, CensusStage& 
     __builtin_amdgcn_wave_barrier();
 }
 
+// Stages the wave's census arrivals (lanes with at_census) in CS: the point
+// x + mu (C - t), the direction and the state.  Called by the whole wave.
+__device__ __forceinline__ void census_stage(const PulseParams& P, CensusStage& CS, uint32_t& cstaged,
+                                             bool at_census, const PParticle& p, uint32_t lane) {
+    const uint64_t cm = __ballot(at_census);
+    if (cm == 0) return;
+    const uint32_t cnt = static_cast<uint32_t>(__popcll(cm));
+    if (cstaged + cnt > CensusStage::kCap) {
+        census_flush(P, CS, cstaged, lane);
+        cstaged = 0;
+    }
+    if (at_census) {
+        const uint32_t e = cstaged + lane_prefix(cm);
+        const double rest = P.t_end - p.t;
+        const double step = p.mu * rest;
+        CS.x[e] = p.x + step;
+        CS.mu[e] = p.mu;
+        CS.X[e] = p.X;
+        CS.batch[e] = p.batch;
+    }
+    cstaged += cnt;
+}
+
+// Loads input item j of a bank or copies launch into p.
+template <int ITEMS>
+__device__ __forceinline__ void load_item(const PulseParams& P, uint64_t j, PParticle& p) {
+    if (ITEMS == PULSE_ITEMS_COPIES) {
+        const PulseCensusEntry e = P.copies[j];
+        p.x = e.x;
+        p.mu = e.mu;
+        p.has_mu = true;
+        p.X = e.X;
+        p.batch = e.batch;
+        p.t = P.t_start;
+        p.tb = P.tb_start;
+    } else {
+        p.x = P.in.x[j];
+        p.t = P.in.t[j];
+        p.X = P.in.X[j];
+        p.batch = P.in.batch[j];
+        p.tb = P.in.tb[j];
+        p.has_mu = false;
+    }
+}
+
 // ITEMS: what a launch takes as input (sources, a generation bank, or the
 // census copies starting an epoch).  PC: the launch's census (P.t_end) is a
 // census of population control, whose arrivals go to P.cen.
@@ -363,22 +408,8 @@ __global__ void __launch_bounds__(BLOCK) k_pulse_bank(PulseParams P) {
                 p.t = 0.0;
                 p.tb = P.tb0;
                 c.sources++;
-            } else if (COPIES) {
-                const PulseCensusEntry e = P.copies[j];
-                p.x = e.x;
-                p.mu = e.mu;
-                p.has_mu = true;
-                p.X = e.X;
-                p.batch = e.batch;
-                p.t = P.t_start;
-                p.tb = P.tb_start;
             } else {
-                p.x = P.in.x[j];
-                p.t = P.in.t[j];
-                p.X = P.in.X[j];
-                p.batch = P.in.batch[j];
-                p.tb = P.in.tb[j];
-                p.has_mu = false;
+                load_item<ITEMS>(P, j, p);
             }
             active = true;
         }
@@ -393,27 +424,7 @@ __global__ void __launch_bounds__(BLOCK) k_pulse_bank(PulseParams P) {
             if (n == 0) active = false;
         }
         wave_tally(P, tally, lane, lds_counts);
-        if (PC) {
-            // census arrivals: the point x + mu (C - t), the direction and the state
-            const uint64_t cm = __ballot(at_census);
-            if (cm != 0) {
-                const uint32_t cnt = static_cast<uint32_t>(__popcll(cm));
-                if (cstaged + cnt > CensusStage::kCap) {
-                    census_flush(P, CS, cstaged, lane);
-                    cstaged = 0;
-                }
-                if (at_census) {
-                    const uint32_t e = cstaged + lane_prefix(cm);
-                    const double rest = P.t_end - p.t;
-                    const double step = p.mu * rest;
-                    CS.x[e] = p.x + step;
-                    CS.mu[e] = p.mu;
-                    CS.X[e] = p.X;
-                    CS.batch[e] = p.batch;
-                }
-                cstaged += cnt;
-            }
-        }
+        if (PC) census_stage(P, CS, cstaged, at_census, p, lane);
         // siblings (keys 2..n) are banked and the line runs on with key 1
         // while this wave's view of the output count (last flush + staged)
         // is within the budget; past it, a scattering banks all n and ends
@@ -467,45 +478,77 @@ __global__ void __launch_bounds__(BLOCK) k_pulse_bank(PulseParams P) {
 
 // ------------------------------------------------------------ family schedule
 
-template <bool HASH, int BLOCK>
+// Banks the particles of keys k0..k1 emerging from a scattering of state
+// key at (x, t, tb): a finish launch leaves them to the next generation.
+__device__ __forceinline__ void spill(const PulseParams& P, double x, double t, int32_t tb, uint32_t batch,
+                                      uint64_t key, uint32_t k0, uint32_t k1) {
+    if (k1 < k0) return;
+    const uint64_t base = atomicAdd(reinterpret_cast<unsigned long long*>(P.out_count),
+                                    static_cast<unsigned long long>(k1 - k0 + 1));
+    for (uint32_t k = k0; k <= k1; ++k)
+        bank_store(P, base + (k - k0), x, t, murmur_hash(k, key) & P.lcg.mask, batch, tb);
+}
+
+// ITEMS = sources: the family schedule.  ITEMS = a generation bank (hash
+// seeding): a finish launch, which runs each input particle's descendants
+// depth first as well, up to P.lane_budget particles per input particle;
+// what is left then (the first emerging particle and the stack), and
+// siblings that find the stack full, go to the output bank.  So a finish
+// launch appends at most (budget + stack_depth + 1) n_max particles and
+// banks at most `budget` census arrivals per input particle.
+template <bool HASH, int ITEMS, bool PC, int BLOCK>
 __global__ void __launch_bounds__(BLOCK) k_pulse_family(PulseParams P) {
+    constexpr bool SOURCES = ITEMS == PULSE_ITEMS_SOURCES;
+    constexpr bool SPILL = !SOURCES;
+    constexpr bool DIR = PC || ITEMS == PULSE_ITEMS_COPIES;
+    __shared__ CensusStage cstage[PC ? BLOCK / 64 : 1];
     extern __shared__ unsigned long long lds_counts[];
     tally_lds_begin<BLOCK>(P, lds_counts);
     PulseLane c;
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t gl = static_cast<uint64_t>(blockIdx.x) * BLOCK + threadIdx.x;
     PulseStackEntry* stack = P.stack + gl * P.stack_depth;
+    CensusStage& CS = cstage[PC ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0];
+    uint32_t cstaged = 0;      // wave-uniform: entries in CS
     uint32_t sp = 0;
-    const uint64_t n_sources = P.src_end - P.src_begin;
+    const uint64_t n_items = SOURCES ? P.src_end - P.src_begin : P.n_in;
 
     PParticle p;
     p.x = p.t = 0.0;
     p.X = 0;
     p.tb = -1;
     p.batch = 0;
+    p.mu = 0.0;
+    p.has_mu = false;
     bool active = false;       // the lane holds a particle of a family
-    bool exhausted = false;    // wave-uniform: no sources left
+    bool exhausted = false;    // wave-uniform: no items left
     uint32_t pdraws = 0;       // draws of the current stream (hash: particle; stride: family)
+    uint32_t budget = 0;       // finish: particles the current item may still start
 
     for (;;) {
-        // lanes without a family take the next sources (one atomic per wave)
+        // lanes without a family take the next items (one atomic per wave)
         const uint64_t need = __ballot(!active);
         if (need != 0 && !exhausted) {
             const uint32_t cnt = static_cast<uint32_t>(__popcll(need));
             uint64_t wbase = 0;
             if (lane == 0) wbase = atomicAdd(reinterpret_cast<unsigned long long*>(P.family_counter), cnt);
             wbase = __shfl(wbase, 0);
-            if (wbase + cnt >= n_sources) exhausted = true;
+            if (wbase + cnt >= n_items) exhausted = true;
             if (!active) {
                 const uint64_t j = wbase + lane_prefix(need);
-                if (j < n_sources) {
-                    p.X = pulse_source_state(P, P.src_begin + j, &p.batch);
-                    p.x = 0.0;
-                    p.t = 0.0;
-                    p.tb = P.tb0;
+                if (j < n_items) {
+                    if (SOURCES) {
+                        p.X = pulse_source_state(P, P.src_begin + j, &p.batch);
+                        p.x = 0.0;
+                        p.t = 0.0;
+                        p.tb = P.tb0;
+                        c.sources++;
+                    } else {
+                        load_item<ITEMS>(P, j, p);
+                    }
                     pdraws = 0;
                     sp = 0;
-                    c.sources++;
+                    budget = P.lane_budget;
                     active = true;
                 }
             }
@@ -513,30 +556,50 @@ __global__ void __launch_bounds__(BLOCK) k_pulse_family(PulseParams P) {
         if (__ballot(active) == 0) break;
         uint32_t n = 0;
         int64_t tally = -1;
-        if (active) n = pulse_particle(P, p, c, &pdraws, &tally);
+        bool at_census = false;
+        if (active) n = pulse_particle<DIR>(P, p, c, &pdraws, &tally, &at_census);
         wave_tally(P, tally, lane, lds_counts);
+        if (PC) census_stage(P, CS, cstaged, at_census, p, lane);
         if (!active) continue;
         if (HASH) {
             // the particle's own stream ends here
             note_stream(P, c, pdraws);
             pdraws = 0;
         }
+        if (SPILL) budget--;
         if (n > 0) {
             if (n > 1) {
                 if (sp == P.stack_depth) {
-                    atomicOr(P.overflow, 1u);
-                    active = false;   // the family is abandoned; the run reports an error
-                    continue;
+                    if (SPILL) {
+                        spill(P, p.x, p.t, p.tb, p.batch, p.X, 2, n);
+                    } else {
+                        atomicOr(P.overflow, 1u);
+                        active = false;   // the family is abandoned; the run reports an error
+                        continue;
+                    }
+                } else {
+                    PulseStackEntry& e = stack[sp++];
+                    e.x = p.x;
+                    e.t = p.t;
+                    e.key = p.X;
+                    e.tb = p.tb;
+                    e.next = 2;
+                    e.n = n;
                 }
-                PulseStackEntry& e = stack[sp++];
-                e.x = p.x;
-                e.t = p.t;
-                e.key = p.X;
-                e.tb = p.tb;
-                e.next = 2;
-                e.n = n;
+            }
+            if (SPILL && budget == 0) {
+                // out of budget: the first emerging particle and the stack go to the bank
+                spill(P, p.x, p.t, p.tb, p.batch, p.X, 1, 1);
+                for (uint32_t i = 0; i < sp; ++i) {
+                    const PulseStackEntry& e = stack[i];
+                    spill(P, e.x, e.t, e.tb, p.batch, e.key, e.next, e.n);
+                }
+                sp = 0;
+                active = false;
+                continue;
             }
             if (HASH) p.X = murmur_hash(1ull, p.X) & P.lcg.mask;
+            p.has_mu = false;
             continue;   // the first emerging particle starts at once
         }
         if (sp == 0) {
@@ -544,16 +607,27 @@ __global__ void __launch_bounds__(BLOCK) k_pulse_family(PulseParams P) {
             active = false;
             continue;
         }
+        if (SPILL && budget == 0) {
+            for (uint32_t i = 0; i < sp; ++i) {
+                const PulseStackEntry& e = stack[i];
+                spill(P, e.x, e.t, e.tb, p.batch, e.key, e.next, e.n);
+            }
+            sp = 0;
+            active = false;
+            continue;
+        }
         PulseStackEntry& e = stack[sp - 1];
         p.x = e.x;
         p.t = e.t;
         p.tb = e.tb;
+        p.has_mu = false;
         if (HASH) p.X = murmur_hash(e.next, e.key) & P.lcg.mask;
         if (e.next == e.n)
             --sp;
         else
             e.next++;
     }
+    if (PC && cstaged != 0) census_flush(P, CS, cstaged, lane);
     tally_lds_end<BLOCK>(P, lds_counts);
     flush_lane_counters<BLOCK>(P, c);
 }
@@ -796,7 +870,27 @@ hipError_t launch_pulse_split(const PulseParams& p, uint64_t n_arrivals, hipStre
 
 template <bool HASH, int BLOCK>
 static hipError_t launch_family_b(const PulseParams& p, uint32_t grid, hipStream_t st) {
-    hipLaunchKernelGGL((k_pulse_family<HASH, BLOCK>), dim3(grid), dim3(BLOCK), pulse_tally_lds_bytes(p), st, p);
+    hipLaunchKernelGGL((k_pulse_family<HASH, PULSE_ITEMS_SOURCES, false, BLOCK>), dim3(grid), dim3(BLOCK),
+                       pulse_tally_lds_bytes(p), st, p);
+    return hipGetLastError();
+}
+
+uint32_t pulse_finish_grid(uint64_t items) {
+    uint64_t blocks = (items + 255) / 256;
+    const uint64_t cap = static_cast<uint64_t>(device_cus()) * 8;
+    if (blocks > cap) blocks = cap;
+    if (blocks < 1) blocks = 1;
+    return static_cast<uint32_t>(blocks);
+}
+
+hipError_t launch_pulse_finish(const PulseParams& p, bool pc, uint32_t grid, hipStream_t st) {
+    if (p.n_in == 0) return hipSuccess;
+    if (pc)
+        hipLaunchKernelGGL((k_pulse_family<true, PULSE_ITEMS_BANK, true, 256>), dim3(grid), dim3(256),
+                           pulse_tally_lds_bytes(p), st, p);
+    else
+        hipLaunchKernelGGL((k_pulse_family<true, PULSE_ITEMS_BANK, false, 256>), dim3(grid), dim3(256),
+                           pulse_tally_lds_bytes(p), st, p);
     return hipGetLastError();
 }
 

@@ -84,6 +84,7 @@ struct PulseParams {
     uint64_t* copy_count;
     uint64_t copy_cap;
     PulseCensusEntry* copies_out;
+    uint32_t lane_budget;    // finish launches: particles per input particle before the rest is banked
 };
 
 enum PulseItems : int { PULSE_ITEMS_SOURCES = 0, PULSE_ITEMS_BANK = 1, PULSE_ITEMS_COPIES = 2 };
@@ -102,6 +103,12 @@ hipError_t launch_pulse_bank(const PulseParams& p, int items_kind, bool pc, int 
 hipError_t launch_pulse_census_count(const PulseParams& p, uint64_t n_arrivals, hipStream_t st);
 hipError_t launch_pulse_split(const PulseParams& p, uint64_t n_arrivals, hipStream_t st);
 uint32_t pulse_family_grid(int block);
+// Finish launch (hash seeding): the generation bank p.in (p.n_in particles)
+// run depth first per lane with p.stack (p.stack_depth entries per lane),
+// at most p.lane_budget particles per input particle, the rest banked in
+// p.out (p.out_count); one 256-thread block per 256 inputs, at most 8 per CU.
+uint32_t pulse_finish_grid(uint64_t items);
+hipError_t launch_pulse_finish(const PulseParams& p, bool pc, uint32_t grid, hipStream_t st);
 hipError_t launch_pulse_family(const PulseParams& p, int block, uint32_t grid, hipStream_t st);
 hipError_t launch_pulse_flux(const PulseParams& p, double* flux, hipStream_t st);
 

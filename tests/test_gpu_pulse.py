@@ -109,6 +109,21 @@ def test_edge_problems(M, ctx, orc):
             check(orc, q, *run(M, ctx, q), threads=2)
 
 
+def test_finish_launches_bit_identical(M, ctx, orc):
+    """The bank schedule's tail, run depth first per lane by a finish launch
+    (with its per-particle budget and spills to the next generation), gives
+    the same counts for every switch point, including one that finishes at
+    the first shrinking generation of a growing population."""
+    for p in (W.pulse(W.hash_seeding(), n_batches=8, per_batch=400),
+              W.pulse_few_sources(n_sources=256, t_end=40)):
+        ref = orc.pulse(p, LCG, threads=8)
+        for div in (0xFFFFFFFF, 1, 2, 4, 64):
+            say("finish_div", div, p.n_batches)
+            c, _, d = run(M, ctx, p, schedule=M.PULSE_BANK, finish_div=div)
+            assert np.array_equal(c, ref.counts), div
+            assert d == ref.diag, div
+
+
 def test_stack_overflow_is_reported(M, ctx):
     """A family that outgrows opts.stack_depth is reported (MCRNG_ERANGE);
     the kernel checks the depth before every push, so nothing is written out

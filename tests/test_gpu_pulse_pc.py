@@ -76,6 +76,19 @@ def test_shapes_bit_identical(M, ctx, orc):
         assert d == ref.diag
 
 
+def test_finish_launches_bit_identical(M, ctx, orc):
+    """Census arrivals banked by finish launches (depth first per lane) are
+    the same arrivals: every switch point gives the same populations."""
+    p = W.pulse_pc(n_batches=6, per_batch=500, census_every=4, target=700)
+    ref = orc.pulse_pc(p, LCG, threads=6)
+    for div in (0xFFFFFFFF, 1, 3, 16):
+        say("pc finish_div", div)
+        c, _, d, pop = run(M, ctx, p, finish_div=div)
+        assert np.array_equal(pop, ref.pop), div
+        assert np.array_equal(c, ref.counts), div
+        assert d == ref.diag, div
+
+
 def test_paper_problem_with_population_control(M, ctx, orc):
     """The paper's problem, 1000 batches x 1000 sources, a census at t = 5,
     10, 15 that brings every batch back to 1000 particles on average."""
