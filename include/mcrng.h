@@ -278,7 +278,7 @@ typedef struct {
     mcrng_seeding seeding;       /* kind, base, stride; hier, first_index, group_key must be 0 */
 } mcrng_pulse_problem;
 
-enum { MCRNG_PULSE_AUTO = 0, MCRNG_PULSE_BANK = 1, MCRNG_PULSE_FAMILY = 2 };
+enum { MCRNG_PULSE_AUTO = 0, MCRNG_PULSE_BANK = 1, MCRNG_PULSE_FAMILY = 2, MCRNG_PULSE_EVENT = 3 };
 
 /* Options (zero = default).  No option changes a result bit: counts are
  * integers.
@@ -287,7 +287,12 @@ enum { MCRNG_PULSE_AUTO = 0, MCRNG_PULSE_BANK = 1, MCRNG_PULSE_FAMILY = 2 };
  *                (the first particle emerging from a scattering at once) in
  *                any order and banks the siblings for the next launch;
  *                MCRNG_PULSE_FAMILY: one source family per lane, depth
- *                first; AUTO: bank for hash seeding, family for stride
+ *                first (history based); MCRNG_PULSE_EVENT (hash seeding
+ *                only): event based, every launch advances each live
+ *                particle by one flight and its collision and banks all
+ *                emerging particles for the next launch (the tail is
+ *                finished as for the bank schedule, unless finish_div says
+ *                never); AUTO: bank for hash seeding, family for stride
  *   block        threads per block: 64, 128, 256, 512 or 1024
  *   stack_depth  family schedule: stack entries per lane (default 128; an
  *                entry holds the siblings of one scattering on the current

@@ -11,14 +11,14 @@ are torch device tensors; the library does all the arithmetic.
 output tensors.
 """
 from ._binding import (  # noqa: F401
-    DIAG_NAMES, EXPORTS, FP32, FP64, NDIAG, PULSE_AUTO, PULSE_BANK, PULSE_DIAG_NAMES, PULSE_FAMILY, SCHED_EVENT,
-    SCHED_HISTORY, Context, McrngError, PulseOpts, PulsePc, RunOpts, draw, init_streams, lib, make_opts,
-    make_pulse_opts, make_pulse_pc, pulse_n_census, tally_bins, uniforms,
+    DIAG_NAMES, EXPORTS, FP32, FP64, NDIAG, PULSE_AUTO, PULSE_BANK, PULSE_DIAG_NAMES, PULSE_EVENT, PULSE_FAMILY,
+    SCHED_EVENT, SCHED_HISTORY, Context, McrngError, PulseOpts, PulsePc, RunOpts, draw, init_streams, lib,
+    make_opts, make_pulse_opts, make_pulse_pc, pulse_n_census, tally_bins, uniforms,
 )
 
 __all__ = ["init_streams", "draw", "uniforms", "Context", "RunOpts", "make_opts", "tally_bins", "transport", "pulse",
            "PulseOpts", "make_pulse_opts", "pulse_pc", "PulsePc", "make_pulse_pc", "pulse_n_census", "McrngError", "lib", "FP64", "FP32", "SCHED_HISTORY", "SCHED_EVENT",
-           "PULSE_AUTO", "PULSE_BANK", "PULSE_FAMILY", "NDIAG", "DIAG_NAMES", "PULSE_DIAG_NAMES"]
+           "PULSE_AUTO", "PULSE_BANK", "PULSE_FAMILY", "PULSE_EVENT", "NDIAG", "DIAG_NAMES", "PULSE_DIAG_NAMES"]
 
 
 def transport(problems, lcg, ctx=None, opts=None, stream=None, device="cuda:0"):

@@ -20,7 +20,7 @@ EINVAL, ENOMEM, EDEVICE, ERANGE, ESTATE = -1, -2, -3, -4, -5
 SEED_STRIDE, SEED_HASH = 0, 1
 FP64, FP32 = 0, 1
 SCHED_HISTORY, SCHED_EVENT = 0, 1
-PULSE_AUTO, PULSE_BANK, PULSE_FAMILY = 0, 1, 2
+PULSE_AUTO, PULSE_BANK, PULSE_FAMILY, PULSE_EVENT = 0, 1, 2, 3
 NDIAG = 10
 DIAG_NAMES = ("histories", "leak_left", "leak_right", "absorbed", "census",
               "events", "collisions", "draws", "max_draws", "over_stride")

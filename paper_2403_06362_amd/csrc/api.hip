@@ -1053,10 +1053,11 @@ static int run_pulse(mcrng_ctx* ctx, const mcrng_lcg* lcg, const mcrng_pulse_pro
     const bool hash = P->seeding.kind == MCRNG_SEED_HASH;
     const uint64_t n_src = static_cast<uint64_t>(P->n_batches) * P->per_batch;
     if (o.block == 0) o.block = 256;
-    if (o.schedule != MCRNG_PULSE_AUTO && o.schedule != MCRNG_PULSE_BANK && o.schedule != MCRNG_PULSE_FAMILY)
+    if (o.schedule != MCRNG_PULSE_AUTO && o.schedule != MCRNG_PULSE_BANK && o.schedule != MCRNG_PULSE_FAMILY &&
+        o.schedule != MCRNG_PULSE_EVENT)
         return fail(MCRNG_EINVAL, "opts.schedule unknown");
-    if (o.schedule == MCRNG_PULSE_BANK && !hash)
-        return fail(MCRNG_EINVAL, "the bank schedule needs hash seeding (stride families share one stream)");
+    if ((o.schedule == MCRNG_PULSE_BANK || o.schedule == MCRNG_PULSE_EVENT) && !hash)
+        return fail(MCRNG_EINVAL, "the bank and event schedules need hash seeding (stride families share one stream)");
     if (pc && o.schedule == MCRNG_PULSE_FAMILY)
         return fail(MCRNG_EINVAL, "population control runs on the bank schedule");
     if (o.block != 64 && o.block != 128 && o.block != 256 && o.block != 512 && o.block != 1024)
@@ -1195,7 +1196,9 @@ static int run_pulse(mcrng_ctx* ctx, const mcrng_lcg* lcg, const mcrng_pulse_pro
             }
             const uint32_t grid = pulse_bank_grid(pp, kind, pcen, static_cast<int>(o.block), n);
             const uint64_t waves = static_cast<uint64_t>(grid) * o.block / 64;
-            const uint64_t budget = 2 * n;
+            // event schedule: no line runs on within a launch (one flight
+            // and collision per particle and launch)
+            const uint64_t budget = o.schedule == MCRNG_PULSE_EVENT ? 0 : 2 * n;
             const uint64_t slack = (waves + 1) * (256 + 64 * static_cast<uint64_t>(n_max));
             const uint64_t ocap = budget + static_cast<uint64_t>(n_max) * n + slack;
             int r = ensure(ctx->pulse_bank[nxt], ocap * 32, st, 8);
@@ -1272,7 +1275,7 @@ static int run_pulse(mcrng_ctx* ctx, const mcrng_lcg* lcg, const mcrng_pulse_pro
                 n_copies = w[5];
             }
         }
-    } else if (o.schedule == MCRNG_PULSE_BANK) {
+    } else if (o.schedule == MCRNG_PULSE_BANK || o.schedule == MCRNG_PULSE_EVENT) {
         // Sources go in chunks so that the banks stay within tens of GB.
         const uint64_t chunk = 1ull << 23;
         for (uint64_t c0 = 0; c0 < n_src; c0 += chunk) {

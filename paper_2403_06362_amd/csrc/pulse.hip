@@ -427,11 +427,11 @@ __global__ void __launch_bounds__(BLOCK) k_pulse_bank(PulseParams P) {
         if (PC) census_stage(P, CS, cstaged, at_census, p, lane);
         // siblings (keys 2..n) are banked and the line runs on with key 1
         // while this wave's view of the output count (last flush + staged)
-        // is within the budget; past it, a scattering banks all n and ends
-        // the line
+        // is within the budget; past it (or with no budget: the event
+        // schedule), a scattering banks all n and ends the line
         uint32_t sib_total = 0;
         wave_prefix16(n > 1 ? n - 1 : 0, &sib_total);
-        const bool keep = seen + staged + sib_total <= P.cont_budget;
+        const bool keep = P.cont_budget != 0 && seen + staged + sib_total <= P.cont_budget;   // 0: event based
         const uint32_t k0 = keep ? 2u : 1u;
         const uint32_t npush = n >= k0 ? n - k0 + 1 : 0;
         uint32_t total = 0;

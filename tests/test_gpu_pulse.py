@@ -109,6 +109,24 @@ def test_edge_problems(M, ctx, orc):
             check(orc, q, *run(M, ctx, q), threads=2)
 
 
+def test_event_schedule_bit_identical(M, ctx, orc):
+    """Event based (one flight and collision per particle and launch, every
+    emerging particle banked), with and without the depth-first finish:
+    the same counts as the oracle's history-based walk and the other
+    schedules, since every particle's stream is its own (eq. 5)."""
+    for p in (W.pulse(W.hash_seeding(), n_batches=9, per_batch=300, first_batch=2),
+              W.pulse_few_sources(n_sources=128, t_end=30)):
+        ref = orc.pulse(p, LCG, threads=8)
+        for div in (0xFFFFFFFF, 1):
+            for block in (64, 256, 1024):
+                say("event schedule", p.n_batches, div, block)
+                c, f, d = run(M, ctx, p, schedule=M.PULSE_EVENT, finish_div=div, block=block)
+                assert np.array_equal(c, ref.counts), (div, block)
+                assert d == ref.diag
+    with pytest.raises(M.McrngError):
+        run(M, ctx, W.pulse(W.stride_seeding(), n_batches=1, per_batch=4), schedule=M.PULSE_EVENT)
+
+
 def test_finish_launches_bit_identical(M, ctx, orc):
     """The bank schedule's tail, run depth first per lane by a finish launch
     (with its per-particle budget and spills to the next generation), gives

@@ -89,6 +89,15 @@ def test_finish_launches_bit_identical(M, ctx, orc):
         assert d == ref.diag, div
 
 
+def test_event_schedule_with_population_control(M, ctx, orc):
+    p = W.pulse_pc(n_batches=7, per_batch=300, census_every=3, target=250)
+    ref = orc.pulse_pc(p, LCG, threads=7)
+    for div in (0xFFFFFFFF, 1):
+        say("pc event schedule", div)
+        c, _, d, pop = run(M, ctx, p, schedule=M.PULSE_EVENT, finish_div=div)
+        assert np.array_equal(pop, ref.pop) and np.array_equal(c, ref.counts) and d == ref.diag, div
+
+
 def test_paper_problem_with_population_control(M, ctx, orc):
     """The paper's problem, 1000 batches x 1000 sources, a census at t = 5,
     10, 15 that brings every batch back to 1000 particles on average."""
