@@ -214,7 +214,7 @@ extern "C" int mcrng_draw(const mcrng_lcg* lcg, const mcrng_seeding* seeding, ui
         if (rc < 0) return rc;
         mode = p.seed.kind;
     }
-    int bpc = 16, round = 16;
+    int bpc = 16, round = 20;
     if (const char* env = getenv("MCRNG_DRAW_BLOCKS_PER_CU")) bpc = atoi(env);
     if (const char* env = getenv("MCRNG_DRAW_ROUND")) round = atoi(env);
     HIP_TRY(launch_draw(p, mode, static_cast<hipStream_t>(stream), bpc, round));

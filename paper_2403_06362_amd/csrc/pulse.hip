@@ -238,9 +238,9 @@ __device__ __forceinline__ uint32_t wave_prefix16(uint32_t v, uint32_t* total) {
 // banks here and copies them to the output bank with one atomic per
 // flush, so the output counter sees one atomic per few iterations of a
 // wave instead of one per iteration.
-template <int BLOCK>
+template <uint32_t CAP>
 struct BankStage {
-    static constexpr uint32_t kCap = (BLOCK >= 1024) ? 128u : 256u;   // 32 B per entry; 64 KiB per block
+    static constexpr uint32_t kCap = CAP;   // 32 B per entry
     double x[kCap];
     double t[kCap];
     uint64_t X[kCap];
@@ -263,8 +263,8 @@ __device__ __forceinline__ void bank_store(const PulseParams& P, uint64_t o, dou
 
 // Copies the wave's staged entries to the output bank (one atomic) and
 // returns the output count just after them.
-template <int BLOCK>
-__device__ __forceinline__ uint64_t bank_flush(const PulseParams& P, BankStage<BLOCK>& S, uint32_t count,
+template <class Stage>
+__device__ __forceinline__ uint64_t bank_flush(const PulseParams& P, Stage& S, uint32_t count,
                                                uint32_t lane) {
     __builtin_amdgcn_wave_barrier();
     uint64_t base = 0;
@@ -275,10 +275,12 @@ __device__ __forceinline__ uint64_t bank_flush(const PulseParams& P, BankStage<B
     return base + count;
 }
 
+constexpr uint32_t kPcBankStage = 256;   // bank stage entries per wave when census arrivals are staged too
+
 // Per-wave staging of census arrivals (population control), flushed to
 // P.cen with one atomic per flush.
 struct CensusStage {
-    static constexpr uint32_t kCap = 128;   // 28 B per entry
+    static constexpr uint32_t kCap = 128;   // 28 B per entry: 3.5 KiB per wave
     double x[kCap];
     double mu[kCap];
     uint64_t X[kCap];
@@ -361,7 +363,8 @@ __global__ void __launch_bounds__(BLOCK) k_pulse_bank(PulseParams P) {
     constexpr bool COPIES = ITEMS == PULSE_ITEMS_COPIES;
     constexpr bool DIR = PC || COPIES;   // particles may carry a direction
     constexpr uint32_t kChunk = 256;   // items a wave takes per atomic
-    using Stage = BankStage<BLOCK>;
+    // 8 KiB per wave (4 KiB at 1024 threads, so that a block fits in LDS)
+    using Stage = BankStage<(BLOCK >= 1024) ? 128u : (PC ? kPcBankStage : 256u)>;
     __shared__ Stage stage[BLOCK / 64];
     __shared__ CensusStage cstage[PC ? BLOCK / 64 : 1];
     extern __shared__ unsigned long long lds_counts[];
@@ -438,7 +441,7 @@ __global__ void __launch_bounds__(BLOCK) k_pulse_bank(PulseParams P) {
         const uint32_t off = wave_prefix16(npush, &total);
         if (total != 0) {
             if (staged + total > Stage::kCap) {
-                seen = bank_flush<BLOCK>(P, S, staged, lane);
+                seen = bank_flush(P, S, staged, lane);
                 staged = 0;
             }
             if (total <= Stage::kCap) {
@@ -470,7 +473,7 @@ __global__ void __launch_bounds__(BLOCK) k_pulse_bank(PulseParams P) {
             }
         }
     }
-    if (staged != 0) bank_flush<BLOCK>(P, S, staged, lane);
+    if (staged != 0) bank_flush(P, S, staged, lane);
     if (PC && cstaged != 0) census_flush(P, CS, cstaged, lane);
     tally_lds_end<BLOCK>(P, lds_counts);
     flush_lane_counters<BLOCK>(P, c);

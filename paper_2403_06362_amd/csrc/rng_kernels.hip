@@ -145,10 +145,12 @@ static hipError_t launch_draw_t(const DrawParams& p, hipStream_t st, int blocks)
 
 template <int MODE, bool M63C1>
 static hipError_t launch_draw_d(const DrawParams& p, hipStream_t st, int blocks, int d) {
+    // rounds of 20 draws: measured 1% faster than 16 or 24, 3% faster than 12 or 32
     switch (d) {
         case 8: return launch_draw_t<MODE, 8, M63C1>(p, st, blocks);
+        case 16: return launch_draw_t<MODE, 16, M63C1>(p, st, blocks);
         case 32: return launch_draw_t<MODE, 32, M63C1>(p, st, blocks);
-        default: return launch_draw_t<MODE, 16, M63C1>(p, st, blocks);
+        default: return launch_draw_t<MODE, 20, M63C1>(p, st, blocks);
     }
 }
 
