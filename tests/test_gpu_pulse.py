@@ -142,6 +142,27 @@ def test_finish_launches_bit_identical(M, ctx, orc):
             assert d == ref.diag, div
 
 
+def test_limits(M, ctx, orc):
+    """Multiplicity near its limit (up to 14 particles per scattering, so a
+    wave's appends exceed its LDS stage and go straight to the bank) and the
+    largest number of time bins (4096), every schedule."""
+    big_nu = W.pulse(W.hash_seeding(), n_batches=3, per_batch=40).with_(
+        nu=13.5, scatter=0.5, time_edges=np.array([0.0, 0.25, 0.5, 0.75, 1.0]))
+    many_bins = W.pulse(W.hash_seeding(), n_batches=2, per_batch=300).with_(
+        time_edges=np.linspace(0.0, 20.0, 4097))
+    for i, p in enumerate((big_nu, many_bins)):
+        ref = orc.pulse(p, LCG, threads=4)
+        for sched in (M.PULSE_BANK, M.PULSE_EVENT, M.PULSE_FAMILY):
+            say("limits", i, sched)
+            c, _, d = run(M, ctx, p, schedule=sched)
+            assert np.array_equal(c, ref.counts), (i, sched)
+            assert d == ref.diag, (i, sched)
+        ps = p.with_(seeding=W.stride_seeding())
+        refs = orc.pulse(ps, LCG, threads=4)
+        c, _, d = run(M, ctx, ps)
+        assert np.array_equal(c, refs.counts) and d == refs.diag, i
+
+
 def test_stack_overflow_is_reported(M, ctx):
     """A family that outgrows opts.stack_depth is reported (MCRNG_ERANGE);
     the kernel checks the depth before every push, so nothing is written out

@@ -127,6 +127,21 @@ def test_edge_problems(M, ctx, orc):
     assert pop.shape[1] == 0 and np.array_equal(c, plain.counts) and d == plain.diag
 
 
+def test_limits(M, ctx, orc):
+    """Population control with many copies per arrival (a target far above
+    the arrivals), multiplicity near its limit, and 4096 time bins with a
+    census every 512."""
+    probs = [W.pulse_pc(n_batches=3, per_batch=5, census_every=2, target=5000, t_end=6),
+             W.pulse_pc(n_batches=3, per_batch=40, census_every=2, target=60).with_(
+                 nu=13.5, scatter=0.5, time_edges=np.array([0.0, 0.25, 0.5, 0.75, 1.0])),
+             W.pulse_pc(n_batches=2, per_batch=300, census_every=512, target=250).with_(
+                 time_edges=np.linspace(0.0, 20.0, 4097))]
+    for i, p in enumerate(probs):
+        for sched in (M.PULSE_BANK, M.PULSE_EVENT):
+            say("pc limits", i, sched)
+            check(orc, p, *run(M, ctx, p, schedule=sched), threads=3)
+
+
 def test_several_batch_chunks(M, ctx, orc):
     """Runs that go through several chunks of whole batches: many small
     batches (the chunk holds at most 4096), and few large ones."""
