@@ -17,8 +17,9 @@ Also reported, each timed separately after the headline loop:
                 hash FP32-flight and stride FP64 (kernel time, HIP events)
   pulse         the paper's test problem (pulse in an infinite multiplying
                 medium, secondaries seeded on demand), 1000 x 1000 sources:
-                hash-seeded particle banks vs depth-first families, and the
-                paper's normality study at full size (30 x 1000 batches)
+                hash-seeded generation banks, event-based passes and
+                depth-first families against stride-seeded families, and
+                the paper's normality study at full size (30 x 1000 batches)
   pulse_population_control
                 the same problem with a census every 5 time units that
                 brings each batch back to its source count (one-off hashed
@@ -58,11 +59,12 @@ INT_VALU_PEAK = 256 * 4 * 16 * 2.4e9
 # Algorithmic integer lane-ops: a draw is the 63-bit multiply-add on 32-bit
 # halves (64-bit low product with the increment, two cross products, one
 # three-way add, the mask) plus the 64-bit checksum add = 6; a hash seed is
-# Listing 1 on a 64-bit key = 16; a stride seed is 6 per base-16 digit of
-# the stream index (digit extraction 2, 64-bit multiply-add 4).
+# Listing 1 on a 64-bit key = 16; a stride seed of consecutive streams is
+# one k-step affine map from the previous batch base (64-bit multiply-add
+# with a 64-bit increment, the mask) = 6.
 OPS_PER_DRAW = 6
 OPS_PER_HASH_SEED = 16
-OPS_PER_STRIDE_DIGIT = 6
+OPS_PER_STRIDE_SEED = 6
 
 
 def log(*a):
@@ -266,9 +268,8 @@ def main():
     chk_hash = hsh["chk"].view(torch.int64).cpu().numpy().view(np.uint64)
     chk_stride = strd["chk"].view(torch.int64).cpu().numpy().view(np.uint64)
 
-    digits = max(1, int(np.ceil(np.log2(n) / 4)))
     ops_hash = OPS_PER_DRAW * total_draws + OPS_PER_HASH_SEED * n
-    ops_stride = OPS_PER_DRAW * total_draws + OPS_PER_STRIDE_DIGIT * digits * n
+    ops_stride = OPS_PER_DRAW * total_draws + OPS_PER_STRIDE_SEED * n
     achieved = ops_hash / (hsh["kernel_ms"] * 1e-3)
     src = open(os.path.join(ROOT, "paper_2403_06362_amd", "csrc", "rng_kernels.hip"), "rb").read()
     src += open(os.path.join(ROOT, "paper_2403_06362_amd", "csrc", "device_rng.hpp"), "rb").read()
@@ -500,7 +501,8 @@ def pulse_leg(M, W, torch, lcg, ctx):
     p = W.pulse(W.hash_seeding())
     few = W.pulse_few_sources()
     for tag, base in (("", p), ("few_sources_", few)):
-        for name, prob, sched in (("hash_bank", base, M.PULSE_BANK), ("hash_family", base, M.PULSE_FAMILY),
+        for name, prob, sched in (("hash_bank", base, M.PULSE_BANK), ("hash_event", base, M.PULSE_EVENT),
+                                  ("hash_family", base, M.PULSE_FAMILY),
                                   ("stride_family", base.with_(seeding=W.stride_seeding()), M.PULSE_FAMILY)):
             log("pulse", tag + name)
             ms, _, d = pulse_run(M, torch, lcg, ctx, prob, sched, 3)
@@ -513,6 +515,9 @@ def pulse_leg(M, W, torch, lcg, ctx):
     out["few_sources_hash_bank_over_stride_family"] = (out["few_sources_stride_family"]["ms"] /
                                                        out["few_sources_hash_bank"]["ms"])
     out["hash_family_over_stride_family"] = out["stride_family"]["ms"] / out["hash_family"]["ms"]
+    out["hash_event_over_stride_family"] = out["stride_family"]["ms"] / out["hash_event"]["ms"]
+    out["few_sources_hash_event_over_stride_family"] = (out["few_sources_stride_family"]["ms"] /
+                                                        out["few_sources_hash_event"]["ms"])
 
     study = {}
     for kind in ("hash", "stride"):

@@ -38,10 +38,33 @@ __device__ __forceinline__ uint64_t queue_seed(const DrawParams& P, uint64_t j) 
     return stream_start(P.lcg, P.seed, j);
 }
 
+// Stride seeding of a batch of 64 consecutive streams s0 + l (l = lane):
+// X_{Q(s0 + l)} = A_{Ql}(X_{Q s0}), with A_k the k-step map x -> G_k x + C_k
+// (eq. 2).  A_{Ql} composes the skip table's digit-0 entry for l & 15 and
+// its digit-1 entry for l >> 4; the next batch's base is A_{64Q} (digit 1,
+// value 4) of this one.  Same states as the digit walk of stream_start.
+struct StrideLanes {
+    uint64_t g, c;        // A_{Q lane}
+    uint64_t g64, c64;    // A_{64 Q}
+};
+
+__device__ __forceinline__ StrideLanes stride_lanes(const SeedDev& S, uint32_t lane) {
+    const uint64_t* a = S.table + 2 * (lane & (kStrideRadix - 1));
+    const uint64_t* b = S.table + 2 * (kStrideRadix + (lane >> kStrideRadixBits));
+    const uint64_t* q = S.table + 2 * (kStrideRadix + 4);
+    StrideLanes r;
+    r.g = a[0] * b[0];
+    r.c = a[0] * b[1] + a[1];
+    r.g64 = q[0];
+    r.c64 = q[1];
+    return r;
+}
+
 // Persistent seed + draw kernel.  Each wave owns the streams [lo, hi)
 // (fewer than 2^32) and keeps the next streams ready in a 128-entry LDS ring
 // (start state and draw count at position j & 127 for stream j), seeded 64 at
-// a time by all 64 lanes at once, the counts loaded one batch ahead.  Each
+// a time by all 64 lanes at once (stride seeding: one affine step per lane
+// from the batch's base), the counts loaded one batch ahead.  Each
 // lane carries one active stream; a round draws D steps (only the checksum is
 // masked by the remaining count); after a round, lanes whose stream ended
 // store its checksum and take the next ring entries in order (ballot, prefix
@@ -66,12 +89,27 @@ __global__ void __launch_bounds__(256) k_draw(DrawParams P) {
     // not yet handed out; c_next holds the counts of the batch after them
     uint32_t next = 0, filled = 128;
     uint32_t c_next = 0;
+    // stride seeding: this lane's map A_{Q lane} and the base X_{Q s0} of the
+    // next batch to seed (wave-uniform)
+    StrideLanes sl{};
+    uint64_t sbase = 0;
+    if (MODE == SEED_STRIDE) {
+        sl = stride_lanes(P.seed, lane);
+        sbase = stream_start(P.lcg, P.seed, lo);
+    }
     {
         const uint32_t ja = lane, jb = 64u + lane, jn = 128u + lane;
         rcount[ja] = (ja < nw) ? P.count[lo + ja] : 0u;
         rcount[jb] = (jb < nw) ? P.count[lo + jb] : 0u;
-        rstate[ja] = (ja < nw) ? queue_seed<MODE>(P, lo + ja) : 0ull;
-        rstate[jb] = (jb < nw) ? queue_seed<MODE>(P, lo + jb) : 0ull;
+        if (MODE == SEED_STRIDE) {
+            const uint64_t b1 = affine_apply(sl.g64, sl.c64, P.lcg.mask, sbase);
+            rstate[ja] = (ja < nw) ? affine_apply(sl.g, sl.c, P.lcg.mask, sbase) : 0ull;
+            rstate[jb] = (jb < nw) ? affine_apply(sl.g, sl.c, P.lcg.mask, b1) : 0ull;
+            sbase = affine_apply(sl.g64, sl.c64, P.lcg.mask, b1);
+        } else {
+            rstate[ja] = (ja < nw) ? queue_seed<MODE>(P, lo + ja) : 0ull;
+            rstate[jb] = (jb < nw) ? queue_seed<MODE>(P, lo + jb) : 0ull;
+        }
         if (jn < nw) c_next = P.count[lo + jn];
     }
 
@@ -104,7 +142,12 @@ __global__ void __launch_bounds__(256) k_draw(DrawParams P) {
                 // fewer than 64 ready: seed the next batch of 64 (its ring
                 // positions hold no stream that is still to be handed out)
                 const uint32_t j = filled + lane;
-                rstate[j & 127u] = (j < nw) ? queue_seed<MODE>(P, lo + j) : 0ull;
+                if (MODE == SEED_STRIDE) {
+                    rstate[j & 127u] = (j < nw) ? affine_apply(sl.g, sl.c, P.lcg.mask, sbase) : 0ull;
+                    sbase = affine_apply(sl.g64, sl.c64, P.lcg.mask, sbase);
+                } else {
+                    rstate[j & 127u] = (j < nw) ? queue_seed<MODE>(P, lo + j) : 0ull;
+                }
                 rcount[j & 127u] = c_next;   // the one wait on vector memory per 64 streams
                 const uint32_t jn = j + 64u;
                 c_next = (jn < nw) ? P.count[lo + jn] : 0u;

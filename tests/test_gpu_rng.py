@@ -89,6 +89,39 @@ def test_draw_parity(M, orc, mode, n):
     assert np.array_equal(u64_np(chk)[:n], ref)
 
 
+@pytest.mark.parametrize("gen", ["mcnp", "m48"])
+def test_draw_stride_batches_offsets_generators(M, orc, gen):
+    """Stride seeding in the draw kernel seeds 64 consecutive streams per
+    batch by one affine step each from the batch's base: with 8M streams every
+    wave seeds several batches; an offset first index, another stride, and a
+    48-bit generator with c = 3 (the generic step) give the oracle's
+    checksums and final states on sampled streams."""
+    import torch
+    n = 1 << 23
+    if gen == "mcnp":
+        lcg, first, q = LCG, 12345, 152917
+    else:
+        lcg, first, q = W.Lcg(W.G_MCNP % (1 << 48), 3, 48), 7, 1000003
+    counts = W.draw_counts(n, seed=5)
+    sd = W.Seeding("stride", 11, q, first)
+    say("draw stride batches", gen)
+    chk = _empty_u64(n)
+    st = _empty_u64(n)
+    M.draw(lcg, sd, to_dev_u32(counts), chk, d_state=st)
+    torch.cuda.synchronize()
+    got, gst = u64_np(chk), u64_np(st)
+    rng = np.random.default_rng(21)
+    idx = np.concatenate([np.arange(200), np.arange(n - 200, n), rng.integers(0, n, 2000)])
+    for i in idx:
+        i = int(i)
+        one = orc.seed_and_draw(lcg, W.Seeding("stride", 11, q, first + i), counts[i:i + 1])
+        assert int(got[i]) == int(one[0]), i
+        x = orc.stream_start(lcg, W.Seeding("stride", 11, q, first + i), 0)
+        for _ in range(int(counts[i])):
+            x = orc.lcg_next(x, lcg.g, lcg.c, lcg.m)
+        assert int(gst[i]) == x, i
+
+
 @pytest.mark.parametrize("kind", ["hash", "stride"])
 def test_draw_full_size_sampled(M, orc, kind):
     """The benchmark workload: 2^26 streams, geometric counts (mean 64)."""
