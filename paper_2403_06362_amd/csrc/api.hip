@@ -697,9 +697,9 @@ static int enqueue_run(mcrng_ctx* ctx, const LcgDev& L, const mcrng_run_opts& o,
     sh.timed = ctx->any_timed;
     int dev_lds = 0;
     HIP_TRY(hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
-    if (transport_lds_bytes(tp, sh.f32) + 256 > static_cast<size_t>(dev_lds))
-        return fail(MCRNG_EINVAL, "LDS needed (%zu bytes) exceeds the device's %d", transport_lds_bytes(tp, sh.f32),
-                    dev_lds);
+    const size_t lds_need = transport_lds_bytes(tp, sh.f32) + transport_static_lds_bytes(sh.block);
+    if (lds_need > static_cast<size_t>(dev_lds))
+        return fail(MCRNG_EINVAL, "LDS needed (%zu bytes) exceeds the device's %d", lds_need, dev_lds);
     HIP_TRY(launch_fill_u32(tp.unit_counter, 16, 0u, st));
     HIP_TRY(launch_transport(tp, sh, st, nullptr));
     return MCRNG_OK;

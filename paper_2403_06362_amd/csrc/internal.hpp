@@ -120,6 +120,9 @@ struct LaunchShape {
 };
 
 size_t transport_lds_bytes(const TransportParams& p, int f32);
+// LDS k_transport declares statically for a block size (skip table, the
+// waves' rings of seeded histories, block words).
+size_t transport_static_lds_bytes(int block);
 hipError_t launch_transport(const TransportParams& p, const LaunchShape& s, hipStream_t st,
                             int* grid_used);
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st);

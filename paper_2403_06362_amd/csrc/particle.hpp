@@ -260,13 +260,13 @@ __device__ __forceinline__ int step_particle(Particle<F32>& p, const CellsLds<F3
     return collide<F32>(p, C, L, cnt);
 }
 
-// A new history: source at the left face moving right, at the first time
-// edge; its first flight is sampled before its first geometry step.
+// A new history whose stream starts at state X: source at the left face
+// moving right, at the first time edge; its first flight is sampled before
+// its first geometry step.
 template <bool F32, bool TIMED>
-__device__ __forceinline__ void init_particle(Particle<F32>& p, const CellsLds<F32>& C, const LcgDev& L,
-                                              const SeedDev& S, uint64_t j) {
+__device__ __forceinline__ void init_particle_at(Particle<F32>& p, const CellsLds<F32>& C, uint64_t X) {
     using R = typename Particle<F32>::R;
-    p.X = stream_start(L, S, j);
+    p.X = X;
     if constexpr (F32) {
         p.x = 0.0f;
         p.t = 0.0f;
@@ -280,6 +280,13 @@ __device__ __forceinline__ void init_particle(Particle<F32>& p, const CellsLds<F
     p.tb = 0;
     p.hdraws = 0;
     p.need_tau = true;
+}
+
+// History j (global index) of a problem with seeding S.
+template <bool F32, bool TIMED>
+__device__ __forceinline__ void init_particle(Particle<F32>& p, const CellsLds<F32>& C, const LcgDev& L,
+                                              const SeedDev& S, uint64_t j) {
+    init_particle_at<F32, TIMED>(p, C, stream_start(L, S, j));
 }
 
 }  // namespace mcrng

@@ -76,6 +76,11 @@ size_t transport_lds_bytes(const TransportParams& p, int f32) {
     return b;
 }
 
+size_t transport_static_lds_bytes(int block) {
+    return static_cast<size_t>(kStrideDigits) * kStrideRadix * 2 * sizeof(uint64_t) +
+           static_cast<size_t>(block / 64) * 128 * sizeof(uint64_t) + 256;
+}
+
 template <bool F32, bool TIMED, int H, int BLOCK>
 __global__ void __launch_bounds__(BLOCK) k_transport(TransportParams P) {
     using R = typename Particle<F32>::R;
@@ -83,6 +88,11 @@ __global__ void __launch_bounds__(BLOCK) k_transport(TransportParams P) {
     __shared__ uint32_t s_unit;
     __shared__ uint32_t s_next;
     __shared__ unsigned long long s_diag[kNDiag];
+    // the current problem's stride skip table: a history's start is a chain
+    // of dependent table reads, cheaper from LDS than from the cache
+    __shared__ uint64_t s_skip[kStrideDigits * kStrideRadix * 2];
+    // per wave: start states of the next histories, seeded 64 at a time
+    __shared__ uint64_t s_ring[BLOCK / 64][128];
 
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63u;
@@ -142,6 +152,8 @@ __global__ void __launch_bounds__(BLOCK) k_transport(TransportParams P) {
             }
             if (TIMED)
                 for (uint32_t i = tid; i <= PR.n_time_bins; i += BLOCK) l_tedge[i] = g_tedge[PR.tedge_off + i];
+            if (PR.seed_kind == SEED_STRIDE)
+                for (uint32_t i = tid; i < PR.stride_digits * kStrideRadix * 2u; i += BLOCK) s_skip[i] = PR.table[i];
             cur_problem = static_cast<int32_t>(U.problem);
         }
         __syncthreads();
@@ -160,7 +172,7 @@ __global__ void __launch_bounds__(BLOCK) k_transport(TransportParams P) {
         S.stride_digits = PR.stride_digits;
         S.base = PR.seed_base;
         S.first_index = PR.first_index;
-        S.table = PR.table;
+        S.table = s_skip;
         uint64_t* tally = tally_all + static_cast<size_t>(copy) * P.max_slice * 2;
 
         LaneCounters cnt;
@@ -168,7 +180,11 @@ __global__ void __launch_bounds__(BLOCK) k_transport(TransportParams P) {
         bool alive[H], pend[H], pcoll[H];
 #pragma unroll
         for (int h = 0; h < H; ++h) alive[h] = pend[h] = pcoll[h] = false;
-        bool exhausted = false;   // wave-uniform
+        bool exhausted = false;   // wave-uniform: no history of the unit left for this wave
+        // the wave's ring of seeded histories (positions & 127): [r_next, r_filled)
+        uint64_t* ring = s_ring[__builtin_amdgcn_readfirstlane(wid)];
+        uint32_t r_next = 0, r_filled = 0;   // wave-uniform
+        bool unit_taken = false;             // wave-uniform: s_next has passed the unit's end
 
         // Each iteration: refill idle lanes; geometry step for the lanes not
         // waiting on a collision; then, once enough lanes wait (or none can
@@ -182,20 +198,32 @@ __global__ void __launch_bounds__(BLOCK) k_transport(TransportParams P) {
                     const uint64_t need = __ballot(!alive[h]);
                     if (need != 0) {
                         const uint32_t nneed = static_cast<uint32_t>(__popcll(need));
-                        const int leader = __ffsll(static_cast<unsigned long long>(need)) - 1;
-                        uint32_t base = 0;
-                        if (static_cast<int>(lane) == leader) base = atomicAdd(&s_next, nneed);
-                        base = __shfl(base, leader);
-                        if (base + nneed >= U.count) exhausted = true;
+                        if (r_filled - r_next < nneed && !unit_taken) {
+                            // seed the next 64 histories of the unit at once
+                            // (one per lane), so that a refill is an LDS read
+                            uint32_t base = 0;
+                            if (lane == 0) base = atomicAdd(&s_next, 64u);
+                            base = __shfl(base, 0);
+                            if (base + 64u >= U.count) unit_taken = true;
+                            const uint32_t got = base < U.count ? (U.count - base < 64u ? U.count - base : 64u) : 0u;
+                            if (lane < got) ring[(r_filled + lane) & 127u] = stream_start(P.lcg, S, U.j0 + base + lane);
+                            r_filled += got;
+                            __builtin_amdgcn_wave_barrier();
+                        }
+                        const uint32_t avail = r_filled - r_next;
+                        const uint32_t take = avail < nneed ? avail : nneed;
                         if (!alive[h]) {
-                            const uint32_t j = base + static_cast<uint32_t>(__popcll(need & lt_mask));
-                            if (j < U.count) {
-                                init_particle<F32, TIMED>(p[h], C, P.lcg, S, U.j0 + j);
+                            const uint32_t rank = static_cast<uint32_t>(__popcll(need & lt_mask));
+                            if (rank < take) {
+                                init_particle_at<F32, TIMED>(p[h], C, ring[(r_next + rank) & 127u]);
                                 alive[h] = true;
                                 pend[h] = true;     // waits for its first flight
                                 pcoll[h] = false;
                             }
                         }
+                        r_next += take;
+                        if (unit_taken && r_next == r_filled) exhausted = true;
+                        __builtin_amdgcn_wave_barrier();
                     }
                 }
             }
