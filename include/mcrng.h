@@ -302,13 +302,17 @@ enum { MCRNG_PULSE_AUTO = 0, MCRNG_PULSE_BANK = 1, MCRNG_PULSE_FAMILY = 2, MCRNG
  *                and at most 65536 particles, one launch runs the rest depth
  *                first per lane, up to 64 particles per banked particle
  *                (default 1: the first shrinking generation of that size;
- *                0xffffffff: never) */
+ *                0xffffffff: never)
+ *   chunk        bank and event schedules: particles a wave takes from a
+ *                launch's input per atomic, 64 .. 2^20 (default 0: chosen
+ *                per launch from its input count) */
 typedef struct {
     uint32_t schedule;
     uint32_t block;
     uint32_t stack_depth;
     uint32_t finish_div;
-    uint32_t reserved[4];        /* must be 0 */
+    uint32_t chunk;
+    uint32_t reserved[3];        /* must be 0 */
 } mcrng_pulse_opts;
 
 /* Diagnostics of a pulse run, MCRNG_NDIAG uint64 words in this order; sums

@@ -81,7 +81,7 @@ class PulsePc(C.Structure):
 
 class PulseOpts(C.Structure):
     _fields_ = [("schedule", C.c_uint32), ("block", C.c_uint32), ("stack_depth", C.c_uint32),
-                ("finish_div", C.c_uint32), ("reserved", C.c_uint32 * 4)]
+                ("finish_div", C.c_uint32), ("chunk", C.c_uint32), ("reserved", C.c_uint32 * 3)]
 
 
 _lib = None

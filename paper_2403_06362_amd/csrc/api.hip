@@ -1002,6 +1002,15 @@ static PulseBankView carve_pulse_bank(void* base, uint64_t cap) {
 
 // Reads n <= 8 device words (through a pinned host buffer) after the work
 // queued on st.
+// Input particles a wave of the bank kernel takes per atomic on the item
+// counter: small launches keep many waves busy, large ones need few atomics
+// on that one counter (its same-address atomics serialise across the GPU).
+static uint32_t pulse_auto_chunk(uint64_t n) {
+    uint32_t c = 256;
+    while (c < 4096 && static_cast<uint64_t>(c) * 1024 * 2 <= n) c *= 2;
+    return c;
+}
+
 static int read_words(mcrng_ctx* ctx, const uint64_t* d, uint32_t n, uint64_t* h, hipStream_t st) {
     if (!ctx->h_pinned) HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&ctx->h_pinned), 64, hipHostMallocDefault));
     HIP_TRY(hipMemcpyAsync(ctx->h_pinned, d, n * sizeof *h, hipMemcpyDeviceToHost, st));
@@ -1050,6 +1059,8 @@ static int run_pulse(mcrng_ctx* ctx, const mcrng_lcg* lcg, const mcrng_pulse_pro
     for (uint32_t r : o.reserved)
         if (r) return fail(MCRNG_EINVAL, "opts.reserved must be 0");
     if (o.finish_div == 0) o.finish_div = 1;
+    if (o.chunk != 0 && (o.chunk < 64 || o.chunk > (1u << 20)))
+        return fail(MCRNG_EINVAL, "opts.chunk must be 0 or in 64..2^20");
     const bool hash = P->seeding.kind == MCRNG_SEED_HASH;
     const uint64_t n_src = static_cast<uint64_t>(P->n_batches) * P->per_batch;
     if (o.block == 0) o.block = 256;
@@ -1158,6 +1169,7 @@ static int run_pulse(mcrng_ctx* ctx, const mcrng_lcg* lcg, const mcrng_pulse_pro
         int cur = 0, nxt = 1;
         uint64_t in_cap = 0, peak = 0, prev = ~0ull;
         while (n > 0) {
+            pp.chunk = o.chunk ? o.chunk : pulse_auto_chunk(n);
             peak = std::max(peak, n);
             const bool fin = kind == PULSE_ITEMS_BANK && o.finish_div != 0xffffffffu && n <= kFinishItems &&
                              n < prev && n * o.finish_div <= peak;

@@ -13,8 +13,8 @@
 //   stride seeding they continue the source's one stream, depth first.
 //
 // Two schedules:
-//   k_pulse_bank (hash only)  one launch per generation.  A wave takes 256
-//       input particles (or sources) at a time through one atomic and hands
+//   k_pulse_bank (hash only)  one launch per generation.  A wave takes a chunk
+//       of input particles (or sources) at a time through one atomic and hands
 //       them to its idle lanes; a lane runs each one's line of descent: at a
 //       scattering it keeps the first emerging particle in registers and
 //       banks its siblings (staged per wave in LDS, copied to the output bank
@@ -362,7 +362,7 @@ __global__ void __launch_bounds__(BLOCK) k_pulse_bank(PulseParams P) {
     constexpr bool SOURCES = ITEMS == PULSE_ITEMS_SOURCES;
     constexpr bool COPIES = ITEMS == PULSE_ITEMS_COPIES;
     constexpr bool DIR = PC || COPIES;   // particles may carry a direction
-    constexpr uint32_t kChunk = 256;   // items a wave takes per atomic
+    const uint32_t chunk = P.chunk;   // items a wave takes per atomic
     // 8 KiB per wave (4 KiB at 1024 threads, so that a block fits in LDS)
     using Stage = BankStage<(BLOCK >= 1024) ? 128u : (PC ? kPcBankStage : 256u)>;
     __shared__ Stage stage[BLOCK / 64];
@@ -391,11 +391,11 @@ __global__ void __launch_bounds__(BLOCK) k_pulse_bank(PulseParams P) {
         const uint64_t need = __ballot(!active);
         if (need != 0 && wnext == wend && !exhausted) {
             uint64_t b = 0;
-            if (lane == 0) b = atomicAdd(reinterpret_cast<unsigned long long*>(P.item_counter), kChunk);
+            if (lane == 0) b = atomicAdd(reinterpret_cast<unsigned long long*>(P.item_counter), chunk);
             b = __shfl(b, 0);
-            if (b + kChunk >= n_items) exhausted = true;
+            if (b + chunk >= n_items) exhausted = true;
             wnext = b < n_items ? b : n_items;
-            wend = b + kChunk < n_items ? b + kChunk : n_items;
+            wend = b + chunk < n_items ? b + chunk : n_items;
         }
         const uint64_t avail = wend - wnext;
         const uint32_t nneed = static_cast<uint32_t>(__popcll(need));
@@ -825,7 +825,7 @@ static uint64_t bank_items(const PulseParams& p, int items_kind) {
 }
 
 uint32_t pulse_bank_grid(const PulseParams& p, int items_kind, bool pc, int block, uint64_t items) {
-    // resident blocks only: waves keep taking 256-item chunks, so a launch
+    // resident blocks only: waves keep taking chunks of items, so a launch
     // ends with one tail instead of one per wave
     block = bank_block(block);
     int per_cu = 0;
@@ -833,7 +833,8 @@ uint32_t pulse_bank_grid(const PulseParams& p, int items_kind, bool pc, int bloc
                                                      pulse_tally_lds_bytes(p)) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
-    uint64_t blocks = (items + 4ull * block - 1) / (4ull * block);   // a 256-item chunk per wave at least
+    const uint64_t per_block = static_cast<uint64_t>(p.chunk) * static_cast<uint64_t>(block / 64);
+    uint64_t blocks = (items + per_block - 1) / per_block;   // a chunk per wave at least
     const uint64_t cap = static_cast<uint64_t>(device_cus()) * static_cast<uint64_t>(per_cu);
     if (blocks > cap) blocks = cap;
     if (blocks < 1) blocks = 1;

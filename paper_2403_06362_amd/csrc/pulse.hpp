@@ -62,7 +62,8 @@ struct PulseParams {
     uint64_t n_in;
     uint64_t* out_count;
     uint64_t out_cap;
-    uint64_t* item_counter;  // bank schedule: next input particle (taken 256 per wave)
+    uint64_t* item_counter;  // bank schedule: next input particle (taken `chunk` per wave)
+    uint32_t chunk;          // bank schedule: input particles a wave takes per atomic
     uint64_t cont_budget;    // bank schedule: appends of continuing lines stay within this
     uint32_t* overflow;      // set if an append or a stack push found no room
     uint64_t* family_counter;

@@ -94,6 +94,8 @@ def test_pulse_host_validation_without_gpu(M):
     assert rc == B.EINVAL and "hash" in msg
     rc, msg = call(good, block=96)
     assert rc == B.EINVAL and "block" in msg
+    rc, msg = call(good, chunk=32)
+    assert rc == B.EINVAL and "chunk" in msg
 
 
 def test_pulse_pc_host_validation_without_gpu(M):

@@ -76,6 +76,12 @@ def test_schedules_and_shapes_bit_identical(M, ctx, orc):
             c, _, d = run(M, ctx, p, schedule=schedule, block=block, stack_depth=40)
             assert np.array_equal(c, ref.counts), (schedule, block)
             assert d == ref.diag
+    for chunk in (64, 100, 4096):
+        say("chunk", chunk)
+        for schedule in (M.PULSE_BANK, M.PULSE_EVENT):
+            c, _, d = run(M, ctx, p, schedule=schedule, chunk=chunk)
+            assert np.array_equal(c, ref.counts), (schedule, chunk)
+            assert d == ref.diag
     ps = p.with_(seeding=W.stride_seeding())
     refs = orc.pulse(ps, LCG, threads=8)
     for block in (64, 512):

@@ -68,9 +68,9 @@ def test_small_pc_parity(M, ctx, orc):
 def test_shapes_bit_identical(M, ctx, orc):
     p = W.pulse_pc(n_batches=13, per_batch=257, census_every=3, target=300).with_(first_batch=9)
     ref = orc.pulse_pc(p, LCG, threads=8)
-    for block in (64, 128, 256, 512, 1024):
-        say("pc shape", block)
-        c, f, d, pop = run(M, ctx, p, block=block, schedule=M.PULSE_BANK)
+    for block, chunk in ((64, 0), (128, 64), (256, 0), (256, 3000), (512, 0), (1024, 0)):
+        say("pc shape", block, chunk)
+        c, f, d, pop = run(M, ctx, p, block=block, schedule=M.PULSE_BANK, chunk=chunk)
         assert np.array_equal(pop, ref.pop), block
         assert np.array_equal(c, ref.counts), block
         assert d == ref.diag
