@@ -292,7 +292,9 @@ enum { MCRNG_PULSE_AUTO = 0, MCRNG_PULSE_BANK = 1, MCRNG_PULSE_FAMILY = 2, MCRNG
  *                particle by one flight and its collision and banks all
  *                emerging particles for the next launch (the tail is
  *                finished as for the bank schedule, unless finish_div says
- *                never); AUTO: bank for hash seeding, family for stride
+ *                never); AUTO: for hash seeding the bank below 16 sources per
+ *                resident lane (2048 lanes per CU) and families from there
+ *                on (the bank with population control), family for stride
  *   block        threads per block: 64, 128, 256, 512 or 1024
  *   stack_depth  family schedule: stack entries per lane (default 128; an
  *                entry holds the siblings of one scattering on the current
@@ -372,7 +374,7 @@ typedef struct {
 } mcrng_pulse_pc;
 
 /* Runs a pulse problem with population control: as mcrng_run_pulse (the
- * bank schedule; opts.schedule AUTO or BANK), plus
+ * bank or event schedule; opts.schedule AUTO, BANK or EVENT), plus
  *   d_pop  n_batches x n_census x 2 uint64 (may be NULL): the particles of
  *          each batch reaching each census, and the copies leaving it.
  * Diagnostics: CENSUS counts every census arrival; copies are neither

@@ -1079,9 +1079,20 @@ static int run_pulse(mcrng_ctx* ctx, const mcrng_lcg* lcg, const mcrng_pulse_pro
     if (!d_counts) return fail(MCRNG_EINVAL, "d_counts is NULL");
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t st = static_cast<hipStream_t>(stream);
-    // hash seeding lets every particle run anywhere: the bank; stride
-    // families must run depth first on one lane
-    if (o.schedule == MCRNG_PULSE_AUTO) o.schedule = hash ? MCRNG_PULSE_BANK : MCRNG_PULSE_FAMILY;
+    // hash seeding lets every particle run anywhere: generation banks, or
+    // depth-first families once there are enough of them to fill every lane
+    // many times over (measured crossover on the 1000-source batches: about
+    // 16 families per resident lane); stride families must run depth first
+    // on one lane; population control needs the banks
+    if (o.schedule == MCRNG_PULSE_AUTO) {
+        const uint64_t lanes = static_cast<uint64_t>(pulse_family_grid(static_cast<int>(o.block))) * o.block;
+        if (!hash)
+            o.schedule = MCRNG_PULSE_FAMILY;
+        else if (!pc && n_src >= 16 * lanes)
+            o.schedule = MCRNG_PULSE_FAMILY;
+        else
+            o.schedule = MCRNG_PULSE_BANK;
+    }
 
     PulseParams pp;
     std::memset(&pp, 0, sizeof pp);

@@ -499,6 +499,8 @@ __device__ __forceinline__ void spill(const PulseParams& P, double x, double t, 
 // siblings that find the stack full, go to the output bank.  So a finish
 // launch appends at most (budget + stack_depth + 1) n_max particles and
 // banks at most `budget` census arrivals per input particle.
+constexpr uint32_t kFamilyChunk = 64;   // items a wave of the family kernel takes per atomic
+
 template <bool HASH, int ITEMS, bool PC, int BLOCK>
 __global__ void __launch_bounds__(BLOCK) k_pulse_family(PulseParams P) {
     constexpr bool SOURCES = ITEMS == PULSE_ITEMS_SOURCES;
@@ -524,39 +526,49 @@ __global__ void __launch_bounds__(BLOCK) k_pulse_family(PulseParams P) {
     p.mu = 0.0;
     p.has_mu = false;
     bool active = false;       // the lane holds a particle of a family
-    bool exhausted = false;    // wave-uniform: no items left
+    bool exhausted = false;    // wave-uniform: the item counter has passed the end
+    uint64_t wnext = 0, wend = 0;   // wave-uniform: the wave's untaken items [wnext, wend)
     uint32_t pdraws = 0;       // draws of the current stream (hash: particle; stride: family)
     uint32_t budget = 0;       // finish: particles the current item may still start
 
     for (;;) {
-        // lanes without a family take the next items (one atomic per wave)
+        // lanes without a family take the next items from the wave's chunk
+        // (one atomic per kFamilyChunk items: the counter is one address
+        // for the whole GPU)
         const uint64_t need = __ballot(!active);
-        if (need != 0 && !exhausted) {
-            const uint32_t cnt = static_cast<uint32_t>(__popcll(need));
-            uint64_t wbase = 0;
-            if (lane == 0) wbase = atomicAdd(reinterpret_cast<unsigned long long*>(P.family_counter), cnt);
-            wbase = __shfl(wbase, 0);
-            if (wbase + cnt >= n_items) exhausted = true;
-            if (!active) {
-                const uint64_t j = wbase + lane_prefix(need);
-                if (j < n_items) {
-                    if (SOURCES) {
-                        p.X = pulse_source_state(P, P.src_begin + j, &p.batch);
-                        p.x = 0.0;
-                        p.t = 0.0;
-                        p.tb = P.tb0;
-                        c.sources++;
-                    } else {
-                        load_item<ITEMS>(P, j, p);
-                    }
-                    pdraws = 0;
-                    sp = 0;
-                    budget = P.lane_budget;
-                    active = true;
+        if (need != 0 && wnext == wend && !exhausted) {
+            uint64_t b = 0;
+            if (lane == 0) b = atomicAdd(reinterpret_cast<unsigned long long*>(P.family_counter), kFamilyChunk);
+            b = __shfl(b, 0);
+            if (b + kFamilyChunk >= n_items) exhausted = true;
+            wnext = b < n_items ? b : n_items;
+            wend = b + kFamilyChunk < n_items ? b + kFamilyChunk : n_items;
+        }
+        if (need != 0 && wnext != wend) {
+            const uint64_t avail = wend - wnext;
+            const uint32_t nneed = static_cast<uint32_t>(__popcll(need));
+            const uint32_t take = avail < nneed ? static_cast<uint32_t>(avail) : nneed;
+            const uint32_t rank = lane_prefix(need);
+            const uint64_t wbase = wnext;
+            wnext += take;
+            if (!active && rank < take) {
+                const uint64_t j = wbase + rank;
+                if (SOURCES) {
+                    p.X = pulse_source_state(P, P.src_begin + j, &p.batch);
+                    p.x = 0.0;
+                    p.t = 0.0;
+                    p.tb = P.tb0;
+                    c.sources++;
+                } else {
+                    load_item<ITEMS>(P, j, p);
                 }
+                pdraws = 0;
+                sp = 0;
+                budget = P.lane_budget;
+                active = true;
             }
         }
-        if (__ballot(active) == 0) break;
+        if (__ballot(active) == 0 && wnext == wend && exhausted) break;
         uint32_t n = 0;
         int64_t tally = -1;
         bool at_census = false;
