@@ -12,6 +12,8 @@ Also reported, each timed separately after the headline loop:
   stride        the same workload with stride seeding (X_0 = 1, Q = 152917)
   uniforms      2^26 hash-seeded streams x 16 uniforms written to HBM (GB/s
                 against the 8 TB/s peak)
+  seed_only     the same 2^26 streams seeded alone: init_streams (states to
+                HBM) and the fused kernel with every count 0
   transport     the 1e8-history long-chain slab (50 mfp, c = 0.99, 200 bins,
                 64 batches): histories/s, draws/s, events/s for hash FP64,
                 hash FP32-flight and stride FP64 (kernel time, HIP events)
@@ -90,6 +92,35 @@ def draw_workload(M, W, torch, dev, kind, steps, warmup, d_count, n, total_draws
     kern_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
     return {"ms_per_step": ms_step, "kernel_ms": kern_ms, "draws_per_s": total_draws / (ms_step * 1e-3),
             "chk": chk}
+
+
+def seed_only_leg(M, W, torch, dev, lcg, n, warmup, reps):
+    """Seeding alone over the n streams of the draw workload: mcrng_init_streams
+    (every state written to HBM, 8 B each) and the fused draw kernel with every
+    count 0 (seeds made, checksums 0 written), both seedings."""
+    st = torch.empty(n, dtype=torch.uint64, device=dev)
+    chk = torch.empty(n, dtype=torch.uint64, device=dev)
+    zero = torch.zeros(n, dtype=torch.uint32, device=dev)
+    out = {"streams": n}
+    for kind in ("hash", "stride"):
+        sd = W.hash_seeding() if kind == "hash" else W.stride_seeding()
+        for name, fn in (("init_streams", lambda: M.init_streams(lcg, sd, n, st)),
+                         ("draw_zero_counts", lambda: M.draw(lcg, sd, zero, chk))):
+            for _ in range(warmup):
+                fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            out["%s_%s" % (kind, name)] = {"ms": ms, "seeds_per_s": n / (ms * 1e-3),
+                                           "hbm_gb_per_s": 8.0 * n / (ms * 1e-3) / 1e9}
+    del st, chk, zero
+    torch.cuda.empty_cache()
+    return out
 
 
 def uniforms_leg(M, W, torch, dev, lcg, n, k, warmup, reps):
@@ -264,6 +295,8 @@ def main():
 
     log("uniforms: 2^26 streams x 16 numbers")
     uni = uniforms_leg(M, W, torch, dev, lcg, n, 16, args.warmup, max(3, args.steps // 4))
+    log("seed-only passes")
+    seeds = seed_only_leg(M, W, torch, dev, lcg, n, 3, max(3, args.steps // 4))
 
     chk_hash = hsh["chk"].view(torch.int64).cpu().numpy().view(np.uint64)
     chk_stride = strd["chk"].view(torch.int64).cpu().numpy().view(np.uint64)
@@ -296,6 +329,7 @@ def main():
                            "int_valu_frac": ops_stride / (strd["kernel_ms"] * 1e-3) / INT_VALU_PEAK,
                            "hash_over_stride": strd["ms_per_step"] / hsh["ms_per_step"]},
         "uniforms": uni,
+        "seed_only": seeds,
         "roofline": roofline,
     }
 
@@ -313,6 +347,7 @@ def main():
         tr["fp32_vs_fp64_flux"] = fp32_error(legs["hash_fp32"]["flux"], legs["hash_fp64"]["flux"], prob)
         tr["normality_shapiro_wilk_64_batch_means"] = {
             "hash_fp64": normality(legs["hash_fp64"]["flux"], prob),
+            "hash_fp32": normality(legs["hash_fp32"]["flux"], prob),
             "stride_fp64": normality(legs["stride_fp64"]["flux"], prob)}
         tr["fp32_speedup"] = legs["hash_fp64"]["ms"] / legs["hash_fp32"]["ms"]
         tr["hash_over_stride"] = legs["stride_fp64"]["ms"] / legs["hash_fp64"]["ms"]

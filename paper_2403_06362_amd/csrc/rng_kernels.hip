@@ -9,16 +9,61 @@
 
 namespace mcrng {
 
+// The k-step map of stride seeding, A_{Qk} = x -> G x + C, composed from
+// the skip table's entries for the base-16 digits of k.
+__device__ __forceinline__ void stride_map(const SeedDev& S, uint64_t k, uint64_t* G, uint64_t* C) {
+    uint64_t g = 1, c = 0;
+    for (uint32_t d = 0; d < kStrideDigits && (k >> (kStrideRadixBits * d)) != 0; ++d) {
+        const uint32_t v = static_cast<uint32_t>(k >> (kStrideRadixBits * d)) & (kStrideRadix - 1);
+        const uint64_t* e = S.table + 2 * (d * kStrideRadix + v);
+        c = e[0] * c + e[1];
+        g = e[0] * g;
+    }
+    *G = g;
+    *C = c;
+}
+
+// Stride seeding (256-thread blocks): thread t of block b writes the streams
+// i = b 256 + t + j stride; from the block's first stream X_{Q b 256} (one
+// digit walk) the thread applies A_{Q t} (two table entries), and moves the
+// block base on by A_{Q stride} for the next i.  Same states as
+// stream_start, one affine step per stream.
 __global__ void __launch_bounds__(256) k_init_streams(LcgDev L, SeedDev S, uint64_t n, uint64_t* out) {
-    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-    for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
-        out[i] = stream_start(L, S, i);
+    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * 256;
+    const uint64_t b0 = static_cast<uint64_t>(blockIdx.x) * 256;
+    if (S.kind == SEED_STRIDE) {
+        if (b0 >= n) return;
+        const uint64_t* a = S.table + 2 * (threadIdx.x & (kStrideRadix - 1));
+        const uint64_t* b = S.table + 2 * (kStrideRadix + (threadIdx.x >> kStrideRadixBits));
+        const uint64_t lg = a[0] * b[0], lc = a[0] * b[1] + a[1];
+        uint64_t jg = 0, jc = 0;
+        stride_map(S, stride, &jg, &jc);
+        uint64_t base = stream_start(L, S, b0);
+        for (uint64_t i = b0 + threadIdx.x; i < n; i += stride) {
+            out[i] = affine_apply(lg, lc, L.mask, base);
+            base = affine_apply(jg, jc, L.mask, base);
+        }
+        return;
+    }
+    for (uint64_t i = b0 + threadIdx.x; i < n; i += stride) out[i] = stream_start(L, S, i);
 }
 
 hipError_t launch_init_streams(const LcgDev& L, const SeedDev& S, uint64_t n, uint64_t* out, hipStream_t st) {
     if (n == 0) return hipSuccess;
     uint64_t blocks = (n + 255) / 256;
-    if (blocks > 65536) blocks = 65536;
+    // hash: many short blocks (HBM-bound); stride: fewer, longer-lived
+    // threads, so that each amortises its start (two chains of dependent
+    // table reads) over more streams
+    uint64_t cap = 65536;
+    if (S.kind == SEED_STRIDE) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            cap = static_cast<uint64_t>(cus) * 16;
+        else
+            cap = 4096;
+    }
+    if (blocks > cap) blocks = cap;
     hipLaunchKernelGGL(k_init_streams, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, L, S, n, out);
     return hipGetLastError();
 }
