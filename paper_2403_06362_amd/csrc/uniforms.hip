@@ -16,8 +16,33 @@ template <int MODE>
 __global__ void __launch_bounds__(256) k_uniforms(LcgDev L, SeedDev S, uint64_t n, uint32_t k, uint64_t* state,
                                                   double* u) {
     const uint64_t stride = static_cast<uint64_t>(gridDim.x) * 256;
-    for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * 256 + threadIdx.x; i < n; i += stride) {
-        uint64_t x = (MODE == SEED_LOAD) ? state[i] : stream_start(L, S, i);
+    const uint64_t b0 = static_cast<uint64_t>(blockIdx.x) * 256;
+    // stride seeding: stream b0 + t + j stride starts at A_{Q t} of the
+    // block's base, which moves on by A_{Q stride} (one affine step each)
+    uint64_t lg = 1, lc = 0, jg = 1, jc = 0, base = 0;
+    if (MODE == SEED_STRIDE && b0 < n) {
+        const uint64_t* a = S.table + 2 * (threadIdx.x & (kStrideRadix - 1));
+        const uint64_t* b = S.table + 2 * (kStrideRadix + (threadIdx.x >> kStrideRadixBits));
+        lg = a[0] * b[0];
+        lc = a[0] * b[1] + a[1];
+        for (uint32_t d = 0; d < kStrideDigits && (stride >> (kStrideRadixBits * d)) != 0; ++d) {
+            const uint32_t v = static_cast<uint32_t>(stride >> (kStrideRadixBits * d)) & (kStrideRadix - 1);
+            const uint64_t* e = S.table + 2 * (d * kStrideRadix + v);
+            jc = e[0] * jc + e[1];
+            jg = e[0] * jg;
+        }
+        base = stream_start(L, S, b0);
+    }
+    for (uint64_t i = b0 + threadIdx.x; i < n; i += stride) {
+        uint64_t x;
+        if (MODE == SEED_LOAD) {
+            x = state[i];
+        } else if (MODE == SEED_STRIDE) {
+            x = affine_apply(lg, lc, L.mask, base);
+            base = affine_apply(jg, jc, L.mask, base);
+        } else {
+            x = stream_start(L, S, i);
+        }
         double* out = u + i;
         for (uint32_t j = 0; j < k; ++j) {
             x = lcg_next(L, x);

@@ -191,6 +191,30 @@ def test_uniforms_parity(M, orc, kind, n, k):
     assert np.array_equal(_uniforms(M, sd, n, k), orc.uniforms(LCG, sd, n, k))
 
 
+def test_stride_seeding_across_grid_strides(M, orc):
+    """2^25 streams: every thread of init_streams and of the uniforms kernel
+    seeds several streams, the later ones by the grid-stride jump from its
+    block's base; an offset first index and another stride.  Sampled streams
+    against the oracle."""
+    import torch
+    n, k = 1 << 25, 2
+    sd = W.Seeding("stride", 3, 1000003, 777)
+    say("stride across grid strides")
+    st = _empty_u64(n)
+    M.init_streams(LCG, sd, n, st)
+    u = torch.empty((k, n), dtype=torch.float64, device="cuda:0")
+    M.uniforms(LCG, sd, u)
+    torch.cuda.synchronize()
+    gst, gu = u64_np(st), u.cpu().numpy()
+    rng = np.random.default_rng(33)
+    idx = np.concatenate([np.arange(300), np.arange(n - 300, n), rng.integers(0, n, 3000)])
+    for i in idx:
+        i = int(i)
+        one = W.Seeding("stride", 3, 1000003, 777 + i)
+        assert int(gst[i]) == orc.stream_start(LCG, one, 0), i
+        assert np.array_equal(gu[:, i], orc.uniforms(LCG, one, 1, k)[:, 0]), i
+
+
 def test_uniforms_load_mode_and_final_states(M, orc):
     """Start states loaded from HBM give the seeded run's numbers; the final
     states equal those mcrng_draw leaves after the same number of steps."""
