@@ -12,7 +12,7 @@
 //                  particle can run anywhere, in any order;
 //   stride seeding they continue the source's one stream, depth first.
 //
-// Two schedules:
+// Schedules:
 //   k_pulse_bank (hash only)  one launch per generation.  A wave takes a chunk
 //       of input particles (or sources) at a time through one atomic and hands
 //       them to its idle lanes; a lane runs each one's line of descent: at a
@@ -23,13 +23,17 @@
 //       budget; past it, a scattering banks all n particles and ends the
 //       line.  Appends are thus at most budget + n_max per input particle +
 //       one stage and one iteration's appends per wave (the view lags by at
-//       most a stage), which the output capacity covers.
-//   k_pulse_family            one source family per lane (taken from a
-//       global counter, one atomic per wave), walked depth first with a
-//       per-lane stack in HBM; a stack entry holds the siblings still to
-//       start of one scattering (stride: a count; hash: X_p and the next
-//       key), so the depth is at most the number of scatterings on the
-//       current line of descent.
+//       most a stage), which the output capacity covers.  With no budget
+//       (the event-based schedule) every scattering banks all n particles:
+//       each launch advances every live particle by one flight.
+//   k_pulse_family            one source family per lane (sources taken 64
+//       per wave and atomic), walked depth first with a per-lane stack in
+//       HBM; a stack entry holds the siblings still to start of one
+//       scattering (stride: a count; hash: X_p and the next key), so the
+//       depth is at most the number of scatterings on the current line of
+//       descent.  With bank items (hash seeding) the same kernel finishes
+//       a bank schedule's tail: up to a budget of particles per item, the
+//       rest banked for the next launch.
 // Counts are integers added with 64-bit atomics (into a per-block LDS copy
 // of every counter when they fit, else one HBM atomic per distinct counter
 // of a wave), so every schedule, launch shape and order gives the same

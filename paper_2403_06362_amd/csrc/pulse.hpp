@@ -91,7 +91,7 @@ struct PulseParams {
 enum PulseItems : int { PULSE_ITEMS_SOURCES = 0, PULSE_ITEMS_BANK = 1, PULSE_ITEMS_COPIES = 2 };
 constexpr uint32_t kPulsePcChunkBatches = 4096;   // batches per chunk of a population-controlled run
 
-// Bank launches: the grid (resident blocks, at most one 256-item chunk per
+// Bank launches: the grid (resident blocks, at most one chunk of items per
 // wave) is chosen first, so that the caller can size the output for it.
 // `items` is a PulseItems value; `pc`: the launch's census is a census of
 // population control (arrivals are banked in p.cen).
