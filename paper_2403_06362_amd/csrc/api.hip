@@ -1222,7 +1222,8 @@ static int run_pulse(mcrng_ctx* ctx, const mcrng_lcg* lcg, const mcrng_pulse_pro
             // event schedule: no line runs on within a launch (one flight
             // and collision per particle and launch)
             const uint64_t budget = o.schedule == MCRNG_PULSE_EVENT ? 0 : 2 * n;
-            const uint64_t slack = (waves + 1) * (256 + 64 * static_cast<uint64_t>(n_max));
+            const uint64_t slack =
+                (waves + 1) * (pulse_bank_stage(static_cast<int>(o.block)) + 64 * static_cast<uint64_t>(n_max));
             const uint64_t ocap = budget + static_cast<uint64_t>(n_max) * n + slack;
             int r = ensure(ctx->pulse_bank[nxt], ocap * 32, st, 8);
             if (r < 0) return r;

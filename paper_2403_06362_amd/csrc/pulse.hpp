@@ -97,6 +97,8 @@ constexpr uint32_t kPulsePcChunkBatches = 4096;   // batches per chunk of a popu
 // population control (arrivals are banked in p.cen).
 uint32_t pulse_bank_grid(const PulseParams& p, int items_kind, bool pc, int block, uint64_t items);
 constexpr uint32_t kPulseLdsCounters = 2048;   // block-local tally copies up to this many counters (16 KiB)
+// Entries of a wave's LDS stage of appends in k_pulse_bank (output slack).
+uint32_t pulse_bank_stage(int block);
 hipError_t launch_pulse_bank(const PulseParams& p, int items_kind, bool pc, int block, uint32_t grid,
                              hipStream_t st);
 // Population control at census p.census: arrival counts per batch into
