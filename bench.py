@@ -13,7 +13,7 @@ Also reported, each timed separately after the headline loop:
   uniforms      2^26 hash-seeded streams x 16 uniforms written to HBM (GB/s
                 against the 8 TB/s peak)
   seed_only     the same 2^26 streams seeded alone: init_streams (states to
-                HBM) and the fused kernel with every count 0
+                HBM)
   transport     the 1e8-history long-chain slab (50 mfp, c = 0.99, 200 bins,
                 64 batches): histories/s, draws/s, events/s for hash FP64,
                 hash FP32-flight and stride FP64 (kernel time, HIP events)
@@ -95,17 +95,14 @@ def draw_workload(M, W, torch, dev, kind, steps, warmup, d_count, n, total_draws
 
 
 def seed_only_leg(M, W, torch, dev, lcg, n, warmup, reps):
-    """Seeding alone over the n streams of the draw workload: mcrng_init_streams
-    (every state written to HBM, 8 B each) and the fused draw kernel with every
-    count 0 (seeds made, checksums 0 written), both seedings."""
+    """Seeding alone over the n streams of the draw workload:
+    mcrng_init_streams (every state written to HBM, 8 B each), both
+    seedings."""
     st = torch.empty(n, dtype=torch.uint64, device=dev)
-    chk = torch.empty(n, dtype=torch.uint64, device=dev)
-    zero = torch.zeros(n, dtype=torch.uint32, device=dev)
     out = {"streams": n}
     for kind in ("hash", "stride"):
         sd = W.hash_seeding() if kind == "hash" else W.stride_seeding()
-        for name, fn in (("init_streams", lambda: M.init_streams(lcg, sd, n, st)),
-                         ("draw_zero_counts", lambda: M.draw(lcg, sd, zero, chk))):
+        for name, fn in (("init_streams", lambda: M.init_streams(lcg, sd, n, st)),):
             for _ in range(warmup):
                 fn()
             torch.cuda.synchronize()
@@ -118,7 +115,7 @@ def seed_only_leg(M, W, torch, dev, lcg, n, warmup, reps):
             ms = e0.elapsed_time(e1) / reps
             out["%s_%s" % (kind, name)] = {"ms": ms, "seeds_per_s": n / (ms * 1e-3),
                                            "hbm_gb_per_s": 8.0 * n / (ms * 1e-3) / 1e9}
-    del st, chk, zero
+    del st
     torch.cuda.empty_cache()
     return out
 
