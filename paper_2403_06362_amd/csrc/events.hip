@@ -100,71 +100,105 @@ __global__ void __launch_bounds__(256) k_event_init(EventParams E) {
 }
 
 constexpr int kEventStepBlock = 1024;
+constexpr int kEventStepPer = 4;             // particles per thread: a block takes 4096 consecutive ones
+constexpr uint32_t kEventLdsBins = 2048;     // home-unit tally bins a block keeps in LDS (32 KiB)
 
+// A block advances the 4096 consecutive bank particles from
+// blockIdx * 4096 by one event each.  The bank stays ordered by work unit in
+// runs (the init fills it in order, each compaction keeps a block's order),
+// so most of a block's particles belong to the unit of its first one (its
+// home unit): their scores go to an LDS copy of that unit's tally, added to
+// the unit's slot once at the end; other particles' scores go straight to
+// their slots.  Integer sums, so the bits do not depend on where a score is
+// added first.  (An LDS copy of the home problem's cells as well measured no
+// faster.)
 template <bool F32, bool TIMED>
 __global__ void __launch_bounds__(kEventStepBlock) k_event_step(EventParams E) {
     constexpr int kWaves = kEventStepBlock / 64;
     __shared__ uint32_t s_wave_count[kWaves];
     __shared__ uint32_t s_base;
-    const uint32_t i = blockIdx.x * kEventStepBlock + threadIdx.x;
+    __shared__ unsigned long long s_tally[2 * kEventLdsBins];
+    __shared__ uint32_t s_home, s_home_words;
+    __shared__ uint64_t s_home_slot;
+    const uint32_t b0 = blockIdx.x * (kEventStepBlock * kEventStepPer);
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wid = threadIdx.x >> 6;
-    bool alive = false;
-    Particle<F32> p;
-    uint32_t unit = 0, rec = 0;
-    LaneCounters cnt;
-    if (i < E.n_in) {
-        BankView<F32> v = view<F32>(E.in);
-        p.x = v.x[i];
-        p.mu = v.mu[i];
-        p.t = v.t[i];
-        p.tau = v.tau[i];
-        p.X = E.in.X[i];
-        p.cell = E.in.cell[i];
-        p.tb = E.in.tb[i];
-        p.hdraws = E.in.hdraws[i];
-        p.need_tau = (E.in.flags[i] & 1u) != 0;
-        cnt.events = E.in.events[i];
-        cnt.collisions = E.in.colls[i];
-        unit = E.in.unit[i];
-        rec = E.in.rec[i];
-        const WorkUnit U = E.tp.units[unit];
-        const DevProblem PR = E.tp.problems[U.problem];
-        const CellsLds<F32> C = global_cells<F32>(E.tp, PR);
-        uint64_t* tally = E.tp.partial + U.slot;
-        const int end = step_particle<F32, TIMED>(p, C, E.tp.lcg, tally, cnt);
-        if (end != END_NONE) {
-            HistoryRecord h;
-            h.events = static_cast<uint32_t>(cnt.events);
-            h.collisions = static_cast<uint32_t>(cnt.collisions);
-            h.draws = p.hdraws;
-            h.end = static_cast<uint32_t>(end);
-            E.records[rec] = h;
-        } else {
-            alive = true;
-        }
-    }
-    // compaction: the block's survivors go to consecutive slots of `out`
-    // through one atomic per block (a single counter hit once per wave by
-    // every wave of the GPU serialises)
-    const uint64_t mask = __ballot(alive);
-    if (lane == 0) s_wave_count[wid] = static_cast<uint32_t>(__popcll(mask));
-    __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t total = 0;
-        for (int w = 0; w < kWaves; ++w) {
-            const uint32_t c = s_wave_count[w];
-            s_wave_count[w] = total;
-            total += c;
-        }
-        s_base = total ? atomicAdd(E.n_out, total) : 0u;
+        const uint32_t u = E.in.unit[b0];   // b0 < n_in for every block of the grid
+        const WorkUnit U = E.tp.units[u];
+        const bool fits = U.slice_bins <= kEventLdsBins;
+        s_home = fits ? u : 0xffffffffu;
+        s_home_words = fits ? 2 * U.slice_bins : 0u;
+        s_home_slot = U.slot;
     }
     __syncthreads();
-    if (alive) {
-        const uint32_t lt = static_cast<uint32_t>(__popcll(mask & ((lane == 0) ? 0ull : (~0ull >> (64 - lane)))));
-        store_particle<F32>(E.out, s_base + s_wave_count[wid] + lt, p, static_cast<uint32_t>(cnt.events),
-                            static_cast<uint32_t>(cnt.collisions), unit, rec);
+    const uint32_t home = s_home;
+    for (uint32_t w = threadIdx.x; w < s_home_words; w += kEventStepBlock) s_tally[w] = 0;
+    __syncthreads();
+
+    for (int k = 0; k < kEventStepPer; ++k) {
+        const uint32_t i = b0 + static_cast<uint32_t>(k) * kEventStepBlock + threadIdx.x;
+        bool alive = false;
+        Particle<F32> p;
+        uint32_t unit = 0, rec = 0;
+        LaneCounters cnt;
+        if (i < E.n_in) {
+            BankView<F32> v = view<F32>(E.in);
+            p.x = v.x[i];
+            p.mu = v.mu[i];
+            p.t = v.t[i];
+            p.tau = v.tau[i];
+            p.X = E.in.X[i];
+            p.cell = E.in.cell[i];
+            p.tb = E.in.tb[i];
+            p.hdraws = E.in.hdraws[i];
+            p.need_tau = (E.in.flags[i] & 1u) != 0;
+            cnt.events = E.in.events[i];
+            cnt.collisions = E.in.colls[i];
+            unit = E.in.unit[i];
+            rec = E.in.rec[i];
+            const WorkUnit U = E.tp.units[unit];
+            const DevProblem PR = E.tp.problems[U.problem];
+            const CellsLds<F32> C = global_cells<F32>(E.tp, PR);
+            uint64_t* tally = (unit == home) ? reinterpret_cast<uint64_t*>(s_tally) : E.tp.partial + U.slot;
+            const int end = step_particle<F32, TIMED>(p, C, E.tp.lcg, tally, cnt);
+            if (end != END_NONE) {
+                HistoryRecord h;
+                h.events = static_cast<uint32_t>(cnt.events);
+                h.collisions = static_cast<uint32_t>(cnt.collisions);
+                h.draws = p.hdraws;
+                h.end = static_cast<uint32_t>(end);
+                E.records[rec] = h;
+            } else {
+                alive = true;
+            }
+        }
+        // compaction: the block's survivors go to consecutive slots of `out`
+        // through one atomic per block and pass (a single counter hit once
+        // per wave by every wave of the GPU serialises)
+        const uint64_t mask = __ballot(alive);
+        if (lane == 0) s_wave_count[wid] = static_cast<uint32_t>(__popcll(mask));
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t total = 0;
+            for (int w = 0; w < kWaves; ++w) {
+                const uint32_t c = s_wave_count[w];
+                s_wave_count[w] = total;
+                total += c;
+            }
+            s_base = total ? atomicAdd(E.n_out, total) : 0u;
+        }
+        __syncthreads();
+        if (alive) {
+            const uint32_t lt = static_cast<uint32_t>(__popcll(mask & ((lane == 0) ? 0ull : (~0ull >> (64 - lane)))));
+            store_particle<F32>(E.out, s_base + s_wave_count[wid] + lt, p, static_cast<uint32_t>(cnt.events),
+                                static_cast<uint32_t>(cnt.collisions), unit, rec);
+        }
+        __syncthreads();   // s_wave_count and s_base are reused by the next pass
     }
+    for (uint32_t w = threadIdx.x; w < s_home_words; w += kEventStepBlock)
+        if (s_tally[w] != 0)
+            atomicAdd(reinterpret_cast<unsigned long long*>(E.tp.partial + s_home_slot) + w, s_tally[w]);
 }
 
 // The particles of a small bank run to the end of their histories, one per
@@ -249,8 +283,9 @@ static hipError_t init_t(const EventParams& p, hipStream_t st) {
 
 template <bool F32, bool TIMED>
 static hipError_t step_t(const EventParams& p, hipStream_t st) {
-    hipLaunchKernelGGL((k_event_step<F32, TIMED>), dim3((p.n_in + kEventStepBlock - 1) / kEventStepBlock),
-                       dim3(kEventStepBlock), 0, st, p);
+    constexpr uint32_t per_block = kEventStepBlock * kEventStepPer;
+    hipLaunchKernelGGL((k_event_step<F32, TIMED>), dim3((p.n_in + per_block - 1) / per_block), dim3(kEventStepBlock),
+                       0, st, p);
     return hipGetLastError();
 }
 
