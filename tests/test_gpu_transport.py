@@ -155,6 +155,21 @@ def test_event_schedule_batched_and_stride(M, ctx, orc):
         assert parts[i] == orc.transport(probs[i], LCG).raw
 
 
+def test_event_schedule_tallies_past_the_lds_copy(M, ctx, orc):
+    """A block of the event-sorted schedule keeps its home unit's tally in
+    LDS only up to 2048 bins; a larger tally is scored straight into HBM.
+    A set mixing tallies above, at and below that size gives the oracle's
+    bits either way."""
+    probs = [W.multi_region(n_histories=20_011, n_space_bins=130, n_time_bins=20),          # 2600 bins
+             W.multi_region(n_histories=9_001, seed=5, n_space_bins=128, n_time_bins=16),   # 2048 bins
+             W.small_slab(n_histories=5_000)]
+    ref = [orc.transport(p, LCG, threads=8).raw for p in probs]
+    for bank, unit in ((0, 0), (6_000, 2_000)):
+        say("event schedule large tallies", bank, unit)
+        ev = run(M, ctx, probs, schedule=1, bank_size=bank, unit_histories=unit)
+        assert split(ev[0], probs) == ref, (bank, unit)
+
+
 def test_zero_histories_and_edge_problems(M, ctx, orc):
     probs = [W.small_slab(n_histories=0), W.small_slab(n_histories=1),
              W.homogeneous(1.0, 2.0, 0.0, 1, 777), W.small_slab(n_histories=64)]
