@@ -158,16 +158,23 @@ __global__ void __launch_bounds__(256) k_draw(DrawParams P) {
         if (jn < nw) c_next = P.count[lo + jn];
     }
 
-    uint64_t x = 0, sum = 0;
+    // HALVES (m = 63, c = 1, state not stored): x holds 2 X, which follows
+    // 2X <- g (2X) + 2 mod 2^64 with no mask; the checksum is kept as the
+    // exact sums of the low and the high 32-bit words of 2X (each below
+    // 2^64 for fewer than 2^32 draws), so sum X mod 2^64 =
+    // (lo_sum >> 1) + (hi_sum << 31).  A masked draw slot then costs a
+    // bit-field extract and two 32 x 32 + 64 multiply-adds.
+    constexpr bool HALVES = M63C1 && !STORE_STATE;
+    uint64_t x = 0, sum = 0, hsum = 0;
     uint32_t sid = 0, rem = 0;
     bool active = false;
     for (;;) {
         if (active && rem == 0) {
-            P.checksum[lo + sid] = sum;
+            P.checksum[lo + sid] = HALVES ? (sum >> 1) + (hsum << 31) : sum;
             if (STORE_STATE) P.state[lo + sid] = x;
             active = false;
         }
-        const uint64_t need = __ballot(!active);
+        const uint64_t need = __builtin_amdgcn_ballot_w64(!active);
         const uint32_t left = nw - next;   // streams not yet handed out
         if (need != 0 && left != 0) {
             const uint32_t nneed = static_cast<uint32_t>(__popcll(need));
@@ -176,10 +183,11 @@ __global__ void __launch_bounds__(256) k_draw(DrawParams P) {
                                                             __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(need), 0u));
             if (!active && rank < take) {
                 const uint32_t e = (next + rank) & 127u;
-                x = rstate[e];
+                x = HALVES ? rstate[e] << 1 : rstate[e];
                 rem = rcount[e];
                 sid = next + rank;
                 sum = 0;
+                hsum = 0;
                 active = true;
             }
             next = __builtin_amdgcn_readfirstlane(next + take);
@@ -199,8 +207,9 @@ __global__ void __launch_bounds__(256) k_draw(DrawParams P) {
                 filled += 64u;
             }
         }
-        if (__ballot(active) == 0) break;
-        const uint32_t k = active ? (rem < static_cast<uint32_t>(D) ? rem : static_cast<uint32_t>(D)) : 0u;
+        if (__builtin_amdgcn_ballot_w64(active) == 0) break;
+        // a lane without a stream has rem == 0
+        const uint32_t k = rem < static_cast<uint32_t>(D) ? rem : static_cast<uint32_t>(D);
         if (STORE_STATE) {
 #pragma unroll
             for (int d = 0; d < D; ++d) {
@@ -208,6 +217,18 @@ __global__ void __launch_bounds__(256) k_draw(DrawParams P) {
                     x = draw_step<M63C1>(P.lcg, x, g);
                     sum += x;
                 }
+            }
+        } else if (HALVES) {
+            const uint32_t fb = (D < 32 || k < 32u) ? (1u << k) - 1u : 0xffffffffu;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                x = g * x + 2ull;
+                uint32_t f = __builtin_amdgcn_ubfe(fb, static_cast<uint32_t>(d), 1u);
+                // hides that f <= 1, so that each product-sum stays one
+                // v_mad_u64_u32 (not a 32-bit multiply and a 64-bit add)
+                asm("" : "+v"(f));
+                sum += static_cast<uint64_t>(static_cast<uint32_t>(x)) * f;
+                hsum += static_cast<uint64_t>(static_cast<uint32_t>(x >> 32)) * f;
             }
         } else {
             // the state may run past the end of the stream (it is not

@@ -89,6 +89,33 @@ def test_draw_parity(M, orc, mode, n):
     assert np.array_equal(u64_np(chk)[:n], ref)
 
 
+@pytest.mark.parametrize("rnd", [8, 16, 20, 32])
+def test_draw_round_lengths(M, orc, monkeypatch, rnd):
+    """Every round length of the draw kernel (MCRNG_DRAW_ROUND), with counts
+    on either side of its multiples, a long stream, both seedings, with and
+    without final states (two kernel bodies), and the 48-bit generator with
+    c = 3 (the generic step): every checksum and state is the oracle's."""
+    import torch
+    monkeypatch.setenv("MCRNG_DRAW_ROUND", str(rnd))
+    edge = [0, 1, 2, 7, 8, 9, 15, 16, 17, 19, 20, 21, 31, 32, 33, 63, 64, 65, 96, 97, 1 << 16, 3_000_001]
+    counts = np.concatenate([np.array(edge, dtype=np.uint32), W.draw_counts(20_000, seed=rnd)])
+    n = len(counts)
+    m48 = W.Lcg(W.G_MCNP % (1 << 48), 3, 48)
+    for lcg, sd in ((LCG, W.hash_seeding()), (LCG, W.stride_seeding()), (m48, W.Seeding("stride", 5, 1000003, 0))):
+        ref = orc.seed_and_draw(lcg, sd, counts, threads=8)
+        states = orc.init_streams(lcg, sd, n)
+        orc.seed_and_draw(lcg, None, counts, states=states)
+        for with_state in (False, True):
+            say("draw round", rnd, lcg.m, sd.kind, with_state)
+            chk = _empty_u64(n)
+            st = _empty_u64(n) if with_state else None
+            M.draw(lcg, sd, to_dev_u32(counts), chk, d_state=st)
+            torch.cuda.synchronize()
+            assert np.array_equal(u64_np(chk)[:n], ref), (rnd, lcg.m, sd.kind, with_state)
+            if with_state:
+                assert np.array_equal(u64_np(st)[:n], states), (rnd, lcg.m, sd.kind)
+
+
 @pytest.mark.parametrize("gen", ["mcnp", "m48"])
 def test_draw_stride_batches_offsets_generators(M, orc, gen):
     """Stride seeding in the draw kernel seeds 64 consecutive streams per
