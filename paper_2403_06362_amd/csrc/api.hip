@@ -242,6 +242,7 @@ struct mcrng_ctx {
     std::vector<double> h_pulse_tedges;
     uint64_t* h_pinned = nullptr;   // pinned host words for per-generation readbacks
     std::vector<uint64_t> h_rec_begin;
+    std::vector<uint32_t> h_group_first;   // per unit: the first unit of its (problem, batch) (host only)
 
     // host copies of the current tables (kept alive while copies are staged)
     std::vector<DevProblem> h_problems;
@@ -575,6 +576,9 @@ static int build_tables(mcrng_ctx* ctx, const LcgDev& L, const mcrng_problem* P,
     ctx->h_rec_begin.assign(ctx->h_units.size() + 1, 0);
     for (size_t u = 0; u < ctx->h_units.size(); ++u)
         ctx->h_rec_begin[u + 1] = ctx->h_rec_begin[u] + ctx->h_units[u].count;
+    ctx->h_group_first.assign(std::max<size_t>(ctx->h_units.size(), 1), 0);
+    for (const ReduceGroup& G : ctx->h_groups)
+        for (uint32_t u = G.unit_begin; u < G.unit_end; ++u) ctx->h_group_first[u] = G.unit_begin;
     int rc;
     if ((rc = upload(ctx->problems, ctx->h_problems, st)) < 0) return rc;
     if ((rc = upload(ctx->edges64, ctx->h_edges64, st)) < 0) return rc;
@@ -770,6 +774,7 @@ static int run_event_schedule(mcrng_ctx* ctx, const LcgDev& L, const mcrng_run_o
         while (u1 < nu && ctx->h_rec_begin[u1 + 1] - ctx->h_rec_begin[u0] <= cap) ++u1;
         ep.unit_begin = u0;
         ep.unit_end = u1;
+        ep.one_group = ctx->h_group_first[u1 - 1] <= u0;   // units [u0, u1) of one (problem, batch)
         ep.in = A;
         ep.out = B;
         ep.n_in = static_cast<uint32_t>(ctx->h_rec_begin[u1] - ctx->h_rec_begin[u0]);

@@ -4,10 +4,19 @@
 // k_event_step advances every live particle by exactly one event (the same
 // step_particle as the history-based kernel, so the per-particle operation
 // sequence is identical); survivors are appended to the other bank through
-// one atomic per 1024-thread block, so each launch compacts the bank.  Scores go to the
-// work unit's partial-tally slot with 64-bit global integer atomics (the
-// slots are zeroed first); the sums are exact, so the result is the same as
-// the history-based schedule's bit for bit.  A history that ends writes one
+// one atomic per 1024-thread block, so each launch compacts the bank.  A
+// particle scores into the partial-tally slot of its score unit: its own work
+// unit, or, when the slice holds a single (problem, batch), the slice's first
+// unit.  The reduction adds every unit slot of a (problem, batch), so any
+// slot of it gives the same sum; with one slot for the whole slice every
+// block's particles share its home slot (below) however the compaction
+// orders them.  That slot may collect more than 2^32 additions per word, so
+// its global adds carry a wrap of the low word into the high one
+// (carry_add).  The slots are zeroed first and the sums are exact, so the
+// result is the same as the history-based schedule's bit for bit.  (Scoring
+// a mixed slice by (problem, batch) as well measured 12x slower on 64
+// problems: its particles are mostly away from home, and one slot per
+// problem concentrates their atomics.)  A history that ends writes one
 // outcome record; k_event_unit_diag reduces the records of each unit in
 // history order into the unit's diagnostics slot.  Once a slice's bank is
 // small, k_event_finish runs its remaining particles to their ends (one per
@@ -88,6 +97,7 @@ __global__ void __launch_bounds__(256) k_event_init(EventParams E) {
     const WorkUnit U = E.tp.units[lo];
     const DevProblem PR = E.tp.problems[U.problem];
     const CellsLds<F32> C = global_cells<F32>(E.tp, PR);
+    const uint32_t su = E.one_group ? E.unit_begin : lo;   // score unit
     SeedDev S;
     S.kind = static_cast<int>(PR.seed_kind);
     S.stride_digits = PR.stride_digits;
@@ -96,7 +106,7 @@ __global__ void __launch_bounds__(256) k_event_init(EventParams E) {
     S.table = PR.table;
     Particle<F32> p;
     init_particle<F32, TIMED>(p, C, E.tp.lcg, S, U.j0 + (r - E.rec_begin[lo]));
-    store_particle<F32>(E.in, i, p, 0u, 0u, lo, static_cast<uint32_t>(r));
+    store_particle<F32>(E.in, i, p, 0u, 0u, su, static_cast<uint32_t>(r));
 }
 
 constexpr int kEventStepBlock = 1024;
@@ -104,14 +114,14 @@ constexpr int kEventStepPer = 4;             // particles per thread: a block ta
 constexpr uint32_t kEventLdsBins = 2048;     // home-unit tally bins a block keeps in LDS (32 KiB)
 
 // A block advances the 4096 consecutive bank particles from
-// blockIdx * 4096 by one event each.  The bank stays ordered by work unit in
-// runs (the init fills it in order, each compaction keeps a block's order),
-// so most of a block's particles belong to the unit of its first one (its
-// home unit): their scores go to an LDS copy of that unit's tally, added to
-// the unit's slot once at the end; other particles' scores go straight to
-// their slots.  Integer sums, so the bits do not depend on where a score is
-// added first.  (An LDS copy of the home problem's cells as well measured no
-// faster.)
+// blockIdx * 4096 by one event each.  Particles of the score unit of the
+// block's first particle (its home unit: all of them when the slice holds one
+// (problem, batch)) score into an LDS copy of that unit's tally, added to the
+// unit's slot once at the end; other particles' scores go straight to their
+// slots.  Integer sums, so the bits do not depend on where a score is added
+// first.  (An LDS copy of the home problem's cells as well measured no
+// faster.)  Global adds into a one-group slice's slot carry; a unit's own
+// slot takes at most its histories' scores, as in the history schedule.
 template <bool F32, bool TIMED>
 __global__ void __launch_bounds__(kEventStepBlock) k_event_step(EventParams E) {
     constexpr int kWaves = kEventStepBlock / 64;
@@ -160,8 +170,9 @@ __global__ void __launch_bounds__(kEventStepBlock) k_event_step(EventParams E) {
             const WorkUnit U = E.tp.units[unit];
             const DevProblem PR = E.tp.problems[U.problem];
             const CellsLds<F32> C = global_cells<F32>(E.tp, PR);
-            uint64_t* tally = (unit == home) ? reinterpret_cast<uint64_t*>(s_tally) : E.tp.partial + U.slot;
-            const int end = step_particle<F32, TIMED>(p, C, E.tp.lcg, tally, cnt);
+            const int end = (unit == home)  ? step_particle<F32, TIMED>(p, C, E.tp.lcg, reinterpret_cast<uint64_t*>(s_tally), cnt)
+                            : E.one_group   ? step_particle<F32, TIMED, true>(p, C, E.tp.lcg, E.tp.partial + U.slot, cnt)
+                                            : step_particle<F32, TIMED>(p, C, E.tp.lcg, E.tp.partial + U.slot, cnt);
             if (end != END_NONE) {
                 HistoryRecord h;
                 h.events = static_cast<uint32_t>(cnt.events);
@@ -196,9 +207,9 @@ __global__ void __launch_bounds__(kEventStepBlock) k_event_step(EventParams E) {
         }
         __syncthreads();   // s_wave_count and s_base are reused by the next pass
     }
-    for (uint32_t w = threadIdx.x; w < s_home_words; w += kEventStepBlock)
-        if (s_tally[w] != 0)
-            atomicAdd(reinterpret_cast<unsigned long long*>(E.tp.partial + s_home_slot) + w, s_tally[w]);
+    // a block's LDS words stay below 4096 x 2^32; the slot's may wrap
+    for (uint32_t w = 2 * threadIdx.x; w < s_home_words; w += 2 * kEventStepBlock)
+        if ((s_tally[w] | s_tally[w + 1]) != 0) carry_add(E.tp.partial + s_home_slot + w, s_tally[w], s_tally[w + 1]);
 }
 
 // The particles of a small bank run to the end of their histories, one per
@@ -229,7 +240,10 @@ __global__ void __launch_bounds__(256) k_event_finish(EventParams E) {
     const CellsLds<F32> C = global_cells<F32>(E.tp, PR);
     uint64_t* tally = E.tp.partial + U.slot;
     int end = END_NONE;
-    while (end == END_NONE) end = step_particle<F32, TIMED>(p, C, E.tp.lcg, tally, cnt);
+    if (E.one_group)
+        while (end == END_NONE) end = step_particle<F32, TIMED, true>(p, C, E.tp.lcg, tally, cnt);
+    else
+        while (end == END_NONE) end = step_particle<F32, TIMED>(p, C, E.tp.lcg, tally, cnt);
     HistoryRecord h;
     h.events = static_cast<uint32_t>(cnt.events);
     h.collisions = static_cast<uint32_t>(cnt.collisions);

@@ -164,6 +164,9 @@ struct EventParams {
     // init: the histories of units [unit_begin, unit_end), n_in in total
     uint32_t unit_begin;
     uint32_t unit_end;
+    // the slice holds one (problem, batch): its particles all score into the
+    // slice's first unit (global adds then carry, carry_add)
+    uint32_t one_group;
 };
 
 hipError_t launch_event_init(const EventParams& p, int f32, int timed, hipStream_t st);

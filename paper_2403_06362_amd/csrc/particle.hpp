@@ -55,10 +55,29 @@ struct LaneCounters {
 };
 
 // Adds q to a tally word pair: the low and the high 32-bit halves of q are
-// summed into separate 64-bit words (LDS or global memory).
+// summed into separate 64-bit words (LDS or global memory); the pair holds
+// low + 2^32 high.
 __device__ __forceinline__ void lds_score(uint64_t* slot, uint64_t q) {
     atomicAdd(reinterpret_cast<unsigned long long*>(slot), static_cast<unsigned long long>(q & 0xffffffffull));
     atomicAdd(reinterpret_cast<unsigned long long*>(slot + 1), static_cast<unsigned long long>(q >> 32));
+}
+
+// Adds lo + 2^32 hi to a global word pair that may collect more than 2^32
+// additions: when the low word wraps (it lost 2^64 = 2^32 x 2^32), 2^32 more
+// goes to the high word, so the pair's value stays exact below 2^96.
+__device__ __forceinline__ void carry_add(uint64_t* slot, uint64_t lo, uint64_t hi) {
+    const unsigned long long old = atomicAdd(reinterpret_cast<unsigned long long*>(slot), static_cast<unsigned long long>(lo));
+    if (old + lo < old) hi += 1ull << 32;
+    if (hi != 0) atomicAdd(reinterpret_cast<unsigned long long*>(slot + 1), static_cast<unsigned long long>(hi));
+}
+
+// A score: lds_score, or (CARRY) carry_add into a global pair.
+template <bool CARRY>
+__device__ __forceinline__ void add_score(uint64_t* slot, uint64_t q) {
+    if constexpr (CARRY)
+        carry_add(slot, q & 0xffffffffull, q >> 32);
+    else
+        lds_score(slot, q);
 }
 
 template <bool F32>
@@ -82,7 +101,7 @@ __device__ __forceinline__ void sample_tau(Particle<F32>& p, const LcgDev& L) {
 //          mu < 0: x = E[c], c - 1 (leak left past the first)
 //   other: x = x + mu * s, clamped to [E[c], E[c+1]]
 //   time:  tb + 1, t = T[tb+1]; census past the last time edge
-template <bool TIMED>
+template <bool TIMED, bool CARRY = false>
 __device__ __forceinline__ int geom_f64(Particle<false>& p, const CellsLds<false>& C, uint64_t* tally,
                                         LaneCounters& cnt) {
     const int c = p.cell;
@@ -108,7 +127,7 @@ __device__ __forceinline__ int geom_f64(Particle<false>& p, const CellsLds<false
             ev = 2;
         }
     }
-    lds_score(tally + 2 * (static_cast<uint32_t>(p.tb) * C.n_space_bins + C.bin[c]), quantise(s));
+    add_score<CARRY>(tally + 2 * (static_cast<uint32_t>(p.tb) * C.n_space_bins + C.bin[c]), quantise(s));
     cnt.events++;
     if (timed) {
         double tn = p.t + s;
@@ -155,7 +174,7 @@ __device__ __forceinline__ int geom_f64(Particle<false>& p, const CellsLds<false
 //   tau = tau - sig * s, clamped at 0
 //   edge: mu > 0: c + 1, x = 0;  mu < 0: c - 1, x = W[c - 1]
 //   other: x = x + mu s clamped to [0, W[c]];  time: tb + 1, t = 0
-template <bool TIMED>
+template <bool TIMED, bool CARRY = false>
 __device__ __forceinline__ int geom_f32(Particle<true>& p, const CellsLds<true>& C, uint64_t* tally,
                                         LaneCounters& cnt) {
     const int c = p.cell;
@@ -180,8 +199,8 @@ __device__ __forceinline__ int geom_f32(Particle<true>& p, const CellsLds<true>&
             ev = 2;
         }
     }
-    lds_score(tally + 2 * (static_cast<uint32_t>(p.tb) * C.n_space_bins + C.bin[c]),
-              quantise(static_cast<double>(s)));
+    add_score<CARRY>(tally + 2 * (static_cast<uint32_t>(p.tb) * C.n_space_bins + C.bin[c]),
+                     quantise(static_cast<double>(s)));
     cnt.events++;
     if (timed) {
         float tn = p.t + s;
@@ -220,13 +239,14 @@ __device__ __forceinline__ int geom_f32(Particle<true>& p, const CellsLds<true>&
     return STEP_COLLIDE;
 }
 
-template <bool F32, bool TIMED>
+// CARRY: the tally is a global pair array scored with carry_add.
+template <bool F32, bool TIMED, bool CARRY = false>
 __device__ __forceinline__ int geom_step(Particle<F32>& p, const CellsLds<F32>& C, uint64_t* tally,
                                          LaneCounters& cnt) {
     if constexpr (F32)
-        return geom_f32<TIMED>(p, C, tally, cnt);
+        return geom_f32<TIMED, CARRY>(p, C, tally, cnt);
     else
-        return geom_f64<TIMED>(p, C, tally, cnt);
+        return geom_f64<TIMED, CARRY>(p, C, tally, cnt);
 }
 
 // Collision at the current site: u1 decides absorption (double compare with
@@ -251,11 +271,11 @@ __device__ __forceinline__ int collide(Particle<F32>& p, const CellsLds<F32>& C,
 }
 
 // One whole event (the event-sorted schedule's unit of work).
-template <bool F32, bool TIMED>
+template <bool F32, bool TIMED, bool CARRY = false>
 __device__ __forceinline__ int step_particle(Particle<F32>& p, const CellsLds<F32>& C, const LcgDev& L,
                                              uint64_t* tally, LaneCounters& cnt) {
     if (p.need_tau) sample_tau<F32>(p, L);
-    const int r = geom_step<F32, TIMED>(p, C, tally, cnt);
+    const int r = geom_step<F32, TIMED, CARRY>(p, C, tally, cnt);
     if (r != STEP_COLLIDE) return r;
     return collide<F32>(p, C, L, cnt);
 }
