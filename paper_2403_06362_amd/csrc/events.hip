@@ -214,42 +214,56 @@ __global__ void __launch_bounds__(kEventStepBlock) k_event_step(EventParams E) {
 
 // The particles of a small bank run to the end of their histories, one per
 // thread (the same step_particle calls, event after event): the tail of a
-// slice without one launch per remaining event.
+// slice without one launch per remaining event.  In a one-group slice every
+// particle has the same score unit, whose tally the block keeps in LDS (when
+// it fits) and adds to the slot once, with carries.
 template <bool F32, bool TIMED>
 __global__ void __launch_bounds__(256) k_event_finish(EventParams E) {
+    __shared__ unsigned long long s_tally[2 * kEventLdsBins];
     const uint32_t i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= E.n_in) return;
-    BankView<F32> v = view<F32>(E.in);
-    Particle<F32> p;
-    LaneCounters cnt;
-    p.x = v.x[i];
-    p.mu = v.mu[i];
-    p.t = v.t[i];
-    p.tau = v.tau[i];
-    p.X = E.in.X[i];
-    p.cell = E.in.cell[i];
-    p.tb = E.in.tb[i];
-    p.hdraws = E.in.hdraws[i];
-    p.need_tau = (E.in.flags[i] & 1u) != 0;
-    cnt.events = E.in.events[i];
-    cnt.collisions = E.in.colls[i];
-    const uint32_t unit = E.in.unit[i];
-    const uint32_t rec = E.in.rec[i];
-    const WorkUnit U = E.tp.units[unit];
-    const DevProblem PR = E.tp.problems[U.problem];
-    const CellsLds<F32> C = global_cells<F32>(E.tp, PR);
-    uint64_t* tally = E.tp.partial + U.slot;
-    int end = END_NONE;
-    if (E.one_group)
-        while (end == END_NONE) end = step_particle<F32, TIMED, true>(p, C, E.tp.lcg, tally, cnt);
-    else
-        while (end == END_NONE) end = step_particle<F32, TIMED>(p, C, E.tp.lcg, tally, cnt);
-    HistoryRecord h;
-    h.events = static_cast<uint32_t>(cnt.events);
-    h.collisions = static_cast<uint32_t>(cnt.collisions);
-    h.draws = p.hdraws;
-    h.end = static_cast<uint32_t>(end);
-    E.records[rec] = h;
+    const WorkUnit H = E.tp.units[E.unit_begin];
+    const uint32_t words = (E.one_group && H.slice_bins <= kEventLdsBins) ? 2 * H.slice_bins : 0u;
+    for (uint32_t w = threadIdx.x; w < words; w += 256) s_tally[w] = 0;
+    __syncthreads();
+    if (i < E.n_in) {
+        BankView<F32> v = view<F32>(E.in);
+        Particle<F32> p;
+        LaneCounters cnt;
+        p.x = v.x[i];
+        p.mu = v.mu[i];
+        p.t = v.t[i];
+        p.tau = v.tau[i];
+        p.X = E.in.X[i];
+        p.cell = E.in.cell[i];
+        p.tb = E.in.tb[i];
+        p.hdraws = E.in.hdraws[i];
+        p.need_tau = (E.in.flags[i] & 1u) != 0;
+        cnt.events = E.in.events[i];
+        cnt.collisions = E.in.colls[i];
+        const uint32_t unit = E.in.unit[i];
+        const uint32_t rec = E.in.rec[i];
+        const WorkUnit U = E.tp.units[unit];
+        const DevProblem PR = E.tp.problems[U.problem];
+        const CellsLds<F32> C = global_cells<F32>(E.tp, PR);
+        uint64_t* tally = E.tp.partial + U.slot;
+        int end = END_NONE;
+        if (words != 0)
+            while (end == END_NONE)
+                end = step_particle<F32, TIMED>(p, C, E.tp.lcg, reinterpret_cast<uint64_t*>(s_tally), cnt);
+        else if (E.one_group)
+            while (end == END_NONE) end = step_particle<F32, TIMED, true>(p, C, E.tp.lcg, tally, cnt);
+        else
+            while (end == END_NONE) end = step_particle<F32, TIMED>(p, C, E.tp.lcg, tally, cnt);
+        HistoryRecord h;
+        h.events = static_cast<uint32_t>(cnt.events);
+        h.collisions = static_cast<uint32_t>(cnt.collisions);
+        h.draws = p.hdraws;
+        h.end = static_cast<uint32_t>(end);
+        E.records[rec] = h;
+    }
+    __syncthreads();
+    for (uint32_t w = 2 * threadIdx.x; w < words; w += 2 * 256)
+        if ((s_tally[w] | s_tally[w + 1]) != 0) carry_add(E.tp.partial + H.slot + w, s_tally[w], s_tally[w + 1]);
 }
 
 // One block per unit: the unit's records, in history order, into its
