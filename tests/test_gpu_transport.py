@@ -170,6 +170,27 @@ def test_event_schedule_tallies_past_the_lds_copy(M, ctx, orc):
         assert split(ev[0], probs) == ref, (bank, unit)
 
 
+def test_event_schedule_slot_low_word_wraps(M, ctx):
+    """A slice of one (problem, batch) scores into one slot.  Here 2^24
+    histories in one slice each cross about 900 cells of 0.01 mean free
+    paths, all in one tally bin: more than 1.2 x 2^33 scores, whose low 32-bit
+    halves (uniform below 2^32) add up past 2^64 in the slot's low word.  The
+    wrap must reach the high word as a carry: the event-sorted sums equal the
+    history schedule's (per-unit slots of 4096 histories, far from wrapping)
+    bit for bit."""
+    n_cells = 1000
+    re = np.arange(n_cells + 1, dtype=np.float64) * 0.01
+    p = W.SlabProblem(re, np.ones(n_cells), np.full(n_cells, 0.99), np.array([0.0, re[-1]]), 1 << 24,
+                      W.hash_seeding(), 1)
+    say("slot wrap: history schedule")
+    hist = run(M, ctx, [p])
+    assert hist[2][0]["events"] > 1.2 * 2 ** 33
+    say("slot wrap: event-sorted, one slice")
+    ev = run(M, ctx, [p], schedule=1, bank_size=1 << 24)
+    assert ev[0] == hist[0] and ev[2] == hist[2]
+    assert np.array_equal(ev[1], hist[1])
+
+
 def test_zero_histories_and_edge_problems(M, ctx, orc):
     probs = [W.small_slab(n_histories=0), W.small_slab(n_histories=1),
              W.homogeneous(1.0, 2.0, 0.0, 1, 777), W.small_slab(n_histories=64)]
