@@ -151,7 +151,12 @@ enum { MCRNG_SCHED_HISTORY = 0, MCRNG_SCHED_EVENT = 1 };
  *                   particle bank (one event per particle per launch)
  *   block           threads per block: 64, 128, 256, 512 or 1024
  *   hist_per_lane   histories each lane carries at once: 1, 2 or 4
- *   unit_histories  histories per work unit (the scheduling grain)
+ *   unit_histories  histories per work unit (the scheduling grain), at most
+ *                   2^18 (0 = automatic, at most 2^16).  A unit's partial
+ *                   tally is exact while fewer than 2^32 of its scores fall
+ *                   in one bin (2^14 per history on average at 2^18
+ *                   histories); the event schedule's slots that collect a
+ *                   whole slice carry and have no such limit.
  *   grid            persistent blocks (0 = fill the device)
  *   tally_copies    LDS tally copies per block: 1, or one per wave (= 2)
  *   use_graph       1 = capture the launches of a run in a hipGraph once

@@ -631,6 +631,8 @@ static TransportParams make_params(mcrng_ctx* ctx, const LcgDev& L, uint32_t cop
     return tp;
 }
 
+constexpr uint32_t kMaxUnitHistories = 1u << 18;
+
 static int normalise_opts(const mcrng_run_opts* in, mcrng_run_opts* o) {
     std::memset(o, 0, sizeof *o);
     if (in) *o = *in;
@@ -648,6 +650,10 @@ static int normalise_opts(const mcrng_run_opts* in, mcrng_run_opts* o) {
     if (o->coll_batch > 64 * o->hist_per_lane) o->coll_batch = 64 * o->hist_per_lane;
     if (o->tally_copies == 0) o->tally_copies = 1;
     if (o->tally_copies > 2) return fail(MCRNG_EINVAL, "opts.tally_copies must be 1 or 2");
+    // a unit's LDS tally words take plain 64-bit adds of 32-bit halves: exact
+    // while fewer than 2^32 of its scores fall in one bin
+    if (o->unit_histories > kMaxUnitHistories)
+        return fail(MCRNG_EINVAL, "opts.unit_histories = %u exceeds %u", o->unit_histories, kMaxUnitHistories);
     return MCRNG_OK;
 }
 

@@ -203,6 +203,10 @@ def test_error_paths(M, ctx):
     p = W.small_slab()
     with pytest.raises(M.McrngError):
         run(M, ctx, [p], block=96)
+    with pytest.raises(M.McrngError) as e:   # a unit's tally words bound its size
+        run(M, ctx, [p], unit_histories=(1 << 18) + 1)
+    assert "unit_histories" in str(e.value)
+    run(M, ctx, [p], unit_histories=1 << 18)
     thin = W.homogeneous(100.0, 0.1, 0.5, 10, 10)   # flights up to 367 mfp: fixed point range
     with pytest.raises(M.McrngError) as e:
         run(M, ctx, [thin])
