@@ -747,8 +747,8 @@ static size_t bank_bytes(uint64_t cap) { return 17 * (((cap * 8) + 255) & ~stati
 
 // Event-sorted schedule: slices of whole work units fill a particle bank;
 // each launch advances every live particle by one event and compacts the
-// survivors into the other bank; the host reads the live count after each
-// launch.  Partial slots are zeroed and accumulated with integer atomics.
+// survivors into the other bank; the host reads the live count every few
+// launches.  Partial slots are zeroed and accumulated with integer atomics.
 namespace mcrng {
 hipError_t launch_event_finish(const EventParams& p, int f32, int timed, hipStream_t st);   // events.hip
 }
@@ -768,11 +768,14 @@ static int run_event_schedule(mcrng_ctx* ctx, const LcgDev& L, const mcrng_run_o
     ep.tp = make_params(ctx, L, 1);
     ep.records = static_cast<HistoryRecord*>(ctx->records.p);
     ep.rec_begin = static_cast<const uint64_t*>(ctx->rec_begin.p);
-    ep.n_out = static_cast<uint32_t*>(ctx->counter.p) + 1;
+    // live counts rotate over three device words: launch s reads word s % 3,
+    // appends to word (s + 1) % 3 and zeroes word (s + 2) % 3
+    uint32_t* cnt = static_cast<uint32_t*>(ctx->counter.p) + 4;
     EventBank A = carve_bank(ctx->bank_a.p, cap), B = carve_bank(ctx->bank_b.p, cap);
     const int f32 = o.precision == MCRNG_FP32;
     const int timed = ctx->any_timed;
     HIP_TRY(launch_fill_u64(ep.tp.partial, ctx->partial_words, 0ull, st));
+    if (!ctx->h_pinned) HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&ctx->h_pinned), 64, hipHostMallocDefault));
     const uint32_t nu = static_cast<uint32_t>(ctx->h_units.size());
     uint32_t u0 = 0;
     while (u0 < nu) {
@@ -785,24 +788,32 @@ static int run_event_schedule(mcrng_ctx* ctx, const LcgDev& L, const mcrng_run_o
         ep.out = B;
         ep.n_in = static_cast<uint32_t>(ctx->h_rec_begin[u1] - ctx->h_rec_begin[u0]);
         HIP_TRY(launch_event_init(ep, f32, timed, st));
+        HIP_TRY(launch_fill_u32(cnt, 1, ep.n_in, st));
+        HIP_TRY(launch_fill_u32(cnt + 1, 1, 0u, st));
         // below 1/64 of the bank (64Ki live particles for the default bank) the
-        // slice's remaining particles run to their ends in one launch
+        // slice's remaining particles run to their ends in one launch; the host
+        // reads the live count every few launches and sizes the grids from it
         const uint64_t finish_below = cap / 64;
+        constexpr uint32_t kStepsPerRead = 4;
+        uint32_t s = 0;
         while (ep.n_in > 0) {
             if (ep.n_in < finish_below) {
+                ep.n_live = cnt + s % 3;
                 HIP_TRY(launch_event_finish(ep, f32, timed, st));
                 break;
             }
-            HIP_TRY(launch_fill_u32(ep.n_out, 1, 0u, st));
-            HIP_TRY(launch_event_step(ep, f32, timed, st));
-            if (!ctx->h_pinned)
-                HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&ctx->h_pinned), 64, hipHostMallocDefault));
-            HIP_TRY(hipMemcpyAsync(ctx->h_pinned, ep.n_out, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+            for (uint32_t k = 0; k < kStepsPerRead; ++k, ++s) {
+                ep.n_live = cnt + s % 3;
+                ep.n_out = cnt + (s + 1) % 3;
+                ep.n_clear = cnt + (s + 2) % 3;
+                HIP_TRY(launch_event_step(ep, f32, timed, st));
+                std::swap(ep.in, ep.out);
+            }
+            HIP_TRY(hipMemcpyAsync(ctx->h_pinned, cnt + s % 3, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
             HIP_TRY(hipStreamSynchronize(st));
             uint32_t live = 0;
             std::memcpy(&live, ctx->h_pinned, sizeof live);
             if (live > ep.n_in) return fail(MCRNG_EDEVICE, "event schedule: bank count grew");
-            std::swap(ep.in, ep.out);
             ep.n_in = live;
         }
         u0 = u1;

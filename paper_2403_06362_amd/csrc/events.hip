@@ -133,8 +133,12 @@ __global__ void __launch_bounds__(kEventStepBlock) k_event_step(EventParams E) {
     const uint32_t b0 = blockIdx.x * (kEventStepBlock * kEventStepPer);
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wid = threadIdx.x >> 6;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *E.n_clear = 0;
+    // the grid covers a bound on the live count: blocks past it leave at once
+    const uint32_t n_in = *E.n_live;
+    if (b0 >= n_in) return;
     if (threadIdx.x == 0) {
-        const uint32_t u = E.in.unit[b0];   // b0 < n_in for every block of the grid
+        const uint32_t u = E.in.unit[b0];
         const WorkUnit U = E.tp.units[u];
         const bool fits = U.slice_bins <= kEventLdsBins;
         s_home = fits ? u : 0xffffffffu;
@@ -152,7 +156,7 @@ __global__ void __launch_bounds__(kEventStepBlock) k_event_step(EventParams E) {
         Particle<F32> p;
         uint32_t unit = 0, rec = 0;
         LaneCounters cnt;
-        if (i < E.n_in) {
+        if (i < n_in) {
             BankView<F32> v = view<F32>(E.in);
             p.x = v.x[i];
             p.mu = v.mu[i];
@@ -221,11 +225,13 @@ template <bool F32, bool TIMED>
 __global__ void __launch_bounds__(256) k_event_finish(EventParams E) {
     __shared__ unsigned long long s_tally[2 * kEventLdsBins];
     const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    const uint32_t n_in = *E.n_live;
+    if (blockIdx.x * 256 >= n_in) return;   // the grid covers a bound on the live count
     const WorkUnit H = E.tp.units[E.unit_begin];
     const uint32_t words = (E.one_group && H.slice_bins <= kEventLdsBins) ? 2 * H.slice_bins : 0u;
     for (uint32_t w = threadIdx.x; w < words; w += 256) s_tally[w] = 0;
     __syncthreads();
-    if (i < E.n_in) {
+    if (i < n_in) {
         BankView<F32> v = view<F32>(E.in);
         Particle<F32> p;
         LaneCounters cnt;

@@ -157,8 +157,13 @@ struct HistoryRecord {
 struct EventParams {
     TransportParams tp;      // tables, units, partial slots (atomically accumulated)
     EventBank in, out;
-    uint32_t n_in;           // live particles in `in`
-    uint32_t* n_out;         // append counter of `out`
+    uint32_t n_in;           // init: particles of the slice; step / finish: a bound on the live count (grid size)
+    // step / finish: device words rotated by the host over the launches of a
+    // slice: the live count of `in`, the append counter of `out` (zero at the
+    // start), and the next launch's append counter, which block 0 zeroes
+    const uint32_t* n_live;
+    uint32_t* n_out;
+    uint32_t* n_clear;
     HistoryRecord* records;  // one per history of the run
     const uint64_t* rec_begin;   // per unit: index of its first record
     // init: the histories of units [unit_begin, unit_end), n_in in total
