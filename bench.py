@@ -252,6 +252,7 @@ def main():
     ap.add_argument("--full", action="store_true", help="add the batched and multi-region legs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-transport", action="store_true", help="headline draw workload only")
+    ap.add_argument("--no-pulse", action="store_true", help="skip the pulse-problem legs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 512 MiB device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -350,8 +351,9 @@ def main():
         tr["hash_over_stride"] = legs["stride_fp64"]["ms"] / legs["hash_fp64"]["ms"]
         out["histories_per_s"] = legs["hash_fp64"]["histories_per_s"]
         out["transport"] = tr
-        out["pulse"] = pulse_leg(M, W, torch, lcg, ctx)
-        out["pulse_population_control"] = pulse_pc_leg(M, W, torch, lcg, ctx)
+        if not args.no_pulse:
+            out["pulse"] = pulse_leg(M, W, torch, lcg, ctx)
+            out["pulse_population_control"] = pulse_pc_leg(M, W, torch, lcg, ctx)
         if args.full:
             out["batched"] = batched_leg(M, W, torch, lcg, ctx)
             out["multi_region"] = multi_region_leg(M, W, torch, lcg, ctx)
