@@ -174,6 +174,7 @@ __global__ void __launch_bounds__(256) k_draw(DrawParams P) {
             if (STORE_STATE) P.state[lo + sid] = x;
             active = false;
         }
+        next = __builtin_amdgcn_readfirstlane(next);   // wave-uniform: kept in a scalar register
         const uint64_t need = __builtin_amdgcn_ballot_w64(!active);
         const uint32_t left = nw - next;   // streams not yet handed out
         if (need != 0 && left != 0) {
