@@ -199,8 +199,8 @@ extern "C" int mcrng_draw(const mcrng_lcg* lcg, const mcrng_seeding* seeding, ui
     if (!d_count || !d_checksum) return fail(MCRNG_EINVAL, "d_count and d_checksum are required");
     if (!seeding && !d_state) return fail(MCRNG_EINVAL, "d_state is required when seeding is NULL");
     if (n >> 40) return fail(MCRNG_EINVAL, "n = %llu too large", (unsigned long long)n);
-    // (the kernel needs fewer than 2^32 streams per wave: with n < 2^40 and
-    // at least n/256 threads' worth of waves this always holds)
+    // (the kernel needs fewer than 2^28 streams per wave: the launcher uses at
+    // least n / 2^30 + 1 blocks of 4 waves, at most 1025 for n < 2^40)
     DrawParams p;
     std::memset(&p, 0, sizeof p);
     p.lcg = L;

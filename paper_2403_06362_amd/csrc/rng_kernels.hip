@@ -129,6 +129,17 @@ __global__ void __launch_bounds__(256) k_draw(DrawParams P) {
     const uint64_t g = P.lcg.g;
     uint64_t* rstate = s_state[wib];
     uint32_t* rcount = s_count[wib];
+    // HALVES (m = 63, c = 1, state not stored): a lane holds 2 X, which
+    // follows 2X <- g (2X) + 2 mod 2^64 with no mask; the ring holds 2 X too.
+    // The checksum is kept as the exact sums of the low and the high 32-bit
+    // words of 2X (each below 2^64 for fewer than 2^32 draws), so sum X mod
+    // 2^64 = (lo_sum >> 1) + (hi_sum << 31).  A masked draw slot then costs a
+    // bit-field extract and two 32 x 32 + 64 multiply-adds.
+    constexpr bool HALVES = M63C1 && !STORE_STATE;
+    constexpr int SH = HALVES ? 1 : 0;
+    // wave-uniform base of the wave's checksums; a store adds a 32-bit byte
+    // offset (the launcher keeps a wave below 2^28 streams)
+    char* const cbase = reinterpret_cast<char*>(P.checksum + lo);
 
     // ring bookkeeping, wave-uniform: streams [next, filled) are seeded and
     // not yet handed out; c_next holds the counts of the batch after them
@@ -148,29 +159,22 @@ __global__ void __launch_bounds__(256) k_draw(DrawParams P) {
         rcount[jb] = (jb < nw) ? P.count[lo + jb] : 0u;
         if (MODE == SEED_STRIDE) {
             const uint64_t b1 = affine_apply(sl.g64, sl.c64, P.lcg.mask, sbase);
-            rstate[ja] = (ja < nw) ? affine_apply(sl.g, sl.c, P.lcg.mask, sbase) : 0ull;
-            rstate[jb] = (jb < nw) ? affine_apply(sl.g, sl.c, P.lcg.mask, b1) : 0ull;
+            rstate[ja] = (ja < nw) ? affine_apply(sl.g, sl.c, P.lcg.mask, sbase) << SH : 0ull;
+            rstate[jb] = (jb < nw) ? affine_apply(sl.g, sl.c, P.lcg.mask, b1) << SH : 0ull;
             sbase = affine_apply(sl.g64, sl.c64, P.lcg.mask, b1);
         } else {
-            rstate[ja] = (ja < nw) ? queue_seed<MODE>(P, lo + ja) : 0ull;
-            rstate[jb] = (jb < nw) ? queue_seed<MODE>(P, lo + jb) : 0ull;
+            rstate[ja] = (ja < nw) ? queue_seed<MODE>(P, lo + ja) << SH : 0ull;
+            rstate[jb] = (jb < nw) ? queue_seed<MODE>(P, lo + jb) << SH : 0ull;
         }
         if (jn < nw) c_next = P.count[lo + jn];
     }
 
-    // HALVES (m = 63, c = 1, state not stored): x holds 2 X, which follows
-    // 2X <- g (2X) + 2 mod 2^64 with no mask; the checksum is kept as the
-    // exact sums of the low and the high 32-bit words of 2X (each below
-    // 2^64 for fewer than 2^32 draws), so sum X mod 2^64 =
-    // (lo_sum >> 1) + (hi_sum << 31).  A masked draw slot then costs a
-    // bit-field extract and two 32 x 32 + 64 multiply-adds.
-    constexpr bool HALVES = M63C1 && !STORE_STATE;
     uint64_t x = 0, sum = 0, hsum = 0;
     uint32_t sid = 0, rem = 0;
     bool active = false;
     for (;;) {
         if (active && rem == 0) {
-            P.checksum[lo + sid] = HALVES ? (sum >> 1) + (hsum << 31) : sum;
+            *reinterpret_cast<uint64_t*>(cbase + (sid << 3)) = HALVES ? (sum >> 1) + (hsum << 31) : sum;
             if (STORE_STATE) P.state[lo + sid] = x;
             active = false;
         }
@@ -184,7 +188,7 @@ __global__ void __launch_bounds__(256) k_draw(DrawParams P) {
                                                             __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(need), 0u));
             if (!active && rank < take) {
                 const uint32_t e = (next + rank) & 127u;
-                x = HALVES ? rstate[e] << 1 : rstate[e];
+                x = rstate[e];
                 rem = rcount[e];
                 sid = next + rank;
                 sum = 0;
@@ -197,10 +201,10 @@ __global__ void __launch_bounds__(256) k_draw(DrawParams P) {
                 // positions hold no stream that is still to be handed out)
                 const uint32_t j = filled + lane;
                 if (MODE == SEED_STRIDE) {
-                    rstate[j & 127u] = (j < nw) ? affine_apply(sl.g, sl.c, P.lcg.mask, sbase) : 0ull;
+                    rstate[j & 127u] = (j < nw) ? affine_apply(sl.g, sl.c, P.lcg.mask, sbase) << SH : 0ull;
                     sbase = affine_apply(sl.g64, sl.c64, P.lcg.mask, sbase);
                 } else {
-                    rstate[j & 127u] = (j < nw) ? queue_seed<MODE>(P, lo + j) : 0ull;
+                    rstate[j & 127u] = (j < nw) ? queue_seed<MODE>(P, lo + j) << SH : 0ull;
                 }
                 rcount[j & 127u] = c_next;   // the one wait on vector memory per 64 streams
                 const uint32_t jn = j + 64u;
@@ -220,7 +224,7 @@ __global__ void __launch_bounds__(256) k_draw(DrawParams P) {
                 }
             }
         } else if (HALVES) {
-            const uint32_t fb = (D < 32 || k < 32u) ? (1u << k) - 1u : 0xffffffffu;
+            const uint32_t fb = (D < 32 || k < 32u) ? __builtin_amdgcn_ubfe(0xffffffffu, 0u, k) : 0xffffffffu;
 #pragma unroll
             for (int d = 0; d < D; ++d) {
                 x = g * x + 2ull;
@@ -283,6 +287,9 @@ hipError_t launch_draw(const DrawParams& p, int seed_mode, hipStream_t st, int b
     const uint64_t max_blocks = (p.n + 255) / 256;
     if (blocks > max_blocks) blocks = max_blocks;
     if (blocks < 1) blocks = 1;
+    // fewer than 2^28 streams per wave (4 per block): its checksum offsets fit 32 bits
+    const uint64_t min_blocks = (p.n >> 30) + 1;
+    if (blocks < min_blocks) blocks = min_blocks;
     switch (seed_mode) {
         case SEED_LOAD: return launch_draw_m<SEED_LOAD>(p, st, static_cast<int>(blocks), round);
         case SEED_HASH: return launch_draw_m<SEED_HASH>(p, st, static_cast<int>(blocks), round);
