@@ -116,10 +116,16 @@ __device__ __forceinline__ StrideLanes stride_lanes(const SeedDev& S, uint32_t l
 // count, two LDS reads).  Up to 64 lanes are served per round without a
 // loop, and the refill path never waits on vector memory (one wait per 64
 // streams, when a batch is seeded).
+// One ring entry: a stream's start state and its draw count (one LDS read).
+struct __align__(16) RingEntry {
+    uint64_t state;
+    uint32_t count;
+    uint32_t pad;
+};
+
 template <int MODE, int D, bool STORE_STATE, bool M63C1>
 __global__ void __launch_bounds__(256) k_draw(DrawParams P) {
-    __shared__ uint64_t s_state[4][128];
-    __shared__ uint32_t s_count[4][128];
+    __shared__ RingEntry s_ring[4][128];
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave in block
     const uint64_t wave = static_cast<uint64_t>(blockIdx.x) * (blockDim.x >> 6) + wib;
@@ -127,8 +133,7 @@ __global__ void __launch_bounds__(256) k_draw(DrawParams P) {
     const uint64_t lo = wave * P.n / nwaves;
     const uint32_t nw = static_cast<uint32_t>((wave + 1) * P.n / nwaves - lo);   // streams of this wave
     const uint64_t g = P.lcg.g;
-    uint64_t* rstate = s_state[wib];
-    uint32_t* rcount = s_count[wib];
+    RingEntry* ring = s_ring[wib];
     // HALVES (m = 63, c = 1, state not stored): a lane holds 2 X, which
     // follows 2X <- g (2X) + 2 mod 2^64 with no mask; the ring holds 2 X too.
     // The checksum is kept as the exact sums of the low and the high 32-bit
@@ -155,16 +160,16 @@ __global__ void __launch_bounds__(256) k_draw(DrawParams P) {
     }
     {
         const uint32_t ja = lane, jb = 64u + lane, jn = 128u + lane;
-        rcount[ja] = (ja < nw) ? P.count[lo + ja] : 0u;
-        rcount[jb] = (jb < nw) ? P.count[lo + jb] : 0u;
+        ring[ja].count = (ja < nw) ? P.count[lo + ja] : 0u;
+        ring[jb].count = (jb < nw) ? P.count[lo + jb] : 0u;
         if (MODE == SEED_STRIDE) {
             const uint64_t b1 = affine_apply(sl.g64, sl.c64, P.lcg.mask, sbase);
-            rstate[ja] = (ja < nw) ? affine_apply(sl.g, sl.c, P.lcg.mask, sbase) << SH : 0ull;
-            rstate[jb] = (jb < nw) ? affine_apply(sl.g, sl.c, P.lcg.mask, b1) << SH : 0ull;
+            ring[ja].state = (ja < nw) ? affine_apply(sl.g, sl.c, P.lcg.mask, sbase) << SH : 0ull;
+            ring[jb].state = (jb < nw) ? affine_apply(sl.g, sl.c, P.lcg.mask, b1) << SH : 0ull;
             sbase = affine_apply(sl.g64, sl.c64, P.lcg.mask, b1);
         } else {
-            rstate[ja] = (ja < nw) ? queue_seed<MODE>(P, lo + ja) << SH : 0ull;
-            rstate[jb] = (jb < nw) ? queue_seed<MODE>(P, lo + jb) << SH : 0ull;
+            ring[ja].state = (ja < nw) ? queue_seed<MODE>(P, lo + ja) << SH : 0ull;
+            ring[jb].state = (jb < nw) ? queue_seed<MODE>(P, lo + jb) << SH : 0ull;
         }
         if (jn < nw) c_next = P.count[lo + jn];
     }
@@ -188,8 +193,9 @@ __global__ void __launch_bounds__(256) k_draw(DrawParams P) {
                                                             __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(need), 0u));
             if (!active && rank < take) {
                 const uint32_t e = (next + rank) & 127u;
-                x = rstate[e];
-                rem = rcount[e];
+                const RingEntry r = ring[e];
+                x = r.state;
+                rem = r.count;
                 sid = next + rank;
                 sum = 0;
                 hsum = 0;
@@ -201,12 +207,12 @@ __global__ void __launch_bounds__(256) k_draw(DrawParams P) {
                 // positions hold no stream that is still to be handed out)
                 const uint32_t j = filled + lane;
                 if (MODE == SEED_STRIDE) {
-                    rstate[j & 127u] = (j < nw) ? affine_apply(sl.g, sl.c, P.lcg.mask, sbase) << SH : 0ull;
+                    ring[j & 127u].state = (j < nw) ? affine_apply(sl.g, sl.c, P.lcg.mask, sbase) << SH : 0ull;
                     sbase = affine_apply(sl.g64, sl.c64, P.lcg.mask, sbase);
                 } else {
-                    rstate[j & 127u] = (j < nw) ? queue_seed<MODE>(P, lo + j) << SH : 0ull;
+                    ring[j & 127u].state = (j < nw) ? queue_seed<MODE>(P, lo + j) << SH : 0ull;
                 }
-                rcount[j & 127u] = c_next;   // the one wait on vector memory per 64 streams
+                ring[j & 127u].count = c_next;   // the one wait on vector memory per 64 streams
                 const uint32_t jn = j + 64u;
                 c_next = (jn < nw) ? P.count[lo + jn] : 0u;
                 filled += 64u;
