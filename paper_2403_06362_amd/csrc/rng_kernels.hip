@@ -83,6 +83,17 @@ __device__ __forceinline__ uint64_t queue_seed(const DrawParams& P, uint64_t j) 
     return stream_start(P.lcg, P.seed, j);
 }
 
+// A ring entry's start state: X, or 2X on the halves path (m = 63, c = 1,
+// no stored states), where a hashed start needs no mask:
+// ((h mod 2^63) 2) mod 2^64 = 2h mod 2^64.  Otherwise stream_start's X.
+template <int MODE, bool HALVES>
+__device__ __forceinline__ uint64_t ring_state(const DrawParams& P, uint64_t j) {
+    if constexpr (HALVES && MODE == SEED_HASH)
+        return murmur_with_seed_part(P.seed.first_index + j + 1ull, P.seed.base) << 1;
+    else
+        return queue_seed<MODE>(P, j) << (HALVES ? 1 : 0);
+}
+
 // Stride seeding of a batch of 64 consecutive streams s0 + l (l = lane):
 // X_{Q(s0 + l)} = A_{Ql}(X_{Q s0}), with A_k the k-step map x -> G_k x + C_k
 // (eq. 2).  A_{Ql} composes the skip table's digit-0 entry for l & 15 and
@@ -168,8 +179,8 @@ __global__ void __launch_bounds__(256) k_draw(DrawParams P) {
             ring[jb].state = (jb < nw) ? affine_apply(sl.g, sl.c, P.lcg.mask, b1) << SH : 0ull;
             sbase = affine_apply(sl.g64, sl.c64, P.lcg.mask, b1);
         } else {
-            ring[ja].state = (ja < nw) ? queue_seed<MODE>(P, lo + ja) << SH : 0ull;
-            ring[jb].state = (jb < nw) ? queue_seed<MODE>(P, lo + jb) << SH : 0ull;
+            ring[ja].state = (ja < nw) ? ring_state<MODE, HALVES>(P, lo + ja) : 0ull;
+            ring[jb].state = (jb < nw) ? ring_state<MODE, HALVES>(P, lo + jb) : 0ull;
         }
         if (jn < nw) c_next = P.count[lo + jn];
     }
@@ -210,7 +221,7 @@ __global__ void __launch_bounds__(256) k_draw(DrawParams P) {
                     ring[j & 127u].state = (j < nw) ? affine_apply(sl.g, sl.c, P.lcg.mask, sbase) << SH : 0ull;
                     sbase = affine_apply(sl.g64, sl.c64, P.lcg.mask, sbase);
                 } else {
-                    ring[j & 127u].state = (j < nw) ? queue_seed<MODE>(P, lo + j) << SH : 0ull;
+                    ring[j & 127u].state = (j < nw) ? ring_state<MODE, HALVES>(P, lo + j) : 0ull;
                 }
                 ring[j & 127u].count = c_next;   // the one wait on vector memory per 64 streams
                 const uint32_t jn = j + 64u;
