@@ -45,8 +45,13 @@ __host__ __device__ __forceinline__ uint64_t murmur_seed_part(uint64_t s) {
     return murmur_sub(s ^ (8ull * kMurmurM));
 }
 
+// The steps of hash(k, s) after the first product y = k M.
+__host__ __device__ __forceinline__ uint64_t murmur_from_product(uint64_t y, uint64_t seed_part) {
+    return murmur_sub(seed_part ^ ((y ^ (y >> 47)) * kMurmurM));
+}
+
 __host__ __device__ __forceinline__ uint64_t murmur_with_seed_part(uint64_t k, uint64_t seed_part) {
-    return murmur_sub(seed_part ^ (murmur_sub(k) * kMurmurM));
+    return murmur_from_product(k * kMurmurM, seed_part);
 }
 
 __host__ __device__ __forceinline__ uint64_t murmur_hash(uint64_t k, uint64_t s) {

@@ -83,15 +83,19 @@ __device__ __forceinline__ uint64_t queue_seed(const DrawParams& P, uint64_t j) 
     return stream_start(P.lcg, P.seed, j);
 }
 
-// A ring entry's start state: X, or 2X on the halves path (m = 63, c = 1,
-// no stored states), where a hashed start needs no mask:
-// ((h mod 2^63) 2) mod 2^64 = 2h mod 2^64.  Otherwise stream_start's X.
+// A ring entry's start state for stream j0 + lane (j0 wave-uniform): X, or
+// 2X on the halves path (m = 63, c = 1, no stored states).  There a hashed
+// start needs no mask (((h mod 2^63) 2) mod 2^64 = 2h mod 2^64), and the
+// hash's first product (k0 + lane) M, k0 = first_index + j0 + 1, is
+// k0 M (scalar) plus the lane's lane M.
 template <int MODE, bool HALVES>
-__device__ __forceinline__ uint64_t ring_state(const DrawParams& P, uint64_t j) {
-    if constexpr (HALVES && MODE == SEED_HASH)
-        return murmur_with_seed_part(P.seed.first_index + j + 1ull, P.seed.base) << 1;
-    else
-        return queue_seed<MODE>(P, j) << (HALVES ? 1 : 0);
+__device__ __forceinline__ uint64_t ring_state(const DrawParams& P, uint64_t j0, uint32_t lane, uint64_t lane_m) {
+    if constexpr (HALVES && MODE == SEED_HASH) {
+        const uint64_t k0m = (P.seed.first_index + j0 + 1ull) * kMurmurM;
+        return murmur_from_product(k0m + lane_m, P.seed.base) << 1;
+    } else {
+        return queue_seed<MODE>(P, j0 + lane) << (HALVES ? 1 : 0);
+    }
 }
 
 // Stride seeding of a batch of 64 consecutive streams s0 + l (l = lane):
@@ -156,6 +160,7 @@ __global__ void __launch_bounds__(256) k_draw(DrawParams P) {
     // wave-uniform base of the wave's checksums; a store adds a 32-bit byte
     // offset (the launcher keeps a wave below 2^28 streams)
     char* const cbase = reinterpret_cast<char*>(P.checksum + lo);
+    const uint64_t lane_m = static_cast<uint64_t>(lane) * kMurmurM;   // hashed ring entries
 
     // ring bookkeeping, wave-uniform: streams [next, filled) are seeded and
     // not yet handed out; c_next holds the counts of the batch after them
@@ -179,8 +184,8 @@ __global__ void __launch_bounds__(256) k_draw(DrawParams P) {
             ring[jb].state = (jb < nw) ? affine_apply(sl.g, sl.c, P.lcg.mask, b1) << SH : 0ull;
             sbase = affine_apply(sl.g64, sl.c64, P.lcg.mask, b1);
         } else {
-            ring[ja].state = (ja < nw) ? ring_state<MODE, HALVES>(P, lo + ja) : 0ull;
-            ring[jb].state = (jb < nw) ? ring_state<MODE, HALVES>(P, lo + jb) : 0ull;
+            ring[ja].state = (ja < nw) ? ring_state<MODE, HALVES>(P, lo, lane, lane_m) : 0ull;
+            ring[jb].state = (jb < nw) ? ring_state<MODE, HALVES>(P, lo + 64u, lane, lane_m) : 0ull;
         }
         if (jn < nw) c_next = P.count[lo + jn];
     }
@@ -221,7 +226,7 @@ __global__ void __launch_bounds__(256) k_draw(DrawParams P) {
                     ring[j & 127u].state = (j < nw) ? affine_apply(sl.g, sl.c, P.lcg.mask, sbase) << SH : 0ull;
                     sbase = affine_apply(sl.g64, sl.c64, P.lcg.mask, sbase);
                 } else {
-                    ring[j & 127u].state = (j < nw) ? ring_state<MODE, HALVES>(P, lo + j) : 0ull;
+                    ring[j & 127u].state = (j < nw) ? ring_state<MODE, HALVES>(P, lo + filled, lane, lane_m) : 0ull;
                 }
                 ring[j & 127u].count = c_next;   // the one wait on vector memory per 64 streams
                 const uint32_t jn = j + 64u;
