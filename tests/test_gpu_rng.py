@@ -116,6 +116,28 @@ def test_draw_round_lengths(M, orc, monkeypatch, rnd):
                 assert np.array_equal(u64_np(st)[:n], states), (rnd, lcg.m, sd.kind)
 
 
+def test_hash_draw_keys_wrap_at_2_64(M, orc):
+    """Hash seeding keys stream i by first_index + i + 1 modulo 2^64: with the
+    largest first_index the API accepts, the last stream's key wraps to 0.
+    Checksums with and without final states, and the seeds alone, are the
+    oracle's."""
+    import torch
+    n = 70_001
+    sd = W.hash_seeding((1 << 64) - n)
+    counts = W.draw_counts(n, seed=3)
+    counts[-3:] = [0, 1, 65]
+    ref = orc.seed_and_draw(LCG, sd, counts, threads=8)
+    for with_state in (False, True):
+        say("hash keys wrap", with_state)
+        chk = _empty_u64(n)
+        M.draw(LCG, sd, to_dev_u32(counts), chk, d_state=_empty_u64(n) if with_state else None)
+        torch.cuda.synchronize()
+        assert np.array_equal(u64_np(chk)[:n], ref), with_state
+    out = _empty_u64(n)
+    M.init_streams(LCG, sd, n, out)
+    assert np.array_equal(u64_np(out)[:n], orc.init_streams(LCG, sd, n))
+
+
 @pytest.mark.parametrize("gen", ["mcnp", "m48"])
 def test_draw_stride_batches_offsets_generators(M, orc, gen):
     """Stride seeding in the draw kernel seeds 64 consecutive streams per
