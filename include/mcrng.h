@@ -165,7 +165,7 @@ enum { MCRNG_SCHED_HISTORY = 0, MCRNG_SCHED_EVENT = 1 };
  *   coll_batch      history schedule: a wave runs its collision phase
  *                   (absorption draw, new direction, next flight) once this
  *                   many of its lanes wait at a collision site (1..64 per
- *                   history slot; default 32) */
+ *                   history slot; default 24 in FP64, 32 in FP32) */
 typedef struct {
     uint32_t precision;
     uint32_t schedule;

@@ -646,7 +646,9 @@ static int normalise_opts(const mcrng_run_opts* in, mcrng_run_opts* o) {
     if (o->hist_per_lane == 0) o->hist_per_lane = 1;
     if (o->hist_per_lane != 1 && o->hist_per_lane != 2 && o->hist_per_lane != 4)
         return fail(MCRNG_EINVAL, "opts.hist_per_lane = %u not in {1,2,4}", o->hist_per_lane);
-    if (o->coll_batch == 0) o->coll_batch = 32;
+    // the autotuner's choice on the long-chain and multi-region slabs: 24 in
+    // FP64 (1-3% faster than 32), 32 in FP32
+    if (o->coll_batch == 0) o->coll_batch = o->precision == MCRNG_FP32 ? 32 : 24;
     if (o->coll_batch > 64 * o->hist_per_lane) o->coll_batch = 64 * o->hist_per_lane;
     if (o->tally_copies == 0) o->tally_copies = 1;
     if (o->tally_copies > 2) return fail(MCRNG_EINVAL, "opts.tally_copies must be 1 or 2");
