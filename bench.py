@@ -278,6 +278,19 @@ def main():
     total_draws = int(counts.sum(dtype=np.uint64))
     d_count = torch.from_numpy(counts).to(dev)
 
+    # the GPU's clocks ramp up over the first tens of milliseconds of sustained
+    # work: an untimed spin-up of the same kernels (about half a second) runs
+    # before the first leg's warm-up steps, so that the leg measured first is
+    # not measured on the ramp
+    log("clock spin-up: untimed draws for about 0.5 s")
+    spin = torch.empty(n, dtype=torch.uint64, device=dev)
+    t_spin = time.perf_counter()
+    while time.perf_counter() - t_spin < 0.5:
+        for sd in (W.hash_seeding(), W.stride_seeding()):
+            M.draw(lcg, sd, d_count, spin)
+        torch.cuda.synchronize()
+    del spin
+
     log("headline: hash seeding, %d streams, %d draws" % (n, total_draws))
     hsh = draw_workload(M, W, torch, dev, "hash", args.steps, args.warmup, d_count, n, total_draws, lcg)
     log("stride seeding")
