@@ -120,17 +120,6 @@ __device__ __forceinline__ StrideLanes stride_lanes(const SeedDev& S, uint32_t l
     return r;
 }
 
-// Persistent seed + draw kernel.  Each wave owns the streams [lo, hi)
-// (fewer than 2^32) and keeps the next streams ready in a 128-entry LDS ring
-// (start state and draw count at position j & 127 for stream j), seeded 64 at
-// a time by all 64 lanes at once (stride seeding: one affine step per lane
-// from the batch's base), the counts loaded one batch ahead.  Each
-// lane carries one active stream; a round draws D steps (only the checksum is
-// masked by the remaining count); after a round, lanes whose stream ended
-// store its checksum and take the next ring entries in order (ballot, prefix
-// count, two LDS reads).  Up to 64 lanes are served per round without a
-// loop, and the refill path never waits on vector memory (one wait per 64
-// streams, when a batch is seeded).
 // One ring entry: a stream's start state and its draw count (one LDS read).
 struct __align__(16) RingEntry {
     uint64_t state;
@@ -138,6 +127,17 @@ struct __align__(16) RingEntry {
     uint32_t pad;
 };
 
+// Persistent seed + draw kernel.  Each wave owns the streams [lo, hi)
+// (fewer than 2^28) and keeps the next streams ready in a 128-entry LDS ring
+// (start state and draw count at position j & 127 for stream j), seeded 64 at
+// a time by all 64 lanes at once (stride seeding: one affine step per lane
+// from the batch's base), the counts loaded one batch ahead.  Each
+// lane carries one active stream; a round draws D steps (only the checksum is
+// masked by the remaining count); after a round, lanes whose stream ended
+// store its checksum and take the next ring entries in order (ballot, prefix
+// count, one ring entry read).  Up to 64 lanes are served per round without a
+// loop, and the refill path never waits on vector memory (one wait per 64
+// streams, when a batch is seeded).
 template <int MODE, int D, bool STORE_STATE, bool M63C1>
 __global__ void __launch_bounds__(256) k_draw(DrawParams P) {
     __shared__ RingEntry s_ring[4][128];
