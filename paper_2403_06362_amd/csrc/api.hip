@@ -740,12 +740,11 @@ static EventBank carve_bank(void* base, uint64_t cap) {
     b.hdraws = reinterpret_cast<uint32_t*>(take(cap * 4));
     b.events = reinterpret_cast<uint32_t*>(take(cap * 4));
     b.colls = reinterpret_cast<uint32_t*>(take(cap * 4));
-    b.flags = reinterpret_cast<uint32_t*>(take(cap * 4));
     b.unit = reinterpret_cast<uint32_t*>(take(cap * 4));
     b.rec = reinterpret_cast<uint32_t*>(take(cap * 4));
     return b;
 }
-static size_t bank_bytes(uint64_t cap) { return 17 * (((cap * 8) + 255) & ~static_cast<uint64_t>(255)); }
+static size_t bank_bytes(uint64_t cap) { return 16 * (((cap * 8) + 255) & ~static_cast<uint64_t>(255)); }
 
 // Event-sorted schedule: slices of whole work units fill a particle bank;
 // each launch advances every live particle by one event and compacts the

@@ -63,6 +63,18 @@ __device__ __forceinline__ CellsLds<F32> global_cells(const TransportParams& P, 
     return C;
 }
 
+// A bank particle's cell word carries its need-a-flight flag in bit 31
+// (cell indices stay below 2^31): no separate flag word to read and write
+// per event.
+constexpr uint32_t kNeedTauBit = 0x80000000u;
+
+template <bool F32>
+__device__ __forceinline__ void load_cell(const EventBank& b, uint32_t i, Particle<F32>& p) {
+    const uint32_t w = static_cast<uint32_t>(b.cell[i]);
+    p.cell = static_cast<int32_t>(w & ~kNeedTauBit);
+    p.need_tau = (w & kNeedTauBit) != 0;
+}
+
 template <bool F32>
 __device__ __forceinline__ void store_particle(const EventBank& b, uint32_t i, const Particle<F32>& p, uint32_t ev,
                                                uint32_t co, uint32_t unit, uint32_t rec) {
@@ -72,12 +84,11 @@ __device__ __forceinline__ void store_particle(const EventBank& b, uint32_t i, c
     v.t[i] = p.t;
     v.tau[i] = p.tau;
     b.X[i] = p.X;
-    b.cell[i] = p.cell;
+    b.cell[i] = static_cast<int32_t>(static_cast<uint32_t>(p.cell) | (p.need_tau ? kNeedTauBit : 0u));
     b.tb[i] = p.tb;
     b.hdraws[i] = p.hdraws;
     b.events[i] = ev;
     b.colls[i] = co;
-    b.flags[i] = p.need_tau ? 1u : 0u;
     b.unit[i] = unit;
     b.rec[i] = rec;
 }
@@ -163,10 +174,9 @@ __global__ void __launch_bounds__(kEventStepBlock) k_event_step(EventParams E) {
             p.t = v.t[i];
             p.tau = v.tau[i];
             p.X = E.in.X[i];
-            p.cell = E.in.cell[i];
+            load_cell<F32>(E.in, i, p);
             p.tb = E.in.tb[i];
             p.hdraws = E.in.hdraws[i];
-            p.need_tau = (E.in.flags[i] & 1u) != 0;
             cnt.events = E.in.events[i];
             cnt.collisions = E.in.colls[i];
             unit = E.in.unit[i];
@@ -240,10 +250,9 @@ __global__ void __launch_bounds__(256) k_event_finish(EventParams E) {
         p.t = v.t[i];
         p.tau = v.tau[i];
         p.X = E.in.X[i];
-        p.cell = E.in.cell[i];
+        load_cell<F32>(E.in, i, p);
         p.tb = E.in.tb[i];
         p.hdraws = E.in.hdraws[i];
-        p.need_tau = (E.in.flags[i] & 1u) != 0;
         cnt.events = E.in.events[i];
         cnt.collisions = E.in.colls[i];
         const uint32_t unit = E.in.unit[i];

@@ -136,12 +136,11 @@ struct EventBank {
     double* x64; double* mu64; double* t64; double* tau64;
     float* x32; float* mu32; float* t32; float* tau32;
     uint64_t* X;             // LCG state
-    int32_t* cell;
+    int32_t* cell;           // bit 31: the next step samples a flight
     int32_t* tb;
     uint32_t* hdraws;        // numbers drawn by the history so far
     uint32_t* events;        // events of the history so far
     uint32_t* colls;         // collisions of the history so far
-    uint32_t* flags;         // bit 0: the next step samples a flight
     uint32_t* unit;          // work unit (partial-tally slot, problem)
     uint32_t* rec;           // index of the history's outcome record
 };
