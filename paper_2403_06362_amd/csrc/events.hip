@@ -75,13 +75,15 @@ __device__ __forceinline__ void load_cell(const EventBank& b, uint32_t i, Partic
     p.need_tau = (w & kNeedTauBit) != 0;
 }
 
-template <bool F32>
+// TIMED false: no problem of the set is timed, so a particle's time is never
+// read and is not stored.
+template <bool F32, bool TIMED>
 __device__ __forceinline__ void store_particle(const EventBank& b, uint32_t i, const Particle<F32>& p, uint32_t ev,
                                                uint32_t co, uint32_t unit, uint32_t rec) {
     BankView<F32> v = view<F32>(b);
     v.x[i] = p.x;
     v.mu[i] = p.mu;
-    v.t[i] = p.t;
+    if (TIMED) v.t[i] = p.t;
     v.tau[i] = p.tau;
     b.X[i] = p.X;
     b.cell[i] = static_cast<int32_t>(static_cast<uint32_t>(p.cell) | (p.need_tau ? kNeedTauBit : 0u));
@@ -117,7 +119,7 @@ __global__ void __launch_bounds__(256) k_event_init(EventParams E) {
     S.table = PR.table;
     Particle<F32> p;
     init_particle<F32, TIMED>(p, C, E.tp.lcg, S, U.j0 + (r - E.rec_begin[lo]));
-    store_particle<F32>(E.in, i, p, 0u, 0u, su, static_cast<uint32_t>(r));
+    store_particle<F32, TIMED>(E.in, i, p, 0u, 0u, su, static_cast<uint32_t>(r));
 }
 
 constexpr int kEventStepBlock = 1024;
@@ -171,7 +173,7 @@ __global__ void __launch_bounds__(kEventStepBlock) k_event_step(EventParams E) {
             BankView<F32> v = view<F32>(E.in);
             p.x = v.x[i];
             p.mu = v.mu[i];
-            p.t = v.t[i];
+            p.t = TIMED ? v.t[i] : 0;
             p.tau = v.tau[i];
             p.X = E.in.X[i];
             load_cell<F32>(E.in, i, p);
@@ -216,7 +218,7 @@ __global__ void __launch_bounds__(kEventStepBlock) k_event_step(EventParams E) {
         __syncthreads();
         if (alive) {
             const uint32_t lt = static_cast<uint32_t>(__popcll(mask & ((lane == 0) ? 0ull : (~0ull >> (64 - lane)))));
-            store_particle<F32>(E.out, s_base + s_wave_count[wid] + lt, p, static_cast<uint32_t>(cnt.events),
+            store_particle<F32, TIMED>(E.out, s_base + s_wave_count[wid] + lt, p, static_cast<uint32_t>(cnt.events),
                                 static_cast<uint32_t>(cnt.collisions), unit, rec);
         }
         __syncthreads();   // s_wave_count and s_base are reused by the next pass
@@ -247,7 +249,7 @@ __global__ void __launch_bounds__(256) k_event_finish(EventParams E) {
         LaneCounters cnt;
         p.x = v.x[i];
         p.mu = v.mu[i];
-        p.t = v.t[i];
+        p.t = TIMED ? v.t[i] : 0;
         p.tau = v.tau[i];
         p.X = E.in.X[i];
         load_cell<F32>(E.in, i, p);
