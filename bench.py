@@ -16,7 +16,9 @@ Also reported, each timed separately after the headline loop:
                 HBM)
   transport     the 1e8-history long-chain slab (50 mfp, c = 0.99, 200 bins,
                 64 batches): histories/s, draws/s, events/s for hash FP64,
-                hash FP32-flight and stride FP64 (kernel time, HIP events)
+                hash FP32-flight and stride FP64 (kernel time, HIP events),
+                launch options from the library's autotuner (one search per
+                precision, reported under "opts")
   pulse         the paper's test problem (pulse in an infinite multiplying
                 medium, secondaries seeded on demand), 1000 x 1000 sources:
                 hash-seeded generation banks, event-based passes and
@@ -38,6 +40,7 @@ FP32, against one launch per problem) and the 2e8-history multi-region
 slab are added.
 
 Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 10] [--full] [--no-cpu]
+                       [--no-transport] [--no-pulse] [--no-autotune] [--copy-probe]
 """
 from __future__ import annotations
 
@@ -253,6 +256,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-transport", action="store_true", help="headline draw workload only")
     ap.add_argument("--no-pulse", action="store_true", help="skip the pulse-problem legs")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="long-chain legs with the default launch options (no autotuner runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 512 MiB device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -347,12 +352,22 @@ def main():
     if not args.no_transport:
         ctx = M.Context(0)
         prob = W.long_chain()
+        # launch options from the library's autotuner, once per precision on
+        # the hash-seeded problem (the stride leg reuses the FP64 choice)
+        tuned = {}
+        for prec in (0, 1):
+            if args.no_autotune:
+                tuned[prec] = M.make_opts(precision=prec)
+                continue
+            log("transport long chain: autotune", "fp32" if prec else "fp64")
+            tuned[prec], _ = ctx.autotune(lcg, [prob.with_(seeding=W.hash_seeding())], M.make_opts(precision=prec))
         legs = {}
         for name, sd, prec in (("hash_fp64", W.hash_seeding(), 0), ("hash_fp32", W.hash_seeding(), 1),
                                ("stride_fp64", W.stride_seeding(), 0)):
             log("transport long chain", name)
-            legs[name] = transport_leg(M, W, torch, lcg, ctx, prob.with_(seeding=sd), M.make_opts(precision=prec))
-        tr = {"workload": "long-chain slab: 50 mfp, sigma_t=1, c=0.99, 200 bins, 1e8 histories, 64 batches"}
+            legs[name] = transport_leg(M, W, torch, lcg, ctx, prob.with_(seeding=sd), tuned[prec])
+        tr = {"workload": "long-chain slab: 50 mfp, sigma_t=1, c=0.99, 200 bins, 1e8 histories, 64 batches",
+              "opts": {"fp64": tuned[0].as_dict(), "fp32": tuned[1].as_dict()}}
         for k, v in legs.items():
             tr[k] = {kk: vv for kk, vv in v.items() if kk not in ("flux", "diag")}
         tr["fp32_vs_fp64_flux"] = fp32_error(legs["hash_fp32"]["flux"], legs["hash_fp64"]["flux"], prob)
