@@ -89,22 +89,29 @@ uint64_t orc_skip(uint64_t x0, uint64_t k, uint64_t g, uint64_t c, uint32_t m)
 }
 
 /* ------------------------------------------------------------------ */
-/* Listing 1: the modified 64-bit MurmurHash with one 64-bit key and one
- * 64-bit seed; all arithmetic is modulo 2^64 (wrapping multiplies). */
+/* hash(k, s) of Listing 1 (a modified 64-bit MurmurHash, one 64-bit key
+ * and one 64-bit seed), written as a composition of two bijections of the
+ * 64-bit words (all arithmetic modulo 2^64):
+ *   mul_m(x)  = M x          (M is odd, so this is invertible)
+ *   fold47(y) = y ^ (y >> 47) (its own inverse, since 2 x 47 > 64)
+ *   mix       = fold47 after mul_m
+ * The seed enters as the word mix(s ^ 8M), the key as mul_m(mix(k)), and the
+ * hash is mix of their exclusive or. */
 /* ------------------------------------------------------------------ */
 
 static const uint64_t MURMUR_M = 0xC6A4A7935BD1E995ull;
 
-uint64_t orc_subhash(uint64_t x)
-{
-    uint64_t y = x * MURMUR_M;
-    return y ^ (y >> 47);
-}
+static uint64_t mul_m(uint64_t x) { return x * MURMUR_M; }
+
+static uint64_t fold47(uint64_t y) { return y ^ (y >> 47); }
+
+uint64_t orc_subhash(uint64_t x) { return fold47(mul_m(x)); }
 
 uint64_t orc_hash(uint64_t k, uint64_t s)
 {
-    uint64_t seed_hash = orc_subhash(s ^ (8 * MURMUR_M));
-    return orc_subhash(seed_hash ^ (orc_subhash(k) * MURMUR_M));
+    const uint64_t seed_word = orc_subhash(s ^ mul_m(8));
+    const uint64_t key_word = mul_m(orc_subhash(k));
+    return orc_subhash(seed_word ^ key_word);
 }
 
 /* ------------------------------------------------------------------ */

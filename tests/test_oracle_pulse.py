@@ -5,7 +5,9 @@ The pins come from outside the oracle's own code: hand-derived families
 driven by scripted uniforms, the seed-splitting rule of eq. (5) checked
 against the separately pinned hash and LCG primitives, exact particle and
 draw balances, and closed forms of the expected collision counts (pure
-absorber, critical pure scatterer, supercritical growth e^{(c nu - 1) t})."""
+absorber, critical pure scatterer, supercritical growth e^{(c nu - 1) t}),
+and the flux normalisation against the pure absorber's uncollided flux
+(sigma_t, window and time-bin widths not 1, several batches)."""
 import math
 
 import numpy as np
@@ -218,12 +220,37 @@ def test_hash_and_stride_agree_in_distribution(orc):
     assert np.all(np.abs(z) < 5.0), z
 
 
-def test_flux_normalisation(orc):
-    p = W.pulse(W.hash_seeding(), n_batches=3, per_batch=10).with_(
-        time_edges=np.array([0.0, 0.5, 2.0, 20.0]))
-    r = orc.pulse(p, LCG)
+def _absorber_hit_prob(sig, x_lo, x_hi, a, b):
+    """P(one source of a pure absorber collides at a time in [a, b) inside
+    [x_lo, x_hi]), x_lo < 0 < x_hi: the collision is at distance s with
+    density sig e^{-sig s}, at time s (speed 1) and position mu s with
+    mu ~ U[-1, 1], so P(x_lo <= mu s <= x_hi) = (min(1, x_hi/s) -
+    max(-1, x_lo/s)) / 2."""
+    from scipy.integrate import quad
+
+    def f(s):
+        g = 1.0 if s == 0.0 else 0.5 * (min(1.0, x_hi / s) - max(-1.0, x_lo / s))
+        return sig * math.exp(-sig * s) * g
+    brk = [v for v in (abs(x_lo), x_hi) if a < v < b]
+    return quad(f, a, b, points=brk or None, epsabs=1e-14, epsrel=1e-12)[0]
+
+
+def test_flux_pure_absorber_closed_form(orc):
+    """The flux normalisation against physics: for a pure absorber the
+    scalar flux is the uncollided flux e^{-sig t} / (2 t) for |x| < t, and
+    the collision estimator count / (sig N_b (x_hi - x_lo) dt) must
+    estimate its space-time average P_hit / (sig (x_hi - x_lo) dt) in every
+    batch (within 5 binomial standard errors), with sigma_t, the window and
+    the time-bin widths all different from 1 and several batches."""
+    sig, x_lo, x_hi = 1.7, -0.5, 1.2
+    te = np.array([0.0, 0.4, 1.0, 2.5, 4.0])
+    p = W.PulseProblem(sigma_t=sig, scatter=0.0, x_lo=x_lo, x_hi=x_hi, time_edges=te, n_batches=5,
+                       per_batch=20000, seeding=W.hash_seeding())
+    r = orc.pulse(p, LCG, threads=8)
     f = orc.pulse_flux(p, LCG, r.counts)
-    dt = np.diff(p.time_edges)
-    for b in range(3):
-        for k in range(3):
-            assert f[b, k] == float(r.counts[b, k]) / (((1.0 * 10.0) * 2.0) * dt[k])
+    for k in range(len(te) - 1):
+        ph = _absorber_hit_prob(sig, x_lo, x_hi, te[k], te[k + 1])
+        den = sig * (x_hi - x_lo) * (te[k + 1] - te[k])
+        se = math.sqrt(ph * (1.0 - ph) / p.per_batch) / den
+        for b in range(p.n_batches):
+            assert abs(f[b, k] - ph / den) < 5 * se, (b, k, f[b, k], ph / den, se)

@@ -10,7 +10,10 @@ The pins come from outside the oracle's code:
 * exact particle and draw balances;
 * the supercritical closed form e^{0.1 t}, which the weighted estimate must
   still meet;
-* agreement in distribution with the uncontrolled problem."""
+* agreement in distribution with the uncontrolled problem;
+* the weighted flux normalisation against the pure absorber's closed form
+  (sigma_t, window and time-bin widths not 1, a census that changes the
+  population, so a missing weight, sigma_t or dt fails)."""
 import math
 from fractions import Fraction
 
@@ -213,6 +216,28 @@ def test_center_flux_agrees_with_plain(orc):
     fr = orc.pulse_flux(p, LCG, ref.counts)
     z = (fp.mean(0) - fr.mean(0)) / np.sqrt(fp.var(0, ddof=1) / fp.shape[0] + fr.var(0, ddof=1) / fr.shape[0])
     assert np.all(np.abs(z) < 5.0), z
+
+
+def test_weighted_flux_pure_absorber_closed_form(orc):
+    """Population control must not bias the flux: a pure absorber
+    (sigma_t = 1.7) with a census at t = 1.0 that brings each batch's ~180
+    survivors back to 300 (weight ~0.6 afterwards).  Each time bin's mean
+    flux over the batches meets the uncollided closed form
+    P_hit / (sigma_t (x_hi - x_lo) dt) within 5 standard errors of the
+    batch means."""
+    from test_oracle_pulse import _absorber_hit_prob
+    sig, x_lo, x_hi = 1.7, -0.5, 1.2
+    te = np.array([0.0, 0.4, 1.0, 2.5, 4.0])
+    p = W.PulseProblem(sigma_t=sig, scatter=0.0, x_lo=x_lo, x_hi=x_hi, time_edges=te, n_batches=200,
+                       per_batch=1000, seeding=W.hash_seeding(), census_every=2, pc_target=300)
+    r = orc.pulse_pc(p, LCG, threads=8)
+    assert r.pop.shape == (200, 1, 2) and abs(r.pop[:, 0, 1].mean() - 300) < 5
+    assert abs(r.pop[:, 0, 0].mean() - 1000 * math.exp(-sig)) < 5
+    f = orc.pulse_pc_flux(p, LCG, r.counts, r.pop)
+    mean, se = f.mean(axis=0), f.std(axis=0, ddof=1) / math.sqrt(f.shape[0])
+    for k in range(len(te) - 1):
+        want = _absorber_hit_prob(sig, x_lo, x_hi, te[k], te[k + 1]) / (sig * (x_hi - x_lo) * (te[k + 1] - te[k]))
+        assert abs(mean[k] - want) < 5 * se[k], (k, mean[k], want, se[k])
 
 
 def test_rejects_stride_and_missing_target(orc):

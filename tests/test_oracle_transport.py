@@ -14,6 +14,11 @@
 * Exact particle balance; collision-estimator identity
   E[sum sigma_t * track] = E[collisions] (both estimate the collision rate).
 * Integer tallies are independent of threads, sharding and batching.
+* Flux normalisation: a transparent time-dependent slab (every history's
+  track per space-time bin is the bin's x = t overlap, so the flux is that
+  overlap / (dx dt) exactly, for every batch whatever its size), and a
+  time-dependent pure absorber whose per-batch flux meets the closed-form
+  mean track / (dx dt) within 5 standard errors.
 """
 import math
 
@@ -262,12 +267,66 @@ def test_sharding_and_batches(orc):
     assert [sum(whole.raw[b * nsb + i] for b in range(64)) for i in range(nsb)] == one.raw
 
 
-def test_flux_normalisation(orc):
-    p = W.small_slab(n_histories=2000)
+def _bin_overlap(lo_a, hi_a, lo_b, hi_b):
+    lo, hi = max(lo_a, lo_b), min(hi_a, hi_b)
+    return (lo, hi) if lo < hi else None
+
+
+def test_flux_transparent_slab_exact(orc):
+    """A nearly transparent time-dependent slab: every particle runs at
+    x = t from the left face to the right face, so its track in space bin k
+    and time bin i is the overlap of [x_k, x_k+1) with [t_i, t_i+1), the
+    same for every history.  The flux of each (batch, time bin, space bin)
+    is then exactly that overlap / (dx dt), whatever the batch's size: N is
+    not a multiple of the batch count (batch sizes 3, 3, 3, 1), and no
+    width is 1."""
+    be = [0.0, 0.5, 1.5, 3.0, 4.2]
+    te = [0.0, 0.7, 2.0, 3.1, 5.0]
+    p = slab([0.0, 2.2, 4.2], [1e-7, 2e-7], [0.0, 0.0], be, n=10, time_edges=te, n_batches=4)
     t = orc.transport(p, LCG)
-    fl = orc.flux(p, t)
-    for i in (0, 5, 19):
-        assert fl[i] == (orc.u128_to_f64(t.raw[i]) * 2.0 ** -56) / (2000.0 * 1.0)
+    assert t.diag["leak_right"] == 10 and t.diag["absorbed"] == 0
+    assert orc.batch_sizes(p) == [3, 3, 3, 1]
+    fl = orc.flux(p, t).reshape(4, 4, 4)
+    for b in range(4):
+        for i in range(4):
+            for k in range(4):
+                ov = _bin_overlap(be[k], be[k + 1], te[i], te[i + 1])
+                want = 0.0 if ov is None else (ov[1] - ov[0]) / ((be[k + 1] - be[k]) * (te[i + 1] - te[i]))
+                assert fl[b, i, k] == pytest.approx(want, rel=1e-12, abs=0.0), (b, i, k)
+
+
+def test_flux_time_dependent_absorber_per_batch(orc):
+    """Pure absorber (sigma_t = 0.6) at speed 1: the particle is at x = t
+    until it is absorbed at a distance S ~ Exp(sigma_t).  Its track in a
+    (time bin, space bin) cell whose x = t overlap is [lo, hi) is
+    T = min(max(S - lo, 0), hi - lo), with
+      E[T]   = e^{-s lo} (1 - e^{-s w}) / s,
+      E[T^2] = 2 e^{-s lo} (1/s^2 - e^{-s w} (w/s + 1/s^2)),  w = hi - lo.
+    Every batch's flux must lie within 5 standard errors of
+    E[T] / (dx dt), with N_b that batch's own history count (N = 40003 in
+    6 batches, the last one smaller), dx and dt not 1."""
+    S = 0.6
+    be = [0.0, 0.8, 2.0, 3.5, 6.0]
+    te = [0.0, 0.9, 2.2, 3.0, 4.6, 7.0]
+    p = slab([0.0, 6.0], [S], [0.0], be, n=40003, time_edges=te, n_batches=6)
+    t = orc.transport(p, LCG, threads=8)
+    nb = orc.batch_sizes(p)
+    assert nb[-1] < nb[0]
+    fl = orc.flux(p, t).reshape(6, 5, 4)
+    for i in range(5):
+        for k in range(4):
+            dxdt = (be[k + 1] - be[k]) * (te[i + 1] - te[i])
+            ov = _bin_overlap(be[k], be[k + 1], te[i], te[i + 1])
+            if ov is None:
+                assert np.all(fl[:, i, k] == 0.0)
+                continue
+            lo, w = ov[0], ov[1] - ov[0]
+            m1 = math.exp(-S * lo) * (1.0 - math.exp(-S * w)) / S
+            m2 = 2.0 * math.exp(-S * lo) * (1.0 / S ** 2 - math.exp(-S * w) * (w / S + 1.0 / S ** 2))
+            sd = math.sqrt(m2 - m1 * m1)
+            for b in range(6):
+                se = sd / math.sqrt(nb[b]) / dxdt
+                assert abs(fl[b, i, k] - m1 / dxdt) < 5 * se, (b, i, k, fl[b, i, k], m1 / dxdt, se)
 
 
 def test_stride_exceedance_counted(orc):
