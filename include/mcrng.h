@@ -224,11 +224,16 @@ int mcrng_reduce_tallies(mcrng_ctx *ctx, uint64_t *d_raw, double *d_flux, uint64
 
 /* Times candidate launch options for the problem set (each candidate run
  * once after a warm-up, timed with HIP events on `stream`; the call
- * synchronises the stream) and writes the fastest to *best.  `base` fixes
- * precision and schedule; the search covers block size, histories per
- * lane, work-unit size, tally copies and (history schedule) the collision
- * batch.  The choice is cached in the
- * context per problem-set shape.  *best_ms receives its time (may be NULL). */
+ * synchronises the stream) and writes the fastest to *best.  `base` (NULL =
+ * all defaults) fixes precision, schedule, grid, bank size and use_graph;
+ * the search covers block size, histories per lane, work-unit size, tally
+ * copies and (history schedule) the collision batch, by coordinate
+ * descent.  The generator, problems and options are validated as by
+ * mcrng_run_histories before anything is timed.  The choice is cached in
+ * the context per (problem set, normalised base options): a repeated call
+ * returns it without timing and sets *best_ms to -1.  *best_ms receives the
+ * chosen options' time otherwise (may be NULL).  The runs leave the
+ * context's partial tallies in the state of the last candidate's run. */
 int mcrng_autotune(mcrng_ctx *ctx, const mcrng_lcg *lcg, const mcrng_problem *problems,
                    uint32_t n_problems, const mcrng_run_opts *base, mcrng_run_opts *best,
                    float *best_ms, void *stream);

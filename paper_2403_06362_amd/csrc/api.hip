@@ -897,19 +897,27 @@ extern "C" int mcrng_reduce_tallies(mcrng_ctx* ctx, uint64_t* d_raw, double* d_f
 
 // ------------------------------------------------------------------ autotuner
 
+// Cache key of a tuning: the problem set (generator, geometry, seeding,
+// history counts) and every base option, normalised (the search overwrites
+// block, hist_per_lane, tally_copies, coll_batch and unit_histories, but
+// the other fields, e.g. grid and bank_size, change what is timed).
 static uint64_t shape_key(const mcrng_lcg* lcg, const mcrng_problem* P, uint32_t n, const mcrng_run_opts& base) {
     uint64_t h = signature(lcg, P, n, 0);
-    h = fnv(h, &base.precision, sizeof base.precision);
-    h = fnv(h, &base.schedule, sizeof base.schedule);
-    return h;
+    return fnv(h, &base, sizeof base);
 }
 
 extern "C" int mcrng_autotune(mcrng_ctx* ctx, const mcrng_lcg* lcg, const mcrng_problem* problems, uint32_t n_problems,
                               const mcrng_run_opts* base, mcrng_run_opts* best, float* best_ms, void* stream) {
     if (!ctx || !best) return fail(MCRNG_EINVAL, "ctx and best are required");
-    mcrng_run_opts b0;
-    int rc = normalise_opts(base, &b0);
+    if (!problems) return fail(MCRNG_EINVAL, "problems is NULL");
+    if (n_problems == 0) return fail(MCRNG_EINVAL, "n_problems must be >= 1");
+    LcgDev L;
+    int rc = validate_lcg(lcg, 53, &L);
     if (rc < 0) return rc;
+    mcrng_run_opts b0;
+    if ((rc = normalise_opts(base, &b0)) < 0) return rc;
+    for (uint32_t i = 0; i < n_problems; ++i)
+        if ((rc = validate_problem(problems[i], i)) < 0) return rc;
     const uint64_t key = shape_key(lcg, problems, n_problems, b0);
     auto hit = ctx->tuned.find(key);
     if (hit != ctx->tuned.end()) {
@@ -955,6 +963,7 @@ extern "C" int mcrng_autotune(mcrng_ctx* ctx, const mcrng_lcg* lcg, const mcrng_
     const uint32_t u0 = default_unit_histories(problems, n_problems);
     if ((rc = try_field(&mcrng_run_opts::unit_histories, {u0 / 4 > 256 ? u0 / 4 : 256, u0, u0 * 4})) < 0) return rc;
     if (cur.unit_histories == 0) cur.unit_histories = u0;
+    cur.use_graph = b0.use_graph;
     HIP_TRY(hipStreamSynchronize(st));
     ctx->tuned[key] = cur;
     *best = cur;

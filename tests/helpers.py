@@ -1,6 +1,18 @@
 """Small helpers shared by the GPU tests (tensor <-> NumPy for unsigned
 words, which torch supports only partially)."""
+import os
+
 import numpy as np
+
+
+def host_threads(cap=16):
+    """Oracle worker threads: the host cores this process may use, at most
+    `cap` (the CPU share of one GPU on a shared node)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(cap, n))
 
 
 def u64_np(t):

@@ -57,6 +57,44 @@ def test_host_validation_without_gpu(M):
     assert lib.mcrng_reduce_tallies(None, None, None, None, None) == B.EINVAL
 
 
+def test_autotune_host_validation_without_gpu(M):
+    """mcrng_autotune checks every argument (generator, problems, options)
+    before it hashes the problem set or times anything."""
+    import workloads as W
+    from paper_2403_06362_amd import _binding as B
+    lib = M.lib()
+    L = B.make_lcg(W.Lcg())
+    arr, keep = B.make_problems([W.small_slab(n_histories=100)])
+    best = B.RunOpts()
+    fake_ctx = C.c_void_p(16)   # never dereferenced: validation fails first
+
+    def call(ctx, lcg, probs, n, base=None, out=True):
+        rc = lib.mcrng_autotune(ctx, lcg, probs, n, base, C.byref(best) if out else None, None, None)
+        return rc, lib.mcrng_last_error().decode()
+
+    assert call(None, C.byref(L), arr, 1)[0] == B.EINVAL
+    assert call(fake_ctx, C.byref(L), arr, 1, out=False)[0] == B.EINVAL
+    rc, msg = call(fake_ctx, None, arr, 1)
+    assert rc == B.EINVAL and "lcg" in msg
+    rc, msg = call(fake_ctx, C.byref(L), None, 1)
+    assert rc == B.EINVAL and "problems" in msg
+    rc, msg = call(fake_ctx, C.byref(L), arr, 0)
+    assert rc == B.EINVAL and "n_problems" in msg
+    bad_opts = B.make_opts(block=96)
+    rc, msg = call(fake_ctx, C.byref(L), arr, 1, C.byref(bad_opts))
+    assert rc == B.EINVAL and "block" in msg
+    short = B.make_lcg(W.Lcg(m=40))
+    rc, msg = call(fake_ctx, C.byref(short), arr, 1)
+    assert rc == B.EINVAL and "m" in msg
+    badp, keep2 = B.make_problems([W.small_slab(n_histories=100).with_(sigma_t=np.array([-1.0]))])
+    rc, msg = call(fake_ctx, C.byref(L), badp, 1)
+    assert rc == B.EINVAL and "sigma_t" in msg
+    nregions, keep3 = B.make_problems([W.small_slab(n_histories=100)])
+    nregions[0].n_regions = 0
+    rc, msg = call(fake_ctx, C.byref(L), nregions, 1)
+    assert rc == B.EINVAL and "n_regions" in msg
+
+
 def test_tally_bins_host_only(M):
     import workloads as W
     probs = [W.small_slab(), W.long_chain(n_histories=10), W.multi_region(n_histories=10)]

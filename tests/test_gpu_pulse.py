@@ -6,15 +6,14 @@ Counts are integers, so the bar is bit-exact counts per (batch, time bin),
 bit-exact flux and equal diagnostics, for every schedule (particle banks by
 generation, depth-first families per lane) and launch shape.  At the
 paper's full study size (30 repetitions x 1000 batches x 1000 sources) the
-oracle recomputes sampled batches; the run is checked whole by its exact
-balances."""
+oracle recomputes the whole run for both seedings."""
 import sys
 
 import numpy as np
 import pytest
 
 import workloads as W
-from helpers import u64_np
+from helpers import host_threads, u64_np
 
 pytestmark = pytest.mark.gpu
 LCG = W.Lcg()
@@ -182,26 +181,26 @@ def test_stack_overflow_is_reported(M, ctx):
     assert d["sources"] == 5
 
 
-def test_full_study_sampled(M, ctx, orc):
+@pytest.mark.parametrize("kind", ["hash", "stride"])
+def test_full_study_whole(M, ctx, orc, kind):
     """The paper's normality study at full size: 30 repetitions x 1000
     batches x 1000 sources = 3e7 sources in one run (the bank schedule goes
-    through several source chunks).  Sampled batches are recomputed by the
-    oracle; the whole run satisfies the exact particle and draw balances."""
-    p = W.pulse(W.hash_seeding(), n_batches=30000, per_batch=1000)
-    say("full study, hash")
-    counts, _, d = run(M, ctx, p)
+    through several source chunks).  Every batch's counts, the flux and the
+    diagnostics equal the oracle's whole run, and the exact particle and
+    draw balances hold."""
+    sd = W.hash_seeding() if kind == "hash" else W.stride_seeding()
+    p = W.pulse(sd, n_batches=30000, per_batch=1000)
+    say("full study", kind)
+    counts, flux, d = run(M, ctx, p)
     assert d["sources"] == p.n_sources
     particles = d["sources"] + d["secondaries"]
-    assert particles == d["absorbed"] + d["census"] + d["scatters"]
-    assert d["draws"] == 2 * particles + d["collisions"] + d["scatters"]
+    if kind == "hash":
+        assert particles == d["absorbed"] + d["census"] + d["scatters"]
+        assert d["draws"] == 2 * particles + d["collisions"] + d["scatters"]
     assert int(counts.sum()) == d["tallied"]
-    for b in (0, 4321, 29999):
-        ref = orc.pulse(p, LCG, b, b + 1)
-        assert np.array_equal(counts[b], ref.counts[b]), b
-    say("full study, stride")
-    ps = p.with_(seeding=W.stride_seeding())
-    counts, _, d = run(M, ctx, ps)
-    assert d["sources"] == p.n_sources and d["over_stride"] <= d["sources"]
-    for b in (1, 17000, 29998):
-        ref = orc.pulse(ps, LCG, b, b + 1)
-        assert np.array_equal(counts[b], ref.counts[b]), b
+    say("full study: oracle", kind, host_threads())
+    ref = orc.pulse(p, LCG, threads=host_threads())
+    bad = np.flatnonzero(np.any(counts != ref.counts, axis=1))
+    assert bad.size == 0, (bad.size, bad[:8])
+    assert d == ref.diag
+    assert np.array_equal(flux, orc.pulse_flux(p, LCG, ref.counts))

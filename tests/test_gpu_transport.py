@@ -4,16 +4,18 @@ mcrng_reduce_tallies) against the CPU oracle.
 Tallies are exact integers, so the bar is bit-exact raw sums (and bit-exact
 flux, whose normalisation is the same operation sequence on both sides),
 equal diagnostics, and bit-identical results across launch shapes.  At the
-full workload sizes the oracle recomputes sampled outputs: whole batches of
-the 1e8-history long-chain slab, whole small problems of the 512-problem
-set, and sub-ranges (sharding) of the 2e8-history multi-region slab."""
+full workload sizes the oracle recomputes every output: all 64 batches of
+the 1e8-history long-chain slab (FP64 and FP32), all 512 problems of the
+batched set (FP64 and FP32), and the whole 2e8-history multi-region slab
+(FP64 and FP32), whose shards and event-sorted run must add up to the same
+bits."""
 import sys
 
 import numpy as np
 import pytest
 
 import workloads as W
-from helpers import diag_dict, raw_ints
+from helpers import diag_dict, host_threads, raw_ints
 
 pytestmark = pytest.mark.gpu
 LCG = W.Lcg()
@@ -129,6 +131,36 @@ def test_graph_replays_match_eager(M, ctx, orc):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
+def test_autotune_choice_legal_cached_and_exact(M, ctx, orc, precision):
+    """The autotuner's choice for a reduced batched set and a reduced long
+    chain: every option is one the search may pick, a second call returns
+    the cached choice without timing, another base option is another cache
+    entry, and a run with the chosen options equals the oracle bit for bit
+    (and the default options' run)."""
+    sets = {"batched": W.batched(scale=2e-3)[:48], "long chain": [W.long_chain(n_histories=300_007)]}
+    for name, probs in sets.items():
+        say("autotune", name, precision)
+        best, ms = ctx.autotune(LCG, probs, M.make_opts(precision=precision))
+        d = best.as_dict()
+        assert ms > 0.0
+        assert d["precision"] == precision and d["schedule"] == 0 and d["use_graph"] == 0
+        assert d["block"] in (64, 128, 256, 512, 1024)
+        assert d["hist_per_lane"] in (1, 2, 4)
+        assert d["tally_copies"] in (1, 2)
+        assert d["coll_batch"] in (1, 16, 24, 32, 48)
+        assert 256 <= d["unit_histories"] <= (1 << 18)
+        assert d["grid"] == 0 and d["bank_size"] == 0 and not any(best.reserved)
+        again, ms2 = ctx.autotune(LCG, probs, M.make_opts(precision=precision))
+        assert again.as_dict() == d and ms2 == -1.0
+        _, ms3 = ctx.autotune(LCG, probs, M.make_opts(precision=precision, grid=256))
+        assert ms3 > 0.0   # a different base is a separate search
+        tuned = run(M, ctx, probs, **d)
+        default = run(M, ctx, probs, precision=precision)
+        assert tuned[0] == default[0] and tuned[2] == default[2]
+        check_parity(orc, probs, *tuned, float_mode=bool(precision), threads=8)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
 def test_event_schedule_matches_oracle_and_history(M, ctx, orc, precision):
     """Event-sorted schedule (one event per particle per launch, compacted
     bank) gives the history-based schedule's and the oracle's bits."""
@@ -221,55 +253,76 @@ def _batch_raw(raw, p, b):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-def test_long_chain_full_size_sampled_batches(M, ctx, orc, precision):
-    """1e8 histories, 64 batches (the transport benchmark configuration):
-    two whole batches recomputed by the oracle, plus exact balance."""
+def test_long_chain_full_size_whole(M, ctx, orc, precision):
+    """1e8 histories, 64 batches (the transport benchmark configuration, in
+    its default launch options): every batch's raw sums, the flux and the
+    diagnostics equal the oracle's whole run."""
     p = W.long_chain()
     say("long chain full", precision)
     raw, flux, diag = run(M, ctx, [p], precision=precision)
-    d = diag[0]
-    assert d["histories"] == p.n_histories
-    assert d["leak_left"] + d["leak_right"] + d["absorbed"] + d["census"] == p.n_histories
-    bs = p.n_histories // p.n_batches
-    for b in (0, 45):
-        ref = orc.transport(p, LCG, float_mode=bool(precision), j0=b * bs, j1=(b + 1) * bs, threads=16)
-        assert _batch_raw(raw, p, b) == _batch_raw(ref.raw, p, b), b
+    say("long chain full: oracle", precision, host_threads())
+    ref = orc.transport(p, LCG, float_mode=bool(precision), threads=host_threads())
+    bad = [i for i, (a, b) in enumerate(zip(raw, ref.raw)) if a != b]
+    assert not bad, (len(bad), bad[:8])
+    assert diag[0] == ref.diag
+    assert np.array_equal(flux, orc.flux(p, ref))
 
 
-def test_multi_region_full_size_sharded(M, ctx, orc):
-    """2e8 histories: the full run equals the sum of two shards run
-    separately (first_index), a sub-range agrees with the oracle, and the
-    particle balance is exact."""
+def test_multi_region_full_size_whole_and_sharded(M, ctx, orc):
+    """2e8 histories: the full run equals the oracle's whole run, equals the
+    sum of two shards run separately (first_index) with other launch
+    shapes, and equals the event-sorted schedule's run."""
     p = W.multi_region()
     say("multi region full")
-    raw, _, diag = run(M, ctx, [p])
-    assert diag[0]["histories"] == p.n_histories
-    d = diag[0]
-    assert d["leak_left"] + d["leak_right"] + d["absorbed"] + d["census"] == p.n_histories
+    raw, flux, diag = run(M, ctx, [p])
+    say("multi region full: oracle", host_threads())
+    ref = orc.transport(p, LCG, threads=host_threads())
+    assert raw == ref.raw and diag[0] == ref.diag
+    assert np.array_equal(flux, orc.flux(p, ref))
     h = p.n_histories // 2
     a = p.with_(n_histories=h)
     b = p.with_(n_histories=p.n_histories - h, seeding=W.hash_seeding(first_index=h))
     ra, _, _ = run(M, ctx, [a], block=512, unit_histories=100_000)
     rb, _, _ = run(M, ctx, [b], block=128, hist_per_lane=2)
     assert [x + y for x, y in zip(ra, rb)] == raw
-    sub = p.with_(n_histories=200_000, seeding=W.hash_seeding(first_index=150_000_000))
-    rs, _, ds = run(M, ctx, [sub])
-    ref = orc.transport(sub, LCG, threads=16)
-    assert rs == ref.raw and ds[0] == ref.diag
     say("multi region full, event-sorted schedule")
     re_, _, de = run(M, ctx, [p], schedule=1)
     assert re_ == raw and de == diag
 
 
-def test_batched_full_size_small_problems(M, ctx, orc):
-    """512 problems, 5.6e8 histories in one persistent launch: the 24
-    smallest problems recomputed whole by the oracle."""
+def test_multi_region_full_size_fp32_whole(M, ctx, orc):
+    """The FP32-flight form of the 2e8-history multi-region slab equals the
+    oracle's FP32 mode bit for bit."""
+    p = W.multi_region()
+    say("multi region full fp32")
+    raw, _, diag = run(M, ctx, [p], precision=1)
+    say("multi region full fp32: oracle", host_threads())
+    ref = orc.transport(p, LCG, float_mode=True, threads=host_threads())
+    assert raw == ref.raw and diag[0] == ref.diag
+
+
+def _oracle_set(orc, probs, float_mode=False):
+    """The oracle over a problem set, one problem per worker thread."""
+    from concurrent.futures import ThreadPoolExecutor
+    order = sorted(range(len(probs)), key=lambda i: -probs[i].n_histories)   # largest first
+    with ThreadPoolExecutor(host_threads()) as ex:
+        res = dict(zip(order, ex.map(lambda i: orc.transport(probs[i], LCG, float_mode=float_mode), order)))
+    return [res[i] for i in range(len(probs))]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batched_full_size_whole(M, ctx, orc, precision):
+    """512 problems, 5.4e8 histories in one persistent launch: every
+    problem's raw sums and diagnostics equal the oracle's (including the
+    1e6-1e7-history problems that load the persistent scheduler)."""
     probs = W.batched()
-    say("batched full")
-    raw, _, diag = run(M, ctx, probs)
+    say("batched full", precision)
+    raw, flux, diag = run(M, ctx, probs, precision=precision)
+    say("batched full: oracle", precision, host_threads())
+    refs = _oracle_set(orc, probs, float_mode=bool(precision))
     parts = split(raw, probs)
-    order = np.argsort([p.n_histories for p in probs])[:24]
-    for i in order:
-        ref = orc.transport(probs[i], LCG, threads=4)
-        assert parts[i] == ref.raw, int(i)
-        assert diag[i] == ref.diag
+    fparts = split(list(flux), probs)
+    for i, ref in enumerate(refs):
+        assert parts[i] == ref.raw, i
+        assert diag[i] == ref.diag, i
+        assert np.array_equal(np.array(fparts[i]), orc.flux(probs[i], ref)), i
