@@ -222,6 +222,36 @@ int mcrng_run_histories(mcrng_ctx *ctx, const mcrng_lcg *lcg, const mcrng_proble
 int mcrng_reduce_tallies(mcrng_ctx *ctx, uint64_t *d_raw, double *d_flux, uint64_t *d_diag,
                          void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): runs every
+ * history of the problem set and reduces its tallies in one call, like
+ * mcrng_run_histories followed by mcrng_reduce_tallies with the same
+ * options, with the same outputs bit for bit (d_raw, d_flux, d_diag as for
+ * mcrng_reduce_tallies), without a context and without allocating any
+ * device memory: no hipMalloc, hipFree or allocating library call.
+ * Limits:
+ *   - every device buffer of the run (tables, stride skip tables, work
+ *     units, one partial tally slot per work unit, unit diagnostics, the
+ *     scheduling counter) comes from one static device array of 64 MiB per
+ *     device, which the library allocates with its code object the first
+ *     time this call runs on a device and keeps until the process ends;
+ *     a run that needs more (about units x slice_bins x 16 bytes, e.g. the
+ *     2e8-history multi-region slab takes 49 MB) returns MCRNG_EINVAL and
+ *     enqueues nothing;
+ *   - history schedule only; opts.schedule = MCRNG_SCHED_EVENT or
+ *     opts.use_graph = 1 return MCRNG_EINVAL;
+ *   - every call on a device shares that device's array and leaves its
+ *     contents to the next call (the scheduling counter is cleared by a
+ *     kernel at the start of each run, the partial slots are overwritten):
+ *     calls whose work overlaps on one device (other streams, other
+ *     threads' streams) race and give undefined results.  Calls from several
+ *     host threads are serialised while they enqueue, not on the device.
+ * Uses the current device.  Returns MCRNG_WSTRIDE_WRAP as
+ * mcrng_run_histories does. */
+int mcrng_run_histories_noalloc(const mcrng_lcg *lcg, const mcrng_problem *problems, uint32_t n_problems,
+                                const mcrng_run_opts *opts, uint64_t *d_raw, double *d_flux, uint64_t *d_diag,
+                                void *stream);
+
 /* Times candidate launch options for the problem set (each candidate run
  * once after a warm-up, timed with HIP events on `stream`; the call
  * synchronises the stream) and writes the fastest to *best.  `base` (NULL =

@@ -5,7 +5,8 @@ Paper: Cuneo & Variansyah, "An Alternative to Stride-Based RNG for Monte
 Carlo Transport" (arXiv 2403.06362).
 
 The entry points mirror the C ABI: init_streams, draw, uniforms, Context.run_histories,
-Context.reduce_tallies, Context.run_pulse, Context.run_pulse_pc (plus Context.autotune).  Tensors
+Context.reduce_tallies, Context.run_pulse, Context.run_pulse_pc (plus Context.autotune), and
+run_histories_noalloc (run and reduce without device allocation).  Tensors
 are torch device tensors; the library does all the arithmetic.
 `transport()`, `pulse()` and `pulse_pc()` are convenience wrappers that allocate the
 output tensors.
@@ -13,10 +14,10 @@ output tensors.
 from ._binding import (  # noqa: F401
     DIAG_NAMES, EXPORTS, FP32, FP64, NDIAG, PULSE_AUTO, PULSE_BANK, PULSE_DIAG_NAMES, PULSE_EVENT, PULSE_FAMILY,
     SCHED_EVENT, SCHED_HISTORY, Context, McrngError, PulseOpts, PulsePc, RunOpts, draw, init_streams, lib,
-    make_opts, make_pulse_opts, make_pulse_pc, pulse_n_census, tally_bins, uniforms,
+    make_opts, make_pulse_opts, make_pulse_pc, pulse_n_census, run_histories_noalloc, tally_bins, uniforms,
 )
 
-__all__ = ["init_streams", "draw", "uniforms", "Context", "RunOpts", "make_opts", "tally_bins", "transport", "pulse",
+__all__ = ["init_streams", "draw", "uniforms", "Context", "run_histories_noalloc", "RunOpts", "make_opts", "tally_bins", "transport", "pulse",
            "PulseOpts", "make_pulse_opts", "pulse_pc", "PulsePc", "make_pulse_pc", "pulse_n_census", "McrngError", "lib", "FP64", "FP32", "SCHED_HISTORY", "SCHED_EVENT",
            "PULSE_AUTO", "PULSE_BANK", "PULSE_FAMILY", "PULSE_EVENT", "NDIAG", "DIAG_NAMES", "PULSE_DIAG_NAMES"]
 

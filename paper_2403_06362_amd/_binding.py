@@ -31,7 +31,7 @@ PULSE_DIAG_NAMES = ("sources", "collisions", "tallied", "scatters", "absorbed", 
 EXPORTS = ("mcrng_init_streams", "mcrng_draw", "mcrng_ctx_create", "mcrng_ctx_destroy",
            "mcrng_tally_bins", "mcrng_run_histories", "mcrng_reduce_tallies", "mcrng_autotune",
            "mcrng_last_run_ms", "mcrng_last_error", "mcrng_version", "mcrng_run_pulse", "mcrng_uniforms",
-           "mcrng_run_pulse_pc")
+           "mcrng_run_pulse_pc", "mcrng_run_histories_noalloc")
 
 
 class McrngError(RuntimeError):
@@ -114,6 +114,7 @@ def lib():
         L.mcrng_run_pulse.argtypes = [vp, P(Lcg), P(PulseProblem), P(PulseOpts), vp, vp, vp, vp]
         L.mcrng_uniforms.argtypes = [P(Lcg), P(Seeding), u64, u32, vp, vp, vp]
         L.mcrng_run_pulse_pc.argtypes = [vp, P(Lcg), P(PulseProblem), P(PulsePc), P(PulseOpts), vp, vp, vp, vp, vp]
+        L.mcrng_run_histories_noalloc.argtypes = [P(Lcg), P(Problem), u32, P(RunOpts), vp, vp, vp, vp]
         for name in EXPORTS:
             if name not in ("mcrng_tally_bins", "mcrng_last_run_ms", "mcrng_last_error"):
                 getattr(L, name).restype = C.c_int
@@ -264,6 +265,21 @@ def uniforms(lcg, seeding, d_u, d_state=None, stream=None):
     S = None if seeding is None else C.byref(make_seeding(seeding))
     return _check(lib().mcrng_uniforms(C.byref(L), S, n, k, _ptr(d_state, torch.uint64, n, "d_state"),
                                        _ptr(d_u, torch.float64, n * k, "d_u"), _stream(stream)))
+
+
+def run_histories_noalloc(lcg, problems, d_raw, d_flux, d_diag=None, opts=None, stream=None):
+    """mcrng_run_histories_noalloc: run and reduce in one call, no device
+    allocation by the library (its static scratch holds the run)."""
+    import torch
+    arr, _keep = make_problems(problems)
+    nb = int(lib().mcrng_tally_bins(arr, len(problems)))
+    L = make_lcg(lcg)
+    o = opts if opts is not None else RunOpts()
+    return _check(lib().mcrng_run_histories_noalloc(C.byref(L), arr, len(problems), C.byref(o),
+                                                    _ptr(d_raw, torch.uint64, 2 * nb, "d_raw"),
+                                                    _ptr(d_flux, torch.float64, nb, "d_flux"),
+                                                    _ptr(d_diag, torch.uint64, len(problems) * NDIAG, "d_diag"),
+                                                    _stream(stream)))
 
 
 def tally_bins(problems):

@@ -84,6 +84,33 @@ static int validate_lcg(const mcrng_lcg* L, uint32_t min_m, LcgDev* out) {
     return MCRNG_OK;
 }
 
+// ------------------------------------------------------------------ arena
+
+// A bump allocator over a fixed device region (the static scratch of the
+// allocation-free entry point).  Buffers carved from it are never freed;
+// reset() hands the whole region out again.  Stride tables are computed on
+// the host when carved and uploaded later, once the whole run is known to
+// fit, so that a run that does not fit enqueues nothing.
+struct Arena {
+    char* base = nullptr;     // device address of the region on its device
+    size_t cap = 0;
+    size_t used = 0;
+    struct Table {
+        uint64_t g, c, Q;
+        uint32_t m;
+        size_t off;
+        std::vector<uint64_t> host;
+    };
+    std::vector<Table> tables;   // carved this run; uploaded by flush_tables
+    size_t uploaded = 0;         // tables[0 .. uploaded) are on the device
+    static size_t round(size_t b) { return (std::max<size_t>(b, 1) + 255) & ~static_cast<size_t>(255); }
+    void reset() {
+        used = 0;
+        tables.clear();
+        uploaded = 0;
+    }
+};
+
 // ------------------------------------------------------------------ stride tables
 
 // Process-wide cache of device skip tables, one per (device, g, c, m, Q).
@@ -103,16 +130,8 @@ struct TableKey {
 static std::mutex g_table_mu;
 static std::map<TableKey, uint64_t*> g_tables;
 
-static int get_stride_table(const LcgDev& L, uint64_t Q, const uint64_t** out) {
-    int dev = 0;
-    HIP_TRY(hipGetDevice(&dev));
-    TableKey key{dev, L.g, L.c, Q, L.m};
-    std::lock_guard<std::mutex> lk(g_table_mu);
-    auto it = g_tables.find(key);
-    if (it != g_tables.end()) {
-        *out = it->second;
-        return MCRNG_OK;
-    }
+// Host values of the skip table of stride Q (see TableKey).
+static std::vector<uint64_t> stride_table_host(const LcgDev& L, uint64_t Q) {
     std::vector<uint64_t> h(2 * kStrideDigits * kStrideRadix);
     for (int d = 0; d < kStrideDigits; ++d) {
         // Q * 16^d steps, taken modulo 2^64 (the cycle length 2^m divides it)
@@ -125,6 +144,36 @@ static int get_stride_table(const LcgDev& L, uint64_t Q, const uint64_t** out) {
             cur = compose(cur, step, L.mask);
         }
     }
+    return h;
+}
+
+// The device skip table of stride Q: from the process-wide cache, or (with
+// an arena) carved from the arena, its upload deferred to flush_tables.
+static int get_stride_table(const LcgDev& L, uint64_t Q, const uint64_t** out, Arena* arena = nullptr) {
+    if (arena) {
+        for (const Arena::Table& t : arena->tables)
+            if (t.g == L.g && t.c == L.c && t.Q == Q && t.m == L.m) {
+                *out = reinterpret_cast<const uint64_t*>(arena->base + t.off);
+                return MCRNG_OK;
+            }
+        const size_t bytes = 2 * kStrideDigits * kStrideRadix * sizeof(uint64_t);
+        if (arena->used + Arena::round(bytes) > arena->cap)
+            return fail(MCRNG_EINVAL, "stride tables exceed the %zu-byte static scratch", arena->cap);
+        arena->tables.push_back(Arena::Table{L.g, L.c, Q, L.m, arena->used, stride_table_host(L, Q)});
+        *out = reinterpret_cast<const uint64_t*>(arena->base + arena->used);
+        arena->used += Arena::round(bytes);
+        return MCRNG_OK;
+    }
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    TableKey key{dev, L.g, L.c, Q, L.m};
+    std::lock_guard<std::mutex> lk(g_table_mu);
+    auto it = g_tables.find(key);
+    if (it != g_tables.end()) {
+        *out = it->second;
+        return MCRNG_OK;
+    }
+    const std::vector<uint64_t> h = stride_table_host(L, Q);
     uint64_t* d_tab = nullptr;
     HIP_TRY(hipMalloc(&d_tab, h.size() * sizeof(uint64_t)));
     hipError_t e = hipMemcpy(d_tab, h.data(), h.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
@@ -148,7 +197,7 @@ static uint32_t hex_digits(uint64_t v) {
 
 // Fills *S for n streams; returns MCRNG_WSTRIDE_WRAP when a stride
 // allocation passes 2^m states.
-static int build_seed(const LcgDev& L, const mcrng_seeding* sd, uint64_t n, SeedDev* S) {
+static int build_seed(const LcgDev& L, const mcrng_seeding* sd, uint64_t n, SeedDev* S, Arena* arena = nullptr) {
     if (!sd) return fail(MCRNG_EINVAL, "seeding is NULL");
     S->first_index = sd->first_index;
     S->table = nullptr;
@@ -166,7 +215,7 @@ static int build_seed(const LcgDev& L, const mcrng_seeding* sd, uint64_t n, Seed
     const uint64_t last = n ? sd->first_index + n - 1 : sd->first_index;
     if (n && last < sd->first_index) return fail(MCRNG_EINVAL, "stream index overflows 64 bits");
     S->stride_digits = hex_digits(last);
-    int rc = get_stride_table(L, sd->stride, &S->table);
+    int rc = get_stride_table(L, sd->stride, &S->table, arena);
     if (rc < 0) return rc;
     const u128 used = (static_cast<u128>(sd->first_index) + n) * static_cast<u128>(sd->stride);
     const u128 cycle = static_cast<u128>(1) << L.m;
@@ -226,6 +275,7 @@ extern "C" int mcrng_draw(const mcrng_lcg* lcg, const mcrng_seeding* seeding, ui
 struct DevBuf {
     void* p = nullptr;
     size_t cap = 0;
+    Arena* arena = nullptr;   // set: carved from the arena, never hipMalloc'd or freed
 };
 
 struct mcrng_ctx {
@@ -262,10 +312,21 @@ struct mcrng_ctx {
 
     std::map<uint64_t, hipGraphExec_t> graphs;          // (tables, opts) -> executable
     std::map<uint64_t, mcrng_run_opts> tuned;           // shape -> options
+
+    Arena* arena = nullptr;   // allocation-free runs: every buffer and table comes from here
 };
 
 static int ensure(DevBuf& b, size_t bytes, hipStream_t st, size_t growth_quarters = 5) {
     if (bytes <= b.cap) return MCRNG_OK;
+    if (b.arena) {
+        Arena& a = *b.arena;
+        if (a.used + Arena::round(bytes) > a.cap)
+            return fail(MCRNG_EINVAL, "the run needs more than the %zu-byte static scratch", a.cap);
+        b.p = a.base + a.used;
+        b.cap = bytes;
+        a.used += Arena::round(bytes);
+        return MCRNG_OK;
+    }
     if (b.p) {
         HIP_TRY(hipStreamSynchronize(st));
         HIP_TRY(hipFree(b.p));
@@ -495,7 +556,7 @@ static int build_tables(mcrng_ctx* ctx, const LcgDev& L, const mcrng_problem* P,
         ctx->max_slice = std::max(ctx->max_slice, D.slice_bins);
         // seeding
         SeedDev S;
-        int rc = build_seed(L, &Q.seeding, Q.n_histories, &S);
+        int rc = build_seed(L, &Q.seeding, Q.n_histories, &S, ctx->arena);
         if (rc < 0) return rc;
         if (rc > 0) *warn = rc;
         D.seed_kind = static_cast<uint32_t>(S.kind);
@@ -579,6 +640,33 @@ static int build_tables(mcrng_ctx* ctx, const LcgDev& L, const mcrng_problem* P,
     ctx->h_group_first.assign(std::max<size_t>(ctx->h_units.size(), 1), 0);
     for (const ReduceGroup& G : ctx->h_groups)
         for (uint32_t u = G.unit_begin; u < G.unit_end; ++u) ctx->h_group_first[u] = G.unit_begin;
+    if (ctx->arena) {
+        // the device copies below, in the order they are carved: all must
+        // fit before anything is enqueued
+        Arena& a = *ctx->arena;
+        const size_t sizes[] = {
+            ctx->h_problems.size() * sizeof(DevProblem), ctx->h_edges64.size() * sizeof(double),
+            ctx->h_sig64.size() * sizeof(double), ctx->h_scat64.size() * sizeof(double),
+            ctx->h_cbin.size() * sizeof(int32_t), ctx->h_edges32.size() * sizeof(float),
+            ctx->h_sig32.size() * sizeof(float), ctx->h_tedges64.size() * sizeof(double),
+            ctx->h_tedges32.size() * sizeof(float), ctx->h_units.size() * sizeof(WorkUnit),
+            ctx->h_order.size() * sizeof(uint32_t), ctx->h_groups.size() * sizeof(ReduceGroup),
+            ctx->h_dx.size() * sizeof(double), ctx->h_dt.size() * sizeof(double),
+            ctx->h_pu_begin.size() * sizeof(uint32_t), ctx->h_rec_begin.size() * sizeof(uint64_t),
+            std::max<uint64_t>(slot, 2) * sizeof(uint64_t),
+            std::max<size_t>(ctx->h_units.size(), 1) * kNDiag * sizeof(uint64_t), 64};
+        size_t need = a.used;
+        for (size_t b : sizes)
+            if (b) need += Arena::round(b);
+        if (need > a.cap)
+            return fail(MCRNG_EINVAL, "the run needs %zu bytes of scratch, more than the %zu-byte static scratch", need,
+                        a.cap);
+        for (; a.uploaded < a.tables.size(); ++a.uploaded) {
+            const Arena::Table& t = a.tables[a.uploaded];
+            HIP_TRY(hipMemcpyAsync(a.base + t.off, t.host.data(), t.host.size() * sizeof(uint64_t),
+                                   hipMemcpyHostToDevice, st));
+        }
+    }
     int rc;
     if ((rc = upload(ctx->problems, ctx->h_problems, st)) < 0) return rc;
     if ((rc = upload(ctx->edges64, ctx->h_edges64, st)) < 0) return rc;
@@ -871,11 +959,7 @@ extern "C" float mcrng_last_run_ms(mcrng_ctx* ctx) {
     return ms;
 }
 
-extern "C" int mcrng_reduce_tallies(mcrng_ctx* ctx, uint64_t* d_raw, double* d_flux, uint64_t* d_diag, void* stream) {
-    if (!ctx) return fail(MCRNG_EINVAL, "ctx is NULL");
-    if (!ctx->have_run) return fail(MCRNG_ESTATE, "reduce_tallies before any run_histories");
-    if (!d_raw || !d_flux) return fail(MCRNG_EINVAL, "d_raw and d_flux are required");
-    HIP_TRY(hipSetDevice(ctx->device));
+static int enqueue_reduce(mcrng_ctx* ctx, uint64_t* d_raw, double* d_flux, uint64_t* d_diag, hipStream_t st) {
     ReduceParams rp;
     std::memset(&rp, 0, sizeof rp);
     rp.groups = static_cast<const ReduceGroup*>(ctx->groups.p);
@@ -891,8 +975,104 @@ extern "C" int mcrng_reduce_tallies(mcrng_ctx* ctx, uint64_t* d_raw, double* d_f
     rp.n_problems = ctx->n_problems;
     rp.unit_diag = static_cast<const uint64_t*>(ctx->unit_diag.p);
     rp.diag = d_diag;
-    HIP_TRY(launch_reduce(rp, static_cast<hipStream_t>(stream)));
+    HIP_TRY(launch_reduce(rp, st));
     return MCRNG_OK;
+}
+
+extern "C" int mcrng_reduce_tallies(mcrng_ctx* ctx, uint64_t* d_raw, double* d_flux, uint64_t* d_diag, void* stream) {
+    if (!ctx) return fail(MCRNG_EINVAL, "ctx is NULL");
+    if (!ctx->have_run) return fail(MCRNG_ESTATE, "reduce_tallies before any run_histories");
+    if (!d_raw || !d_flux) return fail(MCRNG_EINVAL, "d_raw and d_flux are required");
+    HIP_TRY(hipSetDevice(ctx->device));
+    return enqueue_reduce(ctx, d_raw, d_flux, d_diag, static_cast<hipStream_t>(stream));
+}
+
+// ------------------------------------------------------------------ allocation-free runs
+
+// Device memory of mcrng_run_histories_noalloc: tables, work units, partial
+// tallies, unit diagnostics and the scheduling counter of a run, carved in
+// order by an Arena.  The array belongs to this file's code object, which
+// the runtime loads on a device (and so allocates the array there) when its
+// address is first taken on that device; it stays until the process ends.
+// Host code must use the per-device address from hipGetSymbolAddress, never
+// the array's name.
+constexpr size_t kStaticScratchBytes = static_cast<size_t>(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+struct StaticDevice {
+    std::mutex mu;      // one host thread at a time builds and enqueues a run
+    Arena arena;
+    mcrng_ctx ctx;      // host tables of the last run; every buffer is carved from `arena`
+};
+static std::mutex g_static_mu;
+static std::map<int, StaticDevice*> g_static;   // per device, kept for the process (like the array)
+
+// The device's static state; on the first call for a device (the current
+// one) takes the array's address there.
+static int static_device(int dev, StaticDevice** out) {
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    auto it = g_static.find(dev);
+    if (it != g_static.end()) {
+        *out = it->second;
+        return MCRNG_OK;
+    }
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr)
+        return fail(MCRNG_EDEVICE, "static scratch address on device %d: %s", dev, hipGetErrorString(e));
+    StaticDevice* d = new (std::nothrow) StaticDevice();
+    if (!d) return fail(MCRNG_ENOMEM, "static state");
+    d->arena.base = static_cast<char*>(ptr);
+    d->arena.cap = kStaticScratchBytes;
+    d->ctx.device = dev;
+    d->ctx.arena = &d->arena;
+    DevBuf* bufs[] = {&d->ctx.problems, &d->ctx.edges64, &d->ctx.sig64, &d->ctx.scat64, &d->ctx.cbin,
+                      &d->ctx.edges32, &d->ctx.sig32, &d->ctx.tedges64, &d->ctx.tedges32, &d->ctx.units,
+                      &d->ctx.order, &d->ctx.partial, &d->ctx.unit_diag, &d->ctx.counter, &d->ctx.groups,
+                      &d->ctx.dx, &d->ctx.dt, &d->ctx.pu_begin, &d->ctx.rec_begin};
+    for (DevBuf* b : bufs) b->arena = &d->arena;
+    g_static[dev] = d;
+    *out = d;
+    return MCRNG_OK;
+}
+
+extern "C" int mcrng_run_histories_noalloc(const mcrng_lcg* lcg, const mcrng_problem* problems, uint32_t n_problems,
+                                           const mcrng_run_opts* opts, uint64_t* d_raw, double* d_flux,
+                                           uint64_t* d_diag, void* stream) {
+    if (!problems) return fail(MCRNG_EINVAL, "problems is NULL");
+    if (n_problems == 0) return fail(MCRNG_EINVAL, "n_problems must be >= 1");
+    if (!d_raw || !d_flux) return fail(MCRNG_EINVAL, "d_raw and d_flux are required");
+    LcgDev L;
+    int rc = validate_lcg(lcg, 53, &L);
+    if (rc < 0) return rc;
+    mcrng_run_opts o;
+    if ((rc = normalise_opts(opts, &o)) < 0) return rc;
+    if (o.schedule != MCRNG_SCHED_HISTORY) return fail(MCRNG_EINVAL, "the allocation-free run has the history schedule only");
+    if (o.use_graph) return fail(MCRNG_EINVAL, "the allocation-free run does not capture graphs");
+    for (uint32_t i = 0; i < n_problems; ++i)
+        if ((rc = validate_problem(problems[i], i)) < 0) return rc;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    StaticDevice* sd = nullptr;
+    if ((rc = static_device(dev, &sd)) < 0) return rc;
+    std::lock_guard<std::mutex> lk(sd->mu);
+    mcrng_ctx* ctx = &sd->ctx;
+    sd->arena.reset();
+    DevBuf* bufs[] = {&ctx->problems, &ctx->edges64, &ctx->sig64, &ctx->scat64, &ctx->cbin, &ctx->edges32,
+                      &ctx->sig32, &ctx->tedges64, &ctx->tedges32, &ctx->units, &ctx->order, &ctx->partial,
+                      &ctx->unit_diag, &ctx->counter, &ctx->groups, &ctx->dx, &ctx->dt, &ctx->pu_begin,
+                      &ctx->rec_begin};
+    for (DevBuf* b : bufs) {
+        b->p = nullptr;
+        b->cap = 0;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    o.unit_histories = o.unit_histories ? o.unit_histories : default_unit_histories(problems, n_problems);
+    int warn = MCRNG_OK;
+    if ((rc = build_tables(ctx, L, problems, n_problems, o.unit_histories, st, &warn)) < 0) return rc;
+    if ((rc = enqueue_run(ctx, L, o, st)) < 0) return rc;
+    if ((rc = enqueue_reduce(ctx, d_raw, d_flux, d_diag, st)) < 0) return rc;
+    return warn;
 }
 
 // ------------------------------------------------------------------ autotuner

@@ -95,6 +95,33 @@ def test_autotune_host_validation_without_gpu(M):
     assert rc == B.EINVAL and "n_regions" in msg
 
 
+def test_noalloc_host_validation_without_gpu(M):
+    """mcrng_run_histories_noalloc rejects bad arguments and the options it
+    does not support before any HIP call."""
+    import workloads as W
+    from paper_2403_06362_amd import _binding as B
+    lib = M.lib()
+    L = B.make_lcg(W.Lcg())
+    arr, keep = B.make_problems([W.small_slab(n_histories=100)])
+    out = C.c_void_p(16)   # never dereferenced: validation fails first
+
+    def call(lcg, probs, n, opts=None, raw=out, flux=out):
+        rc = lib.mcrng_run_histories_noalloc(lcg, probs, n, opts, raw, flux, None, None)
+        return rc, lib.mcrng_last_error().decode()
+
+    assert call(None, arr, 1)[0] == B.EINVAL
+    assert call(C.byref(L), None, 1)[0] == B.EINVAL
+    assert call(C.byref(L), arr, 0)[0] == B.EINVAL
+    assert call(C.byref(L), arr, 1, raw=None)[0] == B.EINVAL
+    assert call(C.byref(L), arr, 1, flux=None)[0] == B.EINVAL
+    rc, msg = call(C.byref(L), arr, 1, C.byref(B.make_opts(schedule=1)))
+    assert rc == B.EINVAL and "history schedule" in msg
+    rc, msg = call(C.byref(L), arr, 1, C.byref(B.make_opts(use_graph=1)))
+    assert rc == B.EINVAL and "graph" in msg
+    rc, msg = call(C.byref(L), arr, 1, C.byref(B.make_opts(hist_per_lane=3)))
+    assert rc == B.EINVAL and "hist_per_lane" in msg
+
+
 def test_tally_bins_host_only(M):
     import workloads as W
     probs = [W.small_slab(), W.long_chain(n_histories=10), W.multi_region(n_histories=10)]
