@@ -294,8 +294,14 @@ double orc_ln(double u)
  * because s < 2^7 is enforced by the caller) and summed exactly as a
  * 128-bit integer.  The flux of a bin is (sum q) 2^-56 / (N dx [dt]).
  *
- * FP32 flight mode: tau is computed in double by orc_ln and rounded once
- * to float; mu = 2 u2 - 1 is computed in double (exact) and rounded once
+ * FP32 flight mode: the remaining optical depth tau (the -ln(u) sample the
+ * flight consumes) stays in double: it is orc_ln's result, each event
+ * subtracts the product (double)sigma_t x (double)s of two floats (exact)
+ * and clamps at 0, and the collision distance is (float)tau / sigma_t in
+ * single precision (a float tau would lose absolute precision over the
+ * many subtractions of a flight through thin cells, and the last segment,
+ * the small remainder, would carry that error relative to its own length);
+ * mu = 2 u2 - 1 is computed in double (exact) and rounded once
  * to float; the position is kept relative to the current cell's left edge
  * (xl in [0, W[cell]]) and the time relative to the current time bin's
  * start (tl in [0, DT[tb]]), so FP32 keeps its relative precision deep in a
@@ -458,10 +464,10 @@ static void history_f32(const orc_problem *P, const float *W, const float *SG, c
     const int timed = nt > 0;
     float xl = 0.0f, mu = 1.0f, tl = 0.0f;   /* position in the cell, time in the time bin */
     int cell = 0, tb = 0;
-    float tau = (float)(-orc_ln(rng_draw(R)));
+    double tau = -orc_ln(rng_draw(R));   /* the remaining optical depth stays double */
     for (;;) {
         const float sig = SG[cell], w = W[cell];
-        float s = tau / sig;
+        float s = (float)tau / sig;
         int ev = EV_COLL;
         float se;
         if (mu > 0.0f)
@@ -482,9 +488,9 @@ static void history_f32(const orc_problem *P, const float *W, const float *SG, c
             tl = tl + s;
             if (tl > DT[tb]) tl = DT[tb];
         }
-        float dtau = sig * s;
+        double dtau = (double)sig * (double)s;   /* exact: a product of two floats */
         tau = tau - dtau;
-        if (tau < 0.0f) tau = 0.0f;
+        if (tau < 0.0) tau = 0.0;
         if (ev == EV_EDGE) {
             if (mu > 0.0f) {
                 cell = cell + 1;
@@ -514,7 +520,7 @@ static void history_f32(const orc_problem *P, const float *W, const float *SG, c
         double u2 = rng_draw(R);
         mu = (float)(2.0 * u2 - 1.0);
         double u3 = rng_draw(R);
-        tau = (float)(-orc_ln(u3));
+        tau = -orc_ln(u3);
     }
 }
 

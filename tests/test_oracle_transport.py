@@ -121,21 +121,25 @@ def test_scripted_regions_change_cross_section(orc):
 
 def test_scripted_float_mode(orc):
     """FP32 flight: position relative to the cell's left edge, every
-    operation a single-precision one, widths rounded once from doubles."""
-    p = slab([0, 10], [1.0], [0.5], [0, 3.3, 10])
-    raw, d, ev, used = orc.transport_scripted(p, LCG, [2.0 ** -5, 0.25, 0.125, 0.5, 0.75], float_mode=True)
+    distance, position and time operation a single-precision one, widths
+    rounded once from doubles; the remaining optical depth stays double and
+    is consumed by the exact double product of sigma_t and the float track."""
+    p = slab([0, 10], [1.3], [0.5], [0, 3.3, 10])
+    raw, d, ev, used = orc.transport_scripted(p, LCG, [2.0 ** -7, 0.25, 0.125, 0.25, 0.75], float_mode=True)
     f = np.float32
-    W0, W1 = f(3.3 - 0.0), f(10.0 - 3.3)
-    tau = f(-orc.ln(2.0 ** -5))
-    s1 = f(f(W0 - f(0)) / f(1))                 # edge of cell 0 (tau > 3.3)
-    tau = f(tau - f(f(1) * s1))
-    s2 = f(tau / f(1))                          # collision in cell 1, local position s2
+    W0, W1, S = f(3.3 - 0.0), f(10.0 - 3.3), f(1.3)
+    tau = -orc.ln(2.0 ** -7)                    # double: 4.85..., above 1.3 x 3.3
+    s1 = f(f(W0 - f(0)) / f(1))                 # edge of cell 0
+    assert f(f(tau) / S) > s1
+    tau = tau - float(S) * float(s1)            # exact product, one double subtraction
+    s2 = f(f(tau) / S)                          # collision in cell 1, local position s2
     xl = f(f(0) + f(f(1) * s2))
     mu = f(2.0 * 0.125 - 1.0)
-    tau = f(-orc.ln(0.5))
+    tau = -orc.ln(0.25)
     s3 = f(f(f(0) - xl) / mu)                   # back to the edge at 3.3
-    tau = f(tau - f(f(1) * s3))
-    s4 = f(tau / f(1))                          # collision in cell 0, then absorbed
+    assert f(f(tau) / S) > s3
+    tau = tau - float(S) * float(s3)
+    s4 = f(f(tau) / S)                          # collision in cell 0, then absorbed
     assert used == 5 and d["absorbed"] == 1
     assert [e[0] for e in ev] == [1, 0, 1, 0] and [e[1] for e in ev] == [0, 1, 1, 0]
     assert [e[3] for e in ev] == [float(s1), float(s2), float(s3), float(s4)]
