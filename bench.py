@@ -31,13 +31,27 @@ Also reported, each timed separately after the headline loop:
                 run: time, agreement, figure of merit per time bin
   roofline      of the draw kernel: integer VALU lane-ops per launch over the
                 average kernel duration (HIP events on the launch stream)
-  cpu_baseline  the CPU oracle on the host cores: the same draw workload,
-                256 sampled streams of the GPU checksums recomputed, and
-                64-batch samples of the pulse problems (the only part of
-                the benchmark that uses the oracle)
-With --full, the 512-problem batched set (persistent + graph, FP64 and
-FP32, against one launch per problem) and the 2e8-history multi-region
-slab are added.
+  batched       512 slabs (seed 7, 5.4e8 histories): one persistent launch
+                replayed from a captured hipGraph with autotuned options, FP64
+                and FP32-flight, against one run per problem in FP64; the
+                FP32 flux error against FP64 per bin, per problem and
+                integrated
+  multi_region  the 2e8-history 10-region time-dependent slab: history
+                schedule FP64 and FP32, event-sorted FP64 (bit-identical)
+  transport.roofline, pulse.roofline
+                algorithmic VALU lane-operations (counted per event,
+                collision and history, or per flight, from the operation
+                sequence) over the kernel time (HIP events on the launch
+                stream) against the 39.3e12 lane-op/s VALU peak
+  cpu_baseline  the CPU oracle on the host cores (at most 16 threads, the
+                CPU share of one GPU): the whole draw workload for both
+                seedings, every GPU checksum compared with the oracle's;
+                single-thread and all-thread rates for draws, the
+                long-chain and the multi-region slabs (bounded samples), and
+                samples of the pulse problems (the only part of the
+                benchmark that uses the oracle)
+With --full, the slower extras are added (the pulse event-based schedule on
+few sources; nothing the headline or the rooflines depend on).
 
 Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 10] [--full] [--no-cpu]
                        [--no-transport] [--no-pulse] [--no-autotune] [--copy-probe]
@@ -70,10 +84,48 @@ INT_VALU_PEAK = 256 * 4 * 16 * 2.4e9
 OPS_PER_DRAW = 6
 OPS_PER_HASH_SEED = 16
 OPS_PER_STRIDE_SEED = 6
+# Slab transport, algorithmic VALU lane-operations (the derivation, operation
+# by operation, is in the design notes' kernel table):
+#   per geometry step (event), FP64, steady: collision distance through the
+#     cell's refined reciprocal 3, edge choice by direction 3, numerator 1,
+#     edge distance through the flight's reciprocal 3, strict choice 4,
+#     quantisation into two 32-bit words 7, tally address 1, optical depth
+#     with its clamp 3, move (snap and cell step, or x + mu s and clamps) 4
+#   time-dependent: time-edge distance and choice 6, time update 2
+#   per collision: LCG step 5, uniform 6, absorption compare 1
+#   per scatter: LCG step 5 + uniform 6 for the direction, mu = 2u - 1 2,
+#     its refined reciprocal and zero flag 7; the next flight: LCG step 5,
+#     uniform 6, logarithm 48 (exponent split 4, reduction 4, a and 2 + a 2,
+#     division 8, square 1, degree-10 polynomial 20, the rearranged terms 4,
+#     exponent conversion 1, ln 2 terms 4)
+#   per history: its stream's start (hash 16 / stride 6), source set-up 6 and
+#     its first flight (5 + 6 + 48)
+OPS_EVENT = 29
+OPS_EVENT_TIMED_EXTRA = 8
+OPS_COLLISION = 12
+OPS_SCATTER = 5 + 6 + 2 + 7 + 5 + 6 + 48
+OPS_HISTORY_HASH = 16 + 6 + 5 + 6 + 48
+# Pulse problem, per particle flight: direction (LCG 5, uniform 6, 2u - 1 2),
+# flight (LCG 5, uniform 6, logarithm 48, distance through the medium's
+# reciprocal 3), census test 2, move x and t 3, collision-estimator window
+# and time-bin test 5; per collision: absorption draw and compare 12; per
+# scatter: multiplicity draw and count 13; per secondary: its seed (hash of
+# the order number and the parent's state) 17
+OPS_FLIGHT = 13 + 62 + 2 + 3 + 5
+OPS_PULSE_COLLISION = 12
+OPS_PULSE_SCATTER = 13
+OPS_SECONDARY_HASH = 17
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def host_threads(cap=16):
+    """Oracle worker threads: the host cores this process may use, at most
+    `cap` (the CPU share of one GPU on a shared node)."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return max(1, min(cap, n))
 
 
 def draw_workload(M, W, torch, dev, kind, steps, warmup, d_count, n, total_draws, lcg):
@@ -157,17 +209,6 @@ def uniforms_leg(M, W, torch, dev, lcg, n, k, warmup, reps):
     return out
 
 
-def spot_check(oracle, W, lcg, kind, counts, chk_np, k=256):
-    sd = W.hash_seeding() if kind == "hash" else W.stride_seeding()
-    rng = np.random.default_rng(123)
-    for i in rng.integers(0, counts.size, k):
-        i = int(i)
-        one = oracle.seed_and_draw(lcg, W.Seeding(sd.kind, sd.base, sd.stride, i), counts[i:i + 1])
-        if int(one[0]) != int(chk_np[i]):
-            return False
-    return True
-
-
 def traffic_from_profiles(kernel_src_sha):
     """HBM bytes per launch measured with rocprofv3 --pmc (FETCH_SIZE, then
     WRITE_SIZE), scaled by a copy kernel of known size; None if absent or
@@ -212,6 +253,45 @@ def transport_leg(M, W, torch, lcg, ctx, prob, opts, reps=2):
             "flux": flux.cpu().numpy(), "diag": dd}
 
 
+def transport_ops(diag, timed=False, seeding="hash"):
+    """Algorithmic VALU lane-operations of a run, from its diagnostics."""
+    scat = diag["collisions"] - diag["absorbed"]
+    per_hist = OPS_HISTORY_HASH - (0 if seeding == "hash" else OPS_PER_HASH_SEED - OPS_PER_STRIDE_SEED)
+    ev = OPS_EVENT + (OPS_EVENT_TIMED_EXTRA if timed else 0)
+    return ev * diag["events"] + OPS_COLLISION * diag["collisions"] + OPS_SCATTER * scat + per_hist * diag["histories"]
+
+
+def valu_roofline(ops, ms, kernel, unit_counts):
+    a = ops / (ms * 1e-3)
+    return {"bound": "alu", "achieved": a / 1e12, "peak": INT_VALU_PEAK / 1e12,
+            "unit": "Tera VALU lane-ops/s", "frac": a / INT_VALU_PEAK, "traffic": None, "kernel": kernel,
+            "algorithmic_ops_per_launch": int(ops), "kernel_ms": ms, "counts": unit_counts}
+
+
+def flux_errors(f32, f64, sizes):
+    """FP32-flight flux against FP64, per problem (sizes = bins of each):
+    per-problem L1 (sum |d| / sum f64), integrated (|sum d| / sum f64), and
+    per-bin relative error on the bins holding at least 1e-3 of their
+    problem's largest bin."""
+    l1, integ, binmax, off = [], [], [], 0
+    for n in sizes:
+        a, b = f32[off:off + n], f64[off:off + n]
+        off += n
+        tot = b.sum()
+        if tot <= 0:
+            continue
+        d = a - b
+        l1.append(float(np.abs(d).sum() / tot))
+        integ.append(float(abs(d.sum()) / tot))
+        m = b >= 1e-3 * b.max()
+        binmax.append(float((np.abs(d[m]) / b[m]).max()))
+    l1, integ, binmax = np.array(l1), np.array(integ), np.array(binmax)
+    return {"per_problem_l1_max": float(l1.max()), "per_problem_l1_median": float(np.median(l1)),
+            "problems_l1_above_1e-6": int(np.sum(l1 > 1e-6)), "problems": int(l1.size),
+            "integrated_max": float(integ.max()), "integrated_median": float(np.median(integ)),
+            "per_bin_max_on_bins_ge_1e-3_of_max": float(binmax.max())}
+
+
 def fp32_error(f32, f64, prob):
     """Per-bin error of the FP32-flight flux against the FP64 flux (the
     batch-mean flux over all 1e8 histories), relative and in units of the
@@ -252,10 +332,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--full", action="store_true", help="add the batched and multi-region legs")
+    ap.add_argument("--full", action="store_true", help="add the slower extras (few-source event-based pulse runs)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-transport", action="store_true", help="headline draw workload only")
+    ap.add_argument("--no-transport", action="store_true", help="headline draw workload only (no slab or pulse legs)")
     ap.add_argument("--no-pulse", action="store_true", help="skip the pulse-problem legs")
+    ap.add_argument("--no-slab", action="store_true", help="skip the slab legs (long chain, batched, multi-region)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="long-chain legs with the default launch options (no autotuner runs)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -351,6 +432,7 @@ def main():
 
     if not args.no_transport:
         ctx = M.Context(0)
+    if not args.no_transport and not args.no_slab:
         prob = W.long_chain()
         # launch options from the library's autotuner, once per precision on
         # the hash-seeded problem (the stride leg reuses the FP64 choice)
@@ -377,14 +459,20 @@ def main():
             "stride_fp64": normality(legs["stride_fp64"]["flux"], prob)}
         tr["fp32_speedup"] = legs["hash_fp64"]["ms"] / legs["hash_fp32"]["ms"]
         tr["hash_over_stride"] = legs["stride_fp64"]["ms"] / legs["hash_fp64"]["ms"]
+        d64 = legs["hash_fp64"]["diag"]
+        tr["roofline"] = valu_roofline(transport_ops(d64), legs["hash_fp64"]["ms"], "k_transport<fp64> (history)",
+                                       {k: d64[k] for k in ("histories", "events", "collisions", "absorbed")})
+        d32 = legs["hash_fp32"]["diag"]
+        tr["roofline_fp32"] = valu_roofline(transport_ops(d32), legs["hash_fp32"]["ms"], "k_transport<fp32> (history)",
+                                            {k: d32[k] for k in ("histories", "events", "collisions", "absorbed")})
         out["histories_per_s"] = legs["hash_fp64"]["histories_per_s"]
         out["transport"] = tr
-        if not args.no_pulse:
-            out["pulse"] = pulse_leg(M, W, torch, lcg, ctx)
-            out["pulse_population_control"] = pulse_pc_leg(M, W, torch, lcg, ctx)
-        if args.full:
-            out["batched"] = batched_leg(M, W, torch, lcg, ctx)
-            out["multi_region"] = multi_region_leg(M, W, torch, lcg, ctx)
+        out["batched"] = batched_leg(M, W, torch, lcg, ctx, args.no_autotune)
+        out["multi_region"] = multi_region_leg(M, W, torch, lcg, ctx)
+    if not args.no_transport and not args.no_pulse:
+        out["pulse"] = pulse_leg(M, W, torch, lcg, ctx, args.full)
+        out["pulse_population_control"] = pulse_pc_leg(M, W, torch, lcg, ctx)
+    if not args.no_transport:
         ctx.close()
 
     if not args.no_cpu:
@@ -395,11 +483,12 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def batched_leg(M, W, torch, lcg, ctx):
+def batched_leg(M, W, torch, lcg, ctx, no_autotune=False):
     """512 slabs.  Baseline: the plain FP64 per-problem form, one run (and
     reduce) per problem.  Against it: every problem in one persistent launch
     replayed from a captured hipGraph, launch options from the autotuner,
-    in FP64 (bit-identical to the baseline) and FP32-flight."""
+    in FP64 (bit-identical to the baseline) and FP32-flight (its flux error
+    against the FP64 flux per problem and per bin)."""
     import paper_2403_06362_amd as P
     probs = W.batched()
     ntot = sum(p.n_histories for p in probs)
@@ -424,38 +513,36 @@ def batched_leg(M, W, torch, lcg, ctx):
     tot = P.tally_bins(probs)
     raw = torch.empty((tot, 2), dtype=torch.uint64, device="cuda:0")
     flux = torch.empty(tot, dtype=torch.float64, device="cuda:0")
+    diag = torch.empty((len(probs), P.NDIAG), dtype=torch.uint64, device="cuda:0")
     for name, prec in (("fp64", 0), ("fp32", 1)):
-        log("batched: autotune", name)
-        best, _ = ctx.autotune(lcg, probs, M.make_opts(precision=prec))
+        if no_autotune:
+            best = M.make_opts(precision=prec)
+        else:
+            log("batched: autotune", name)
+            best, _ = ctx.autotune(lcg, probs, M.make_opts(precision=prec))
         best.use_graph = 1
         ctx.run_histories(lcg, probs, best)
-        ctx.reduce_tallies(raw, flux)
+        ctx.reduce_tallies(raw, flux, diag)
         torch.cuda.synchronize()
-        times = []
+        times, kms = [], []
         for _ in range(3):
             t0 = time.perf_counter()
             ctx.run_histories(lcg, probs, best)
-            ctx.reduce_tallies(raw, flux)
+            ctx.reduce_tallies(raw, flux, diag)
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
+            kms.append(ctx.last_run_ms())
         sec = float(np.median(times))
-        leg = {"s": sec, "kernel_ms": ctx.last_run_ms(), "opts": best.as_dict(), "histories_per_s": ntot / sec,
+        leg = {"s": sec, "kernel_ms": float(np.median(kms)), "opts": best.as_dict(), "histories_per_s": ntot / sec,
                "speedup_over_per_problem_fp64": per_problem_s / sec}
+        dg = diag.view(torch.int64).cpu().numpy().view(np.uint64).reshape(len(probs), P.NDIAG)
+        dd = {k: int(dg[:, i].sum()) for i, k in enumerate(P.DIAG_NAMES) if k != "max_draws"}
+        leg["roofline"] = valu_roofline(transport_ops(dd), leg["kernel_ms"], "k_transport<%s> (512 problems)" % name,
+                                        {k: dd[k] for k in ("histories", "events", "collisions", "absorbed")})
         if prec == 0:
             leg["bit_identical_to_per_problem"] = bool(np.array_equal(raw.view(torch.int64).cpu().numpy(), ref_raw))
         else:
-            f = flux.cpu().numpy()
-            m = ref_flux > 0
-            rel = np.abs(f[m] - ref_flux[m]) / ref_flux[m]
-            l1, off = [], 0
-            for b in nb:
-                a, r = f[off:off + b], ref_flux[off:off + b]
-                l1.append(float(np.abs(a - r).sum() / r.sum()) if r.sum() > 0 else 0.0)
-                off += b
-            leg["flux_rel_err_vs_fp64"] = {
-                "per_bin_max": float(rel.max()), "per_bin_rms": float(np.sqrt(np.mean(rel ** 2))),
-                "bins_above_1e-6": float(np.mean(rel > 1e-6)),
-                "per_problem_l1_max": float(max(l1)), "per_problem_l1_median": float(np.median(l1))}
+            leg["flux_error_vs_fp64"] = flux_errors(flux.cpu().numpy(), ref_flux, nb)
         res["persistent_graph_" + name] = leg
     return res
 
@@ -463,18 +550,20 @@ def batched_leg(M, W, torch, lcg, ctx):
 def multi_region_leg(M, W, torch, lcg, ctx):
     prob = W.multi_region()
     res = {"workload": "10-region slab (seed 11), 50x20 space-time bins, 2e8 histories, hash"}
+    flux, diag = {}, {}
     for name, opts in (("history_fp64", M.make_opts()), ("history_fp32", M.make_opts(precision=1)),
                        ("event_sorted_fp64", M.make_opts(schedule=1))):
         log("multi region", name)
-        r = transport_leg(M, W, torch, lcg, ctx, prob, opts, reps=1)
+        r = transport_leg(M, W, torch, lcg, ctx, prob, opts, reps=2)
         res[name] = {k: v for k, v in r.items() if k not in ("flux", "diag")}
-        res[name]["_flux"] = r["flux"]
-    res["event_sorted_equals_history"] = bool(np.array_equal(res["event_sorted_fp64"].pop("_flux"),
-                                                             res["history_fp64"]["_flux"]))
-    f32, f64 = res["history_fp32"].pop("_flux"), res["history_fp64"].pop("_flux")
-    m = f64 > 0
-    rel = np.abs(f32[m] - f64[m]) / f64[m]
-    res["fp32_vs_fp64_flux_rel_err"] = {"max": float(rel.max()), "rms": float(np.sqrt(np.mean(rel ** 2)))}
+        flux[name], diag[name] = r["flux"], r["diag"]
+    res["event_sorted_equals_history"] = bool(np.array_equal(flux["event_sorted_fp64"], flux["history_fp64"]))
+    res["fp32_error_vs_fp64"] = flux_errors(flux["history_fp32"], flux["history_fp64"], [flux["history_fp64"].size])
+    res["fp32_speedup"] = res["history_fp64"]["ms"] / res["history_fp32"]["ms"]
+    d = diag["history_fp64"]
+    res["roofline"] = valu_roofline(transport_ops(d, timed=True), res["history_fp64"]["ms"],
+                                    "k_transport<fp64, timed> (history)",
+                                    {k: d[k] for k in ("histories", "events", "collisions", "absorbed")})
     return res
 
 
@@ -548,7 +637,7 @@ def pulse_pc_leg(M, W, torch, lcg, ctx):
     return out
 
 
-def pulse_leg(M, W, torch, lcg, ctx):
+def pulse_leg(M, W, torch, lcg, ctx, full=False):
     """The paper's test problem: a pulse in an infinite medium (c = 0.4,
     nu = 2.75, census t = 20), 1000 batches x 1000 sources; secondaries
     seeded on demand by hashing (eq. 5) or drawing from their source's
@@ -593,46 +682,79 @@ def pulse_leg(M, W, torch, lcg, ctx):
                        "fail_p_lt_0.05": int(np.sum(pv < 0.05)),
                        "median_p_per_time_bin": [float(v) for v in np.median(pv, axis=0)],
                        "over_stride_families": d["over_stride"], "max_draws": d["max_draws"]}
+        if kind == "hash":
+            flights = d["sources"] + d["secondaries"]
+            ops = (OPS_FLIGHT * flights + OPS_PULSE_COLLISION * d["collisions"] + OPS_PULSE_SCATTER * d["scatters"]
+                   + OPS_SECONDARY_HASH * d["secondaries"] + OPS_PER_HASH_SEED * d["sources"])
+            out["roofline"] = valu_roofline(ops, ms, "k_pulse_family (3e7-source study, hash)",
+                                            {"flights": flights, "collisions": d["collisions"],
+                                             "scatters": d["scatters"], "secondaries": d["secondaries"]})
     study["paper_fails_of_600"] = {"stride": 369, "hash": 339}
     out["normality_study"] = study
     return out
 
 
+def _rate(fn, units):
+    t0 = time.perf_counter()
+    fn()
+    dt = time.perf_counter() - t0
+    return units / dt, dt
+
+
 def cpu_baseline(oracle, W, lcg, counts, chk_hash, chk_stride, out):
-    """The CPU oracle on the host cores: the headline draw workload (timed),
-    sampled streams of the GPU's checksums recomputed, and bounded samples
-    of the pulse problems (timed, beside the GPU's rates)."""
-    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    threads = max(1, min(threads, 16))
-    ok_h = spot_check(oracle, W, lcg, "hash", counts, chk_hash)
-    ok_s = spot_check(oracle, W, lcg, "stride", counts, chk_stride)
+    """The CPU oracle on the host cores: the whole headline draw workload for
+    both seedings (timed for hash; every GPU checksum compared with the
+    oracle's), single-thread draw, long-chain and multi-region rates on
+    bounded samples, all-thread rates beside them, and bounded samples of
+    the pulse problems."""
+    threads = host_threads()
     ns = counts.size
-    sample = counts[:ns]
-    draws = int(sample.sum(dtype=np.uint64))
+    draws = int(counts.sum(dtype=np.uint64))
     log("cpu baseline: oracle seed+draw on %d streams, %d threads, 3 passes" % (ns, threads))
-    walls = []
+    walls, ref = [], None
     for _ in range(3):
         t0 = time.perf_counter()
-        oracle.seed_and_draw(lcg, W.hash_seeding(), sample, threads=threads)
+        r = oracle.seed_and_draw(lcg, W.hash_seeding(), counts, threads=threads)
         walls.append(time.perf_counter() - t0)
+        if ref is None:
+            ref = r
     dt = float(np.median(walls))
+    mism_h = int(np.count_nonzero(ref != chk_hash))
+    log("cpu baseline: oracle seed+draw, stride seeding, whole workload")
+    ref_s = oracle.seed_and_draw(lcg, W.stride_seeding(), counts, threads=threads)
+    mism_s = int(np.count_nonzero(ref_s != chk_stride))
+    one = 1 << 21
+    r1, _ = _rate(lambda: oracle.seed_and_draw(lcg, W.hash_seeding(), counts[:one], threads=1),
+                  int(counts[:one].sum(dtype=np.uint64)))
     res = {"value": draws / dt, "unit": "draws/s", "cores": threads, "kind": "oracle",
-           "sample": "the whole workload (%d streams, %d draws), hash seeding, 3 passes, median %.2f s wall "
-                     "(%.0f s of CPU work in total)" % (ns, draws, dt, sum(walls) * threads),
-           "gpu_checksums_match_on_256_sampled_streams": {"hash": ok_h, "stride": ok_s}}
+           "sample": "the whole workload (%d streams, %d draws), hash seeding, %d threads, 3 passes, median %.2f s "
+                     "wall" % (ns, draws, threads, dt),
+           "nproc": os.cpu_count(), "threads_used": threads,
+           "single_thread_draws_per_s": r1, "single_thread_sample": "first 2^21 streams of the workload",
+           "gpu_checksum_mismatches_of_%d" % ns: {"hash": mism_h, "stride": mism_s}}
+    if "transport" in out:
+        tr = {}
+        for name, make, n1, nall in (("long_chain", lambda n: W.long_chain(n_histories=n), 100_000, 1_000_000),
+                                     ("multi_region", lambda n: W.multi_region(n_histories=n), 500_000, 4_000_000)):
+            log("cpu baseline: oracle", name)
+            p1, pa = make(n1), make(nall)
+            h1, _ = _rate(lambda: oracle.transport(p1, lcg, threads=1), n1)
+            ha, _ = _rate(lambda: oracle.transport(pa, lcg, threads=threads), nall)
+            gpu = out["transport"]["hash_fp64"]["histories_per_s"] if name == "long_chain" else \
+                out["multi_region"]["history_fp64"]["histories_per_s"]
+            tr[name] = {"single_thread_histories_per_s": h1, "single_thread_sample": "first %d histories" % n1,
+                        "all_threads_histories_per_s": ha, "threads": threads,
+                        "all_threads_sample": "first %d histories" % nall, "gpu_over_all_threads": gpu / ha}
+        res["transport"] = tr
     if "pulse" in out:
         sample = W.pulse(W.hash_seeding(), n_batches=64)
         log("cpu baseline: oracle pulse problem, 64 batches")
-        t0 = time.perf_counter()
-        oracle.pulse(sample, lcg, threads=threads)
-        rate = sample.n_sources / (time.perf_counter() - t0)
+        rate, _ = _rate(lambda: oracle.pulse(sample, lcg, threads=threads), sample.n_sources)
         res["pulse"] = {"sources_per_s": rate, "threads": threads, "sample": "64 batches x 1000 sources, hash seeding",
                         "gpu_bank_over_cpu": out["pulse"]["hash_bank"]["sources_per_s"] / rate}
         sample = W.pulse_pc(n_batches=64, census_every=5)
         log("cpu baseline: oracle pulse problem with population control, 64 batches")
-        t0 = time.perf_counter()
-        oracle.pulse_pc(sample, lcg, threads=threads)
-        rate = sample.n_sources / (time.perf_counter() - t0)
+        rate, _ = _rate(lambda: oracle.pulse_pc(sample, lcg, threads=threads), sample.n_sources)
         res["pulse_population_control"] = {
             "sources_per_s": rate, "threads": threads, "sample": "64 batches x 1000 sources, census every 5",
             "gpu_over_cpu": out["pulse_population_control"]["sources_per_s"] / rate}

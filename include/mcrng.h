@@ -117,8 +117,8 @@ int mcrng_uniforms(const mcrng_lcg *lcg, const mcrng_seeding *seeding, uint64_t 
  * region and bin edges.  History j (0-based) uses stream j of `seeding`
  * and belongs to batch floor(j / ceil(n_histories / n_batches)).
  * Host arrays:
- *   region_edges  n_regions + 1, strictly increasing
- *   sigma_t       n_regions, > 0 (total cross section)
+ *   region_edges  n_regions + 1, strictly increasing, within [-2^40, 2^40]
+ *   sigma_t       n_regions, in [2^-64, 2^64] (total cross section)
  *   scatter       n_regions, in [0, 1] (scattering ratio c)
  *   bin_edges     n_space_bins + 1, strictly increasing, same first and
  *                 last value as region_edges
@@ -162,10 +162,11 @@ enum { MCRNG_SCHED_HISTORY = 0, MCRNG_SCHED_EVENT = 1 };
  *   use_graph       1 = capture the launches of a run in a hipGraph once
  *                   per (problem set, options) and replay it
  *   bank_size       event schedule: particles per bank slice
- *   coll_batch      history schedule: a wave runs its collision phase
- *                   (absorption draw, new direction, next flight) once this
- *                   many of its lanes wait at a collision site (1..64 per
- *                   history slot; default 24 in FP64, 32 in FP32) */
+ *   coll_batch      history schedule: a wave runs its collision pass
+ *                   (absorption draw, new direction, next flight; empty
+ *                   lanes take new histories) once this many of its lanes
+ *                   wait at a collision site or stand empty (1..64 per
+ *                   history slot; default 36) */
 typedef struct {
     uint32_t precision;
     uint32_t schedule;

@@ -186,6 +186,56 @@ static int get_stride_table(const LcgDev& L, uint64_t Q, const uint64_t** out, A
     return MCRNG_OK;
 }
 
+// Round-alignment tables of the draw kernel, one per (device, g, c, round
+// length D), for m = 63 and 64 and odd g (AlignEntry in internal.hpp): the
+// inverse step Y -> g^-1 (Y - c) modulo 2^64 applied h times, and minus the
+// sum of the states it passes.
+struct AlignKey {
+    int dev;
+    uint64_t g, c;
+    int d;
+    bool operator<(const AlignKey& o) const {
+        if (dev != o.dev) return dev < o.dev;
+        if (g != o.g) return g < o.g;
+        if (c != o.c) return c < o.c;
+        return d < o.d;
+    }
+};
+static std::map<AlignKey, AlignEntry*> g_align;
+
+static int get_align_table(const LcgDev& L, int D, const AlignEntry** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    AlignKey key{dev, L.g, L.c, D};
+    std::lock_guard<std::mutex> lk(g_table_mu);
+    auto it = g_align.find(key);
+    if (it != g_align.end()) {
+        *out = it->second;
+        return MCRNG_OK;
+    }
+    uint64_t gi = L.g;   // g^-1 modulo 2^64 by Newton's iteration (3 correct bits, doubling)
+    for (int k = 0; k < 5; ++k) gi *= 2ull - L.g * gi;
+    std::vector<AlignEntry> h(kMaxRound);
+    uint64_t a = 1, b = 0, sa = 0, sb = 0;   // rewind of h steps, and the sums of the first h of them
+    for (int k = 0; k < kMaxRound; ++k) {
+        h[k] = AlignEntry{a, b, 0ull - sa, 0ull - sb};
+        sa += a;
+        sb += b;
+        a = gi * a;
+        b = gi * b - gi * L.c;
+    }
+    AlignEntry* d_tab = nullptr;
+    HIP_TRY(hipMalloc(&d_tab, h.size() * sizeof(AlignEntry)));
+    hipError_t e = hipMemcpy(d_tab, h.data(), h.size() * sizeof(AlignEntry), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d_tab);
+        return fail(MCRNG_EDEVICE, "alignment table upload: %s", hipGetErrorString(e));
+    }
+    g_align[key] = d_tab;
+    *out = d_tab;
+    return MCRNG_OK;
+}
+
 static uint32_t hex_digits(uint64_t v) {
     uint32_t d = 0;
     while (v) {
@@ -263,9 +313,16 @@ extern "C" int mcrng_draw(const mcrng_lcg* lcg, const mcrng_seeding* seeding, ui
         if (rc < 0) return rc;
         mode = p.seed.kind;
     }
-    int bpc = 16, round = 20;
+    int bpc = 16, round = 20, generic = 0;
     if (const char* env = getenv("MCRNG_DRAW_BLOCKS_PER_CU")) bpc = atoi(env);
     if (const char* env = getenv("MCRNG_DRAW_ROUND")) round = atoi(env);
+    if (const char* env = getenv("MCRNG_DRAW_GENERIC")) generic = atoi(env);
+    if (round != 8 && round != 16 && round != 24 && round != 32) round = 20;
+    // m = 63 or 64 with an odd multiplier: the round-aligned kernel
+    if (!generic && L.m >= 63 && (L.g & 1ull)) {
+        int r2 = get_align_table(L, round, &p.align);
+        if (r2 < 0) return r2;
+    }
     HIP_TRY(launch_draw(p, mode, static_cast<hipStream_t>(stream), bpc, round));
     return rc;
 }
@@ -426,6 +483,8 @@ static bool increasing(const double* a, uint32_t n) {
 constexpr uint32_t kMaxCells = 4096;
 constexpr uint32_t kMaxSlice = 8192;
 constexpr double kTauMax = 36.75;   // above -ln(2^-53) = 36.7368...
+constexpr double kMaxCoord = 0x1p40;
+constexpr double kMinSigma = 0x1p-64, kMaxSigma = 0x1p64;
 
 static int validate_problem(const mcrng_problem& P, uint32_t idx) {
     if (P.n_regions < 1 || P.n_space_bins < 1 || P.n_batches < 1)
@@ -440,10 +499,14 @@ static int validate_problem(const mcrng_problem& P, uint32_t idx) {
         return fail(MCRNG_EINVAL, "problem %u: region and bin edges must span the same interval", idx);
     if (P.n_time_bins > 0 && !increasing(P.time_edges, P.n_time_bins + 1))
         return fail(MCRNG_EINVAL, "problem %u: time edges must be finite and strictly increasing", idx);
+    // the kernels divide by sigma_t and by direction cosines through refined
+    // reciprocals, exact while operands stay well inside the exponent range
+    if (!(std::fabs(P.region_edges[0]) <= kMaxCoord && std::fabs(P.region_edges[P.n_regions]) <= kMaxCoord))
+        return fail(MCRNG_EINVAL, "problem %u: edges must lie within [-2^40, 2^40]", idx);
     double min_sig = INFINITY;
     for (uint32_t r = 0; r < P.n_regions; ++r) {
-        if (!(P.sigma_t[r] > 0.0) || !std::isfinite(P.sigma_t[r]))
-            return fail(MCRNG_EINVAL, "problem %u: sigma_t[%u] must be finite and > 0", idx, r);
+        if (!(P.sigma_t[r] >= kMinSigma && P.sigma_t[r] <= kMaxSigma))
+            return fail(MCRNG_EINVAL, "problem %u: sigma_t[%u] must lie within [2^-64, 2^64]", idx, r);
         if (!(P.scatter[r] >= 0.0 && P.scatter[r] <= 1.0))
             return fail(MCRNG_EINVAL, "problem %u: scatter[%u] must be in [0, 1]", idx, r);
         min_sig = std::min(min_sig, P.sigma_t[r]);
@@ -734,9 +797,11 @@ static int normalise_opts(const mcrng_run_opts* in, mcrng_run_opts* o) {
     if (o->hist_per_lane == 0) o->hist_per_lane = 1;
     if (o->hist_per_lane != 1 && o->hist_per_lane != 2 && o->hist_per_lane != 4)
         return fail(MCRNG_EINVAL, "opts.hist_per_lane = %u not in {1,2,4}", o->hist_per_lane);
-    // the autotuner's choice on the long-chain and multi-region slabs: 24 in
-    // FP64 (1-3% faster than 32), 32 in FP32
-    if (o->coll_batch == 0) o->coll_batch = o->precision == MCRNG_FP32 ? 32 : 24;
+    // a wave's collision pass once 36 of its 64 lanes wait: the best batch in
+    // a model of the long-chain slab's lane occupancy (a geometry step ends at
+    // a collision one time in three; a collision pass costs about twice a
+    // geometry pass); the autotuner searches around it
+    if (o->coll_batch == 0) o->coll_batch = 36;
     if (o->coll_batch > 64 * o->hist_per_lane) o->coll_batch = 64 * o->hist_per_lane;
     if (o->tally_copies == 0) o->tally_copies = 1;
     if (o->tally_copies > 2) return fail(MCRNG_EINVAL, "opts.tally_copies must be 1 or 2");
@@ -1139,7 +1204,7 @@ extern "C" int mcrng_autotune(mcrng_ctx* ctx, const mcrng_lcg* lcg, const mcrng_
     if ((rc = try_field(&mcrng_run_opts::hist_per_lane, {1, 2, 4})) < 0) return rc;
     if ((rc = try_field(&mcrng_run_opts::tally_copies, {1, 2})) < 0) return rc;
     if (cur.schedule == MCRNG_SCHED_HISTORY)
-        if ((rc = try_field(&mcrng_run_opts::coll_batch, {1, 16, 24, 32, 48})) < 0) return rc;
+        if ((rc = try_field(&mcrng_run_opts::coll_batch, {1, 16, 24, 32, 36, 40, 48})) < 0) return rc;
     const uint32_t u0 = default_unit_histories(problems, n_problems);
     if ((rc = try_field(&mcrng_run_opts::unit_histories, {u0 / 4 > 256 ? u0 / 4 : 256, u0, u0 * 4})) < 0) return rc;
     if (cur.unit_histories == 0) cur.unit_histories = u0;

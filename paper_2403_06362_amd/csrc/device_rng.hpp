@@ -29,6 +29,12 @@ __device__ __forceinline__ uint64_t lcg_next(const LcgDev& L, uint64_t x) {
     return (L.g * x + L.c) & L.mask;
 }
 
+// The same step for m >= 32, where the mask leaves the low word alone (one
+// AND on the high word instead of two).
+__device__ __forceinline__ uint64_t lcg_next_wide(const LcgDev& L, uint64_t x) {
+    return (L.g * x + L.c) & (L.mask | 0xffffffffull);
+}
+
 __device__ __forceinline__ uint64_t affine_apply(uint64_t G, uint64_t C, uint64_t mask, uint64_t x) {
     return (G * x + C) & mask;
 }
@@ -60,9 +66,51 @@ __host__ __device__ __forceinline__ uint64_t murmur_hash(uint64_t k, uint64_t s)
 
 // u = ((X >> (m - 53)) + 1) * 2^-53.  The integer is at most 2^53, so the
 // conversion to double is exact.
+// The integer's halves are converted separately and joined by one fused
+// multiply-add, hi 2^32 + lo, exact (as the plain conversion is) below 2^53.
 __device__ __forceinline__ double to_uniform(const LcgDev& L, uint64_t x) {
     const uint64_t top = (x >> L.shift53) + 1ull;
-    return static_cast<double>(top) * 0x1p-53;
+    const double hi = static_cast<double>(static_cast<uint32_t>(top >> 32));
+    const double lo = static_cast<double>(static_cast<uint32_t>(top));
+    return __builtin_fma(hi, 0x1p32, lo) * 0x1p-53;
+}
+
+// ------------------------------------------------------------ division
+// A correctly rounded quotient a / b is, on this hardware, the reciprocal
+// r = rcp(b) refined by Newton steps r <- r + r (1 - b r) (two in double
+// precision, one in single), the product q = a r and residual corrections
+// q <- q + (a - b q) r (one in double, two in single), each a fused
+// multiply-add, wrapped in operand scaling that acts only near the ends of
+// the exponent range.  The refined reciprocal depends on b alone, so a
+// divisor used many times (a cell's sigma_t, a flight's direction cosine)
+// has it computed once.  quot(a, b, recip_refined(b)) then equals a / b bit
+// for bit wherever the scaling does not act, which holds when |a| is at
+// least 2^-900 (single: 2^-60), b is nonzero with |b| in [2^-64, 2^64] and
+// |a| is at most 2^42: what the transport's validated geometry allows.  A
+// smaller |a| (zero included) takes the plain division.
+__device__ __forceinline__ double recip_refined(double b) {
+    double r = __builtin_amdgcn_rcp(b);
+    r = __builtin_fma(r, __builtin_fma(-b, r, 1.0), r);
+    r = __builtin_fma(r, __builtin_fma(-b, r, 1.0), r);
+    return r;
+}
+
+__device__ __forceinline__ double quot(double a, double b, double r) {
+    if (!(__builtin_fabs(a) >= 0x1p-900)) return a / b;
+    const double q = a * r;
+    return __builtin_fma(__builtin_fma(-b, q, a), r, q);
+}
+
+__device__ __forceinline__ float recip_refined(float b) {
+    const float r = __builtin_amdgcn_rcpf(b);
+    return __builtin_fmaf(__builtin_fmaf(-b, r, 1.0f), r, r);
+}
+
+__device__ __forceinline__ float quot(float a, float b, float r) {
+    if (!(__builtin_fabsf(a) >= 0x1p-60f)) return a / b;
+    float q = a * r;
+    q = __builtin_fmaf(__builtin_fmaf(-b, q, a), r, q);
+    return __builtin_fmaf(__builtin_fmaf(-b, q, a), r, q);
 }
 
 // Natural logarithm of u in (0, 1] (any positive normal double works).
@@ -91,7 +139,7 @@ __device__ __forceinline__ double fixed_log(double u) {
     }
     const double a = f - 1.0;
     const double b = 2.0 + a;
-    const double s = a / b;
+    const double s = quot(a, b, recip_refined(b));   // a in {0} or [2^-53, 1/2), b in [7/4, 5/2)
     const double w = s * s;
     double p = kC[11];
 #pragma unroll

@@ -29,14 +29,15 @@ namespace mcrng {
 template <bool F32>
 struct BankView {
     using R = typename std::conditional<F32, float, double>::type;
-    R* x; R* mu; R* t; R* tau;
+    R* x; R* mu; R* t;
+    double* tau;   // the remaining optical depth is double in both modes
 };
 
 template <bool F32>
 __device__ __forceinline__ BankView<F32> view(const EventBank& b) {
     BankView<F32> v;
     if constexpr (F32) {
-        v.x = b.x32; v.mu = b.mu32; v.t = b.t32; v.tau = b.tau32;
+        v.x = b.x32; v.mu = b.mu32; v.t = b.t32; v.tau = b.tau64;
     } else {
         v.x = b.x64; v.mu = b.mu64; v.t = b.t64; v.tau = b.tau64;
     }
@@ -55,6 +56,7 @@ __device__ __forceinline__ CellsLds<F32> global_cells(const TransportParams& P, 
         C.sig = P.sig64 + PR.cell_off;
         C.tedge = P.tedges64 + PR.tedge_off;
     }
+    C.rsig = nullptr;   // each event refines its cell's reciprocal
     C.scat = P.scat64 + PR.cell_off;
     C.bin = P.cbin + PR.cell_off;
     C.n_cells = static_cast<int32_t>(PR.n_cells);
@@ -173,6 +175,8 @@ __global__ void __launch_bounds__(kEventStepBlock) k_event_step(EventParams E) {
             BankView<F32> v = view<F32>(E.in);
             p.x = v.x[i];
             p.mu = v.mu[i];
+        set_direction<F32>(p);
+            set_direction<F32>(p);
             p.t = TIMED ? v.t[i] : 0;
             p.tau = v.tau[i];
             p.X = E.in.X[i];
@@ -249,6 +253,7 @@ __global__ void __launch_bounds__(256) k_event_finish(EventParams E) {
         LaneCounters cnt;
         p.x = v.x[i];
         p.mu = v.mu[i];
+        set_direction<F32>(p);
         p.t = TIMED ? v.t[i] : 0;
         p.tau = v.tau[i];
         p.X = E.in.X[i];

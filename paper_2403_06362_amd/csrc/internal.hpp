@@ -46,6 +46,19 @@ __device__ __forceinline__ uint64_t stream_start(const LcgDev& L, const SeedDev&
 
 // ------------------------------------------------------------ draw kernels
 
+// Round alignment of a stream (the draw kernel for m = 63 and 64 with an odd
+// multiplier): a stream of n draws runs rounds = ceil(n / D) whole rounds of
+// D steps and starts h = rounds D - n steps before its own start state X_0,
+// so that it ends on a round boundary.  Entry h holds the affine maps, modulo
+// 2^64, of that rewind, X_{-h} = a X_0 + b, and of minus the sum of the h
+// outputs drawn before X_1 (X_{-h+1} .. X_0): na X_0 + nb.
+struct __align__(16) AlignEntry {
+    uint64_t a, b;
+    uint64_t na, nb;
+};
+
+constexpr int kMaxRound = 32;
+
 struct DrawParams {
     LcgDev lcg;
     SeedDev seed;
@@ -53,6 +66,7 @@ struct DrawParams {
     const uint32_t* count;
     uint64_t* state;      // SEED_LOAD: in/out; else optional out (may be null)
     uint64_t* checksum;
+    const AlignEntry* align;   // round alignment for the round length (null: the generic kernel)
 };
 
 hipError_t launch_init_streams(const LcgDev& L, const SeedDev& S, uint64_t n, uint64_t* out,

@@ -4,14 +4,20 @@
 //
 // An event is split in three parts that a schedule may run at different
 // times for one particle (never reordered, never skipped):
-//   sample_tau   X = lcg(X); tau = R(-ln(uniform(X)))              (the flight)
+//   sample_tau   X = lcg(X); tau = -ln(uniform(X))                 (the flight)
 //   geom_*       distances to collision / edge / time, choice, score,
 //                move; returns END_*, END_NONE (edge or time step) or
 //                STEP_COLLIDE (the particle stands at its collision site)
 //   collide      X = lcg(X), absorbed unless uniform < c; X = lcg(X),
 //                mu = R(2 u - 1); the next part is sample_tau
-// Every floating-point operation is one IEEE operation rounded to nearest,
-// no fused multiply-add (the library is built with -ffp-contract=off).
+// Every floating-point result is the IEEE operation's, rounded to nearest,
+// with no fused multiply-add where the operation is a separate multiply and
+// add (the library is built with -ffp-contract=off).  Divisions by a
+// cell's sigma_t and by the flight's mu go through the divisor's refined
+// reciprocal (quot, device_rng.hpp), which gives the correctly rounded
+// quotient; minima and maxima are the compare-and-replace clamps of the
+// operation sequence (their operands are never NaN, and a zero's sign never
+// reaches a tally, a decision or a stored state).
 #pragma once
 
 #include <type_traits>
@@ -23,21 +29,35 @@ namespace mcrng {
 template <bool F32>
 struct Particle {
     using R = typename std::conditional<F32, float, double>::type;
-    R x, mu, t, tau;    // FP64: global x, t; FP32: x from the cell's left edge, t from the time bin start
+    R x, mu, t;         // FP64: global x, t; FP32: x from the cell's left edge, t from the time bin start
+    double tau;         // remaining optical depth of the flight (double in both modes)
+    R rmu;              // refined reciprocal of mu (set_direction)
+    R far;              // +inf when mu == 0 (the flight meets no edge), else 0
     uint64_t X;         // LCG state
     int32_t cell, tb;
     uint32_t hdraws;    // numbers drawn by this history
     bool need_tau;      // the next event starts by sampling a flight
 };
 
+// Derived direction values, after every change of mu.
+template <bool F32>
+__device__ __forceinline__ void set_direction(Particle<F32>& p) {
+    using R = typename Particle<F32>::R;
+    p.rmu = recip_refined(p.mu);
+    p.far = (p.mu == R(0)) ? static_cast<R>(__builtin_huge_val()) : R(0);
+}
+
 // Cell data of the current problem (LDS-staged or global).  FP64: edge[c]
 // is the position of edge c (n_cells + 1), tedge[t] the time edges.  FP32:
 // edge[c] is the width of cell c, tedge[t] the duration of time bin t.
+// rsig[c] is recip_refined(sig[c]) (staged with the cells), or null: then
+// it is computed per event.
 template <bool F32>
 struct CellsLds {
     using R = typename std::conditional<F32, float, double>::type;
     const R* edge;
     const R* sig;       // n_cells
+    const R* rsig;      // n_cells, or null
     const double* scat; // n_cells (the absorption test stays in double)
     const int32_t* bin; // n_cells
     const R* tedge;
@@ -45,6 +65,12 @@ struct CellsLds {
     int32_t n_time_bins;
     int32_t n_space_bins;
 };
+
+template <bool F32>
+__device__ __forceinline__ typename CellsLds<F32>::R cell_recip(const CellsLds<F32>& C, int c,
+                                                               typename CellsLds<F32>::R sig) {
+    return C.rsig ? C.rsig[c] : recip_refined(sig);
+}
 
 enum : int { STEP_COLLIDE = -1, END_NONE = 0, END_LEAK_LEFT, END_LEAK_RIGHT, END_ABSORBED, END_CENSUS };
 
@@ -82,11 +108,9 @@ __device__ __forceinline__ void add_score(uint64_t* slot, uint64_t q) {
 
 template <bool F32>
 __device__ __forceinline__ void sample_tau(Particle<F32>& p, const LcgDev& L) {
-    using R = typename Particle<F32>::R;
-    p.X = lcg_next(L, p.X);
+    p.X = lcg_next_wide(L, p.X);
     p.hdraws++;
-    const double lg = fixed_log(to_uniform(L, p.X));
-    p.tau = static_cast<R>(-lg);
+    p.tau = -fixed_log(to_uniform(L, p.X));
     p.need_tau = false;
 }
 
@@ -101,18 +125,18 @@ __device__ __forceinline__ void sample_tau(Particle<F32>& p, const LcgDev& L) {
 //          mu < 0: x = E[c], c - 1 (leak left past the first)
 //   other: x = x + mu * s, clamped to [E[c], E[c+1]]
 //   time:  tb + 1, t = T[tb+1]; census past the last time edge
+// (far turns the mu == 0 edge distance into +inf or NaN, which loses the
+// strict comparison as +inf does.)
 template <bool TIMED, bool CARRY = false>
-__device__ __forceinline__ int geom_f64(Particle<false>& p, const CellsLds<false>& C, uint64_t* tally,
-                                        LaneCounters& cnt) {
+__device__ __forceinline__ int geom_f64(Particle<false>& p, const CellsLds<false>& C, uint64_t* tally) {
     const int c = p.cell;
     const double sig = C.sig[c];
     const double e_lo = C.edge[c], e_hi = C.edge[c + 1];
-    double s = p.tau / sig;
+    double s = quot(p.tau, sig, cell_recip<false>(C, c, sig));
     int ev = 0;   // 0 collision, 1 edge, 2 time
-    // one division for both directions: the crossed edge is selected first
-    const double e_to = (p.mu > 0.0) ? e_hi : e_lo;
-    double se = (e_to - p.x) / p.mu;
-    if (!(p.mu != 0.0)) se = __builtin_huge_val();
+    const bool up = p.mu > 0.0;
+    const double e_to = up ? e_hi : e_lo;
+    const double se = quot(e_to - p.x, p.mu, p.rmu) + p.far;
     if (se < s) {
         s = se;
         ev = 1;
@@ -128,34 +152,17 @@ __device__ __forceinline__ int geom_f64(Particle<false>& p, const CellsLds<false
         }
     }
     add_score<CARRY>(tally + 2 * (static_cast<uint32_t>(p.tb) * C.n_space_bins + C.bin[c]), quantise(s));
-    cnt.events++;
-    if (timed) {
-        double tn = p.t + s;
-        if (tn > tnext) tn = tnext;
-        p.t = tn;
-    }
-    const double dtau = sig * s;
-    double tau = p.tau - dtau;
-    if (tau < 0.0) tau = 0.0;
-    p.tau = tau;
+    if (timed) p.t = __builtin_fmin(p.t + s, tnext);
+    p.tau = __builtin_fmax(p.tau - sig * s, 0.0);
     if (ev == 1) {
-        if (p.mu > 0.0) {
-            const int nc = c + 1;
-            if (nc == C.n_cells) return END_LEAK_RIGHT;
-            p.cell = nc;
-            p.x = e_hi;
-        } else {
-            p.x = e_lo;
-            if (c == 0) return END_LEAK_LEFT;
-            p.cell = c - 1;
-        }
+        const int nc = up ? c + 1 : c - 1;
+        if (nc < 0) return END_LEAK_LEFT;
+        if (nc == C.n_cells) return END_LEAK_RIGHT;
+        p.cell = nc;
+        p.x = e_to;
         return END_NONE;
     }
-    const double step = p.mu * s;
-    double nx = p.x + step;
-    if (nx < e_lo) nx = e_lo;
-    if (nx > e_hi) nx = e_hi;
-    p.x = nx;
+    p.x = __builtin_fmin(__builtin_fmax(p.x + p.mu * s, e_lo), e_hi);
     if (timed && ev == 2) {
         const int ntb = p.tb + 1;
         p.tb = ntb;
@@ -167,24 +174,26 @@ __device__ __forceinline__ int geom_f64(Particle<false>& p, const CellsLds<false
 }
 
 // FP32 geometry with the position measured from the cell's left edge and
-// the time from the time bin's start (W = cell width, DT = bin duration):
-//   s = tau / sig[c];  se = (W[c] - x)/mu (mu > 0), (0 - x)/mu (mu < 0),
+// the time from the time bin's start (W = cell width, DT = bin duration);
+// the remaining optical depth tau stays double (a float tau would lose
+// absolute precision over a flight's many subtractions, and the flight's
+// last segment, their small remainder, would carry it):
+//   s = R(tau) / sig[c];  se = (W[c] - x)/mu (mu > 0), (0 - x)/mu (mu < 0),
 //   +inf (mu == 0);  timed: st = DT[tb] - t;  strict-less order as in FP64
 //   score q(double(s));  timed: t = t + s, clamped to DT[tb]
-//   tau = tau - sig * s, clamped at 0
+//   tau = tau - double(sig) double(s) (exact product), clamped at 0
 //   edge: mu > 0: c + 1, x = 0;  mu < 0: c - 1, x = W[c - 1]
 //   other: x = x + mu s clamped to [0, W[c]];  time: tb + 1, t = 0
 template <bool TIMED, bool CARRY = false>
-__device__ __forceinline__ int geom_f32(Particle<true>& p, const CellsLds<true>& C, uint64_t* tally,
-                                        LaneCounters& cnt) {
+__device__ __forceinline__ int geom_f32(Particle<true>& p, const CellsLds<true>& C, uint64_t* tally) {
     const int c = p.cell;
     const float sig = C.sig[c];
     const float w = C.edge[c];
-    float s = p.tau / sig;
+    float s = quot(static_cast<float>(p.tau), sig, cell_recip<true>(C, c, sig));
     int ev = 0;
-    const float e_to = (p.mu > 0.0f) ? w : 0.0f;
-    float se = (e_to - p.x) / p.mu;
-    if (!(p.mu != 0.0f)) se = __builtin_huge_valf();
+    const bool up = p.mu > 0.0f;
+    const float e_to = up ? w : 0.0f;
+    const float se = quot(e_to - p.x, p.mu, p.rmu) + p.far;
     if (se < s) {
         s = se;
         ev = 1;
@@ -201,18 +210,10 @@ __device__ __forceinline__ int geom_f32(Particle<true>& p, const CellsLds<true>&
     }
     add_score<CARRY>(tally + 2 * (static_cast<uint32_t>(p.tb) * C.n_space_bins + C.bin[c]),
                      quantise(static_cast<double>(s)));
-    cnt.events++;
-    if (timed) {
-        float tn = p.t + s;
-        if (tn > dtb) tn = dtb;
-        p.t = tn;
-    }
-    const float dtau = sig * s;
-    float tau = p.tau - dtau;
-    if (tau < 0.0f) tau = 0.0f;
-    p.tau = tau;
+    if (timed) p.t = __builtin_fminf(p.t + s, dtb);
+    p.tau = __builtin_fmax(p.tau - static_cast<double>(sig) * static_cast<double>(s), 0.0);
     if (ev == 1) {
-        if (p.mu > 0.0f) {
+        if (up) {
             const int nc = c + 1;
             if (nc == C.n_cells) return END_LEAK_RIGHT;
             p.cell = nc;
@@ -224,11 +225,7 @@ __device__ __forceinline__ int geom_f32(Particle<true>& p, const CellsLds<true>&
         }
         return END_NONE;
     }
-    const float step = p.mu * s;
-    float nx = p.x + step;
-    if (nx < 0.0f) nx = 0.0f;
-    if (nx > w) nx = w;
-    p.x = nx;
+    p.x = __builtin_fminf(__builtin_fmaxf(p.x + p.mu * s, 0.0f), w);
     if (timed && ev == 2) {
         const int ntb = p.tb + 1;
         p.tb = ntb;
@@ -241,12 +238,11 @@ __device__ __forceinline__ int geom_f32(Particle<true>& p, const CellsLds<true>&
 
 // CARRY: the tally is a global pair array scored with carry_add.
 template <bool F32, bool TIMED, bool CARRY = false>
-__device__ __forceinline__ int geom_step(Particle<F32>& p, const CellsLds<F32>& C, uint64_t* tally,
-                                         LaneCounters& cnt) {
+__device__ __forceinline__ int geom_step(Particle<F32>& p, const CellsLds<F32>& C, uint64_t* tally) {
     if constexpr (F32)
-        return geom_f32<TIMED, CARRY>(p, C, tally, cnt);
+        return geom_f32<TIMED, CARRY>(p, C, tally);
     else
-        return geom_f64<TIMED, CARRY>(p, C, tally, cnt);
+        return geom_f64<TIMED, CARRY>(p, C, tally);
 }
 
 // Collision at the current site: u1 decides absorption (double compare with
@@ -254,30 +250,31 @@ __device__ __forceinline__ int geom_step(Particle<F32>& p, const CellsLds<F32>& 
 // (computed in double, exact, then rounded once).  The next flight is
 // sampled by sample_tau.
 template <bool F32>
-__device__ __forceinline__ int collide(Particle<F32>& p, const CellsLds<F32>& C, const LcgDev& L,
-                                       LaneCounters& cnt) {
+__device__ __forceinline__ int collide(Particle<F32>& p, const CellsLds<F32>& C, const LcgDev& L) {
     using R = typename Particle<F32>::R;
-    cnt.collisions++;
-    p.X = lcg_next(L, p.X);
+    p.X = lcg_next_wide(L, p.X);
     p.hdraws++;
     const double u1 = to_uniform(L, p.X);
     if (!(u1 < C.scat[p.cell])) return END_ABSORBED;
-    p.X = lcg_next(L, p.X);
+    p.X = lcg_next_wide(L, p.X);
     p.hdraws++;
     const double u2 = to_uniform(L, p.X);
     p.mu = static_cast<R>(2.0 * u2 - 1.0);
+    set_direction<F32>(p);
     p.need_tau = true;
     return END_NONE;
 }
 
-// One whole event (the event-sorted schedule's unit of work).
+// One whole event (the event-sorted schedule's unit of work), counted.
 template <bool F32, bool TIMED, bool CARRY = false>
 __device__ __forceinline__ int step_particle(Particle<F32>& p, const CellsLds<F32>& C, const LcgDev& L,
                                              uint64_t* tally, LaneCounters& cnt) {
     if (p.need_tau) sample_tau<F32>(p, L);
-    const int r = geom_step<F32, TIMED, CARRY>(p, C, tally, cnt);
+    cnt.events++;
+    const int r = geom_step<F32, TIMED, CARRY>(p, C, tally);
     if (r != STEP_COLLIDE) return r;
-    return collide<F32>(p, C, L, cnt);
+    cnt.collisions++;
+    return collide<F32>(p, C, L);
 }
 
 // A new history whose stream starts at state X: source at the left face
@@ -295,7 +292,9 @@ __device__ __forceinline__ void init_particle_at(Particle<F32>& p, const CellsLd
         p.t = (TIMED && C.n_time_bins > 0) ? C.tedge[0] : 0.0;
     }
     p.mu = R(1);
-    p.tau = R(0);
+    p.rmu = R(1);   // recip_refined(1) is exactly 1
+    p.far = R(0);
+    p.tau = 0.0;
     p.cell = 0;
     p.tb = 0;
     p.hdraws = 0;

@@ -68,33 +68,22 @@ hipError_t launch_init_streams(const LcgDev& L, const SeedDev& S, uint64_t n, ui
     return hipGetLastError();
 }
 
-// One LCG step for m = 63, c = 1: with the increment and the mask known at
-// compile time this is one v_mad_u64_u32 (g_lo * x_lo + 1), two
-// v_mul_lo_u32 (cross products), one v_add3_u32 and one v_and_b32.
-template <bool M63C1>
-__device__ __forceinline__ uint64_t draw_step(const LcgDev& L, uint64_t x, uint64_t g) {
-    if (M63C1) return (g * x + 1ull) & 0x7fffffffffffffffull;
-    return lcg_next(L, x);
-}
-
 template <int MODE>
 __device__ __forceinline__ uint64_t queue_seed(const DrawParams& P, uint64_t j) {
     if (MODE == SEED_LOAD) return P.state[j];
     return stream_start(P.lcg, P.seed, j);
 }
 
-// A ring entry's start state for stream j0 + lane (j0 wave-uniform): X, or
-// 2X on the halves path (m = 63, c = 1, no stored states).  There a hashed
-// start needs no mask (((h mod 2^63) 2) mod 2^64 = 2h mod 2^64), and the
-// hash's first product (k0 + lane) M, k0 = first_index + j0 + 1, is
-// k0 M (scalar) plus the lane's lane M.
-template <int MODE, bool HALVES>
-__device__ __forceinline__ uint64_t ring_state(const DrawParams& P, uint64_t j0, uint32_t lane, uint64_t lane_m) {
-    if constexpr (HALVES && MODE == SEED_HASH) {
+// Start state of stream j0 + lane (j0 wave-uniform).  Hashed: the hash's
+// first product (k0 + lane) M, k0 = first_index + j0 + 1, is k0 M (scalar)
+// plus the lane's lane M.
+template <int MODE>
+__device__ __forceinline__ uint64_t lane_start(const DrawParams& P, uint64_t j0, uint32_t lane, uint64_t lane_m) {
+    if constexpr (MODE == SEED_HASH) {
         const uint64_t k0m = (P.seed.first_index + j0 + 1ull) * kMurmurM;
-        return murmur_from_product(k0m + lane_m, P.seed.base) << 1;
+        return murmur_from_product(k0m + lane_m, P.seed.base) & P.lcg.mask;
     } else {
-        return queue_seed<MODE>(P, j0 + lane) << (HALVES ? 1 : 0);
+        return queue_seed<MODE>(P, j0 + lane);
     }
 }
 
@@ -120,25 +109,27 @@ __device__ __forceinline__ StrideLanes stride_lanes(const SeedDev& S, uint32_t l
     return r;
 }
 
-// One ring entry: a stream's start state and its draw count (one LDS read).
+// ------------------------------------------------------------------ generic kernel
+
+// One ring entry of the generic kernel: a stream's start state and its draw
+// count (one LDS read).
 struct __align__(16) RingEntry {
     uint64_t state;
     uint32_t count;
     uint32_t pad;
 };
 
-// Persistent seed + draw kernel.  Each wave owns the streams [lo, hi)
-// (fewer than 2^28) and keeps the next streams ready in a 128-entry LDS ring
-// (start state and draw count at position j & 127 for stream j), seeded 64 at
-// a time by all 64 lanes at once (stride seeding: one affine step per lane
-// from the batch's base), the counts loaded one batch ahead.  Each
-// lane carries one active stream; a round draws D steps (only the checksum is
-// masked by the remaining count); after a round, lanes whose stream ended
-// store its checksum and take the next ring entries in order (ballot, prefix
-// count, one ring entry read).  Up to 64 lanes are served per round without a
-// loop, and the refill path never waits on vector memory (one wait per 64
-// streams, when a batch is seeded).
-template <int MODE, int D, bool STORE_STATE, bool M63C1>
+// Persistent seed + draw kernel for any generator (the round-aligned kernel
+// below serves m = 63 and 64 with an odd multiplier).  Each wave owns the
+// streams [lo, hi) (fewer than 2^28) and keeps the next streams ready in a
+// 128-entry LDS ring (start state and draw count at position j & 127 for
+// stream j), seeded 64 at a time by all 64 lanes at once (stride seeding:
+// one affine step per lane from the batch's base), the counts loaded one
+// batch ahead.  Each lane carries one active stream; a round draws D steps,
+// the checksum (and, with STORE_STATE, the state) masked by the remaining
+// count; after a round, lanes whose stream ended store its checksum and take
+// the next ring entries in order (ballot, prefix count, one ring entry read).
+template <int MODE, int D, bool STORE_STATE>
 __global__ void __launch_bounds__(256) k_draw(DrawParams P) {
     __shared__ RingEntry s_ring[4][128];
     const uint32_t lane = threadIdx.x & 63u;
@@ -147,27 +138,12 @@ __global__ void __launch_bounds__(256) k_draw(DrawParams P) {
     const uint64_t nwaves = static_cast<uint64_t>(gridDim.x) * (blockDim.x >> 6);
     const uint64_t lo = wave * P.n / nwaves;
     const uint32_t nw = static_cast<uint32_t>((wave + 1) * P.n / nwaves - lo);   // streams of this wave
-    const uint64_t g = P.lcg.g;
     RingEntry* ring = s_ring[wib];
-    // HALVES (m = 63, c = 1, state not stored): a lane holds 2 X, which
-    // follows 2X <- g (2X) + 2 mod 2^64 with no mask; the ring holds 2 X too.
-    // The checksum is kept as the exact sums of the low and the high 32-bit
-    // words of 2X (each below 2^64 for fewer than 2^32 draws), so sum X mod
-    // 2^64 = (lo_sum >> 1) + (hi_sum << 31).  A masked draw slot then costs a
-    // bit-field extract and two 32 x 32 + 64 multiply-adds.
-    constexpr bool HALVES = M63C1 && !STORE_STATE;
-    constexpr int SH = HALVES ? 1 : 0;
-    // wave-uniform base of the wave's checksums; a store adds a 32-bit byte
-    // offset (the launcher keeps a wave below 2^28 streams)
     char* const cbase = reinterpret_cast<char*>(P.checksum + lo);
-    const uint64_t lane_m = static_cast<uint64_t>(lane) * kMurmurM;   // hashed ring entries
+    const uint64_t lane_m = static_cast<uint64_t>(lane) * kMurmurM;
 
-    // ring bookkeeping, wave-uniform: streams [next, filled) are seeded and
-    // not yet handed out; c_next holds the counts of the batch after them
     uint32_t next = 0, filled = 128;
     uint32_t c_next = 0;
-    // stride seeding: this lane's map A_{Q lane} and the base X_{Q s0} of the
-    // next batch to seed (wave-uniform)
     StrideLanes sl{};
     uint64_t sbase = 0;
     if (MODE == SEED_STRIDE) {
@@ -180,53 +156,49 @@ __global__ void __launch_bounds__(256) k_draw(DrawParams P) {
         ring[jb].count = (jb < nw) ? P.count[lo + jb] : 0u;
         if (MODE == SEED_STRIDE) {
             const uint64_t b1 = affine_apply(sl.g64, sl.c64, P.lcg.mask, sbase);
-            ring[ja].state = (ja < nw) ? affine_apply(sl.g, sl.c, P.lcg.mask, sbase) << SH : 0ull;
-            ring[jb].state = (jb < nw) ? affine_apply(sl.g, sl.c, P.lcg.mask, b1) << SH : 0ull;
+            ring[ja].state = (ja < nw) ? affine_apply(sl.g, sl.c, P.lcg.mask, sbase) : 0ull;
+            ring[jb].state = (jb < nw) ? affine_apply(sl.g, sl.c, P.lcg.mask, b1) : 0ull;
             sbase = affine_apply(sl.g64, sl.c64, P.lcg.mask, b1);
         } else {
-            ring[ja].state = (ja < nw) ? ring_state<MODE, HALVES>(P, lo, lane, lane_m) : 0ull;
-            ring[jb].state = (jb < nw) ? ring_state<MODE, HALVES>(P, lo + 64u, lane, lane_m) : 0ull;
+            ring[ja].state = (ja < nw) ? lane_start<MODE>(P, lo, lane, lane_m) : 0ull;
+            ring[jb].state = (jb < nw) ? lane_start<MODE>(P, lo + 64u, lane, lane_m) : 0ull;
         }
         if (jn < nw) c_next = P.count[lo + jn];
     }
 
-    uint64_t x = 0, sum = 0, hsum = 0;
+    uint64_t x = 0, sum = 0;
     uint32_t sid = 0, rem = 0;
     bool active = false;
     for (;;) {
         if (active && rem == 0) {
-            *reinterpret_cast<uint64_t*>(cbase + (sid << 3)) = HALVES ? (sum >> 1) + (hsum << 31) : sum;
+            *reinterpret_cast<uint64_t*>(cbase + (sid << 3)) = sum;
             if (STORE_STATE) P.state[lo + sid] = x;
             active = false;
         }
-        next = __builtin_amdgcn_readfirstlane(next);   // wave-uniform: kept in a scalar register
+        next = __builtin_amdgcn_readfirstlane(next);
         const uint64_t need = __builtin_amdgcn_ballot_w64(!active);
-        const uint32_t left = nw - next;   // streams not yet handed out
+        const uint32_t left = nw - next;
         if (need != 0 && left != 0) {
             const uint32_t nneed = static_cast<uint32_t>(__popcll(need));
             const uint32_t take = __builtin_amdgcn_readfirstlane(nneed < left ? nneed : left);
             const uint32_t rank = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(need >> 32),
                                                             __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(need), 0u));
             if (!active && rank < take) {
-                const uint32_t e = (next + rank) & 127u;
-                const RingEntry r = ring[e];
+                const RingEntry r = ring[(next + rank) & 127u];
                 x = r.state;
                 rem = r.count;
                 sid = next + rank;
                 sum = 0;
-                hsum = 0;
                 active = true;
             }
             next = __builtin_amdgcn_readfirstlane(next + take);
             if (filled - next < 64u && filled < nw) {
-                // fewer than 64 ready: seed the next batch of 64 (its ring
-                // positions hold no stream that is still to be handed out)
                 const uint32_t j = filled + lane;
                 if (MODE == SEED_STRIDE) {
-                    ring[j & 127u].state = (j < nw) ? affine_apply(sl.g, sl.c, P.lcg.mask, sbase) << SH : 0ull;
+                    ring[j & 127u].state = (j < nw) ? affine_apply(sl.g, sl.c, P.lcg.mask, sbase) : 0ull;
                     sbase = affine_apply(sl.g64, sl.c64, P.lcg.mask, sbase);
                 } else {
-                    ring[j & 127u].state = (j < nw) ? ring_state<MODE, HALVES>(P, lo + filled, lane, lane_m) : 0ull;
+                    ring[j & 127u].state = (j < nw) ? lane_start<MODE>(P, lo + filled, lane, lane_m) : 0ull;
                 }
                 ring[j & 127u].count = c_next;   // the one wait on vector memory per 64 streams
                 const uint32_t jn = j + 64u;
@@ -235,34 +207,18 @@ __global__ void __launch_bounds__(256) k_draw(DrawParams P) {
             }
         }
         if (__builtin_amdgcn_ballot_w64(active) == 0) break;
-        // a lane without a stream has rem == 0
         const uint32_t k = rem < static_cast<uint32_t>(D) ? rem : static_cast<uint32_t>(D);
-        if (STORE_STATE) {
 #pragma unroll
-            for (int d = 0; d < D; ++d) {
+        for (int d = 0; d < D; ++d) {
+            if (STORE_STATE) {
                 if (static_cast<uint32_t>(d) < k) {
-                    x = draw_step<M63C1>(P.lcg, x, g);
+                    x = lcg_next(P.lcg, x);
                     sum += x;
                 }
-            }
-        } else if (HALVES) {
-            const uint32_t fb = (D < 32 || k < 32u) ? __builtin_amdgcn_ubfe(0xffffffffu, 0u, k) : 0xffffffffu;
-#pragma unroll
-            for (int d = 0; d < D; ++d) {
-                x = g * x + 2ull;
-                uint32_t f = __builtin_amdgcn_ubfe(fb, static_cast<uint32_t>(d), 1u);
-                // hides that f <= 1, so that each product-sum stays one
-                // v_mad_u64_u32 (not a 32-bit multiply and a 64-bit add)
-                asm("" : "+v"(f));
-                sum += static_cast<uint64_t>(static_cast<uint32_t>(x)) * f;
-                hsum += static_cast<uint64_t>(static_cast<uint32_t>(x >> 32)) * f;
-            }
-        } else {
-            // the state may run past the end of the stream (it is not
-            // stored); only the checksum is masked
-#pragma unroll
-            for (int d = 0; d < D; ++d) {
-                x = draw_step<M63C1>(P.lcg, x, g);
+            } else {
+                // the state may run past the end of the stream (it is not
+                // stored); only the checksum is masked
+                x = lcg_next(P.lcg, x);
                 if (static_cast<uint32_t>(d) < k) sum += x;
             }
         }
@@ -270,30 +226,192 @@ __global__ void __launch_bounds__(256) k_draw(DrawParams P) {
     }
 }
 
-template <int MODE, int D, bool M63C1>
-static hipError_t launch_draw_t(const DrawParams& p, hipStream_t st, int blocks) {
-    if (p.state != nullptr)
-        hipLaunchKernelGGL((k_draw<MODE, D, true, M63C1>), dim3(blocks), dim3(256), 0, st, p);
-    else
-        hipLaunchKernelGGL((k_draw<MODE, D, false, M63C1>), dim3(blocks), dim3(256), 0, st, p);
-    return hipGetLastError();
+// ------------------------------------------------------------------ round-aligned kernel
+
+// Ring entry of the round-aligned kernel: the stream's state h steps before
+// its start, its initial sum (minus its h leading outputs), its number of
+// whole rounds and the parity mask of its first round.
+struct __align__(16) RoundEntry {
+    uint64_t y;
+    uint64_t s;
+    uint32_t rounds;
+    uint32_t pm;
+    uint64_t pad;
+};
+
+// The ring entry of a stream with start state x0 and n draws.
+template <int D>
+__device__ __forceinline__ RoundEntry round_entry(const AlignEntry* al, uint64_t x0, uint32_t n) {
+    const uint32_t q = n / static_cast<uint32_t>(D);
+    const uint32_t r = n - q * static_cast<uint32_t>(D);
+    const uint32_t h = r ? static_cast<uint32_t>(D) - r : 0u;
+    const AlignEntry e = al[h];
+    RoundEntry t;
+    t.y = e.a * x0 + e.b;
+    t.s = e.na * x0 + e.nb;
+    t.rounds = q + (r ? 1u : 0u);
+    // slot d of a round leaves its top bit at position D - 1 - d: the first
+    // round counts the slots d >= h only (a 64-bit shift: D - h may be 32)
+    t.pm = static_cast<uint32_t>((1ull << (static_cast<uint32_t>(D) - h)) - 1ull);
+    t.pad = 0;
+    return t;
 }
 
-template <int MODE, bool M63C1>
-static hipError_t launch_draw_d(const DrawParams& p, hipStream_t st, int blocks, int d) {
-    // rounds of 20 draws: measured 1% faster than 16 or 24, 3% faster than 12 or 32
-    switch (d) {
-        case 8: return launch_draw_t<MODE, 8, M63C1>(p, st, blocks);
-        case 16: return launch_draw_t<MODE, 16, M63C1>(p, st, blocks);
-        case 32: return launch_draw_t<MODE, 32, M63C1>(p, st, blocks);
-        default: return launch_draw_t<MODE, 20, M63C1>(p, st, blocks);
+// Seed + draw for m = 63 or 64 and an odd multiplier.  The lane keeps the
+// state Y modulo 2^64 with no mask, Y <- g Y + c: its low m bits are the
+// LCG's state X (2^m divides 2^64), so X_n = Y_n mod 2^m.  Then
+//   sum of X_n = sum of Y_n - 2^63 (number of top bits set)   (m = 63)
+// modulo 2^64, and only the parity of that number matters: a draw slot is
+// the step (one 64-bit multiply-add on 32-bit halves, two cross products, a
+// three-way add), one 64-bit add into the sum and (m = 63) one funnel shift
+// that collects the top bit, with no mask.  Rounds carry no per-slot mask
+// either: each stream starts h steps early (the rewound state of its ring
+// entry) so that its last draw ends a round, its initial sum removes its h
+// leading outputs, and its first round's parity mask drops their top bits.
+// Work distribution, ring and refill as in the generic kernel; the ring
+// entries are computed when a batch of 64 streams is seeded (all lanes).
+template <int MODE, int D, bool STORE_STATE, bool TOPBIT>
+__global__ void __launch_bounds__(256) k_draw_rounds(DrawParams P) {
+    __shared__ RoundEntry s_ring[4][128];
+    __shared__ AlignEntry s_align[kMaxRound];
+    if (threadIdx.x < static_cast<uint32_t>(D)) s_align[threadIdx.x] = P.align[threadIdx.x];
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint64_t wave = static_cast<uint64_t>(blockIdx.x) * (blockDim.x >> 6) + wib;
+    const uint64_t nwaves = static_cast<uint64_t>(gridDim.x) * (blockDim.x >> 6);
+    const uint64_t lo = wave * P.n / nwaves;
+    const uint32_t nw = static_cast<uint32_t>((wave + 1) * P.n / nwaves - lo);
+    const uint64_t g = P.lcg.g, c = P.lcg.c;
+    RoundEntry* ring = s_ring[wib];
+    char* const cbase = reinterpret_cast<char*>(P.checksum + lo);
+    const uint64_t lane_m = static_cast<uint64_t>(lane) * kMurmurM;
+    constexpr uint32_t kFull = (D >= 32) ? 0xffffffffu : ((1u << (D & 31)) - 1u);
+
+    uint32_t next = 0, filled = 128;
+    uint32_t c_next = 0;
+    StrideLanes sl{};
+    uint64_t sbase = 0;
+    if (MODE == SEED_STRIDE) {
+        sl = stride_lanes(P.seed, lane);
+        sbase = stream_start(P.lcg, P.seed, lo);
     }
+    {
+        const uint32_t ja = lane, jb = 64u + lane, jn = 128u + lane;
+        const uint32_t na = (ja < nw) ? P.count[lo + ja] : 0u;
+        const uint32_t nb = (jb < nw) ? P.count[lo + jb] : 0u;
+        uint64_t xa, xb;
+        if (MODE == SEED_STRIDE) {
+            const uint64_t b1 = affine_apply(sl.g64, sl.c64, P.lcg.mask, sbase);
+            xa = affine_apply(sl.g, sl.c, P.lcg.mask, sbase);
+            xb = affine_apply(sl.g, sl.c, P.lcg.mask, b1);
+            sbase = affine_apply(sl.g64, sl.c64, P.lcg.mask, b1);
+        } else {
+            xa = (ja < nw) ? lane_start<MODE>(P, lo, lane, lane_m) : 0ull;
+            xb = (jb < nw) ? lane_start<MODE>(P, lo + 64u, lane, lane_m) : 0ull;
+        }
+        ring[ja] = round_entry<D>(s_align, xa, na);
+        ring[jb] = round_entry<D>(s_align, xb, nb);
+        if (jn < nw) c_next = P.count[lo + jn];
+    }
+
+    uint64_t y = 0, s = 0;
+    uint32_t sid = 0, rounds = 0, pm = 0, par = 0, bits = 0;
+    bool active = false;
+    for (;;) {
+        if (active && rounds == 0) {
+            uint64_t chk = s;
+            if (TOPBIT) chk += static_cast<uint64_t>(par & 1u) << 63;
+            *reinterpret_cast<uint64_t*>(cbase + (sid << 3)) = chk;
+            if (STORE_STATE) P.state[lo + sid] = y & P.lcg.mask;
+            active = false;
+        }
+        next = __builtin_amdgcn_readfirstlane(next);
+        const uint64_t need = __builtin_amdgcn_ballot_w64(!active);
+        const uint32_t left = nw - next;
+        if (need != 0 && left != 0) {
+            const uint32_t nneed = static_cast<uint32_t>(__popcll(need));
+            const uint32_t take = __builtin_amdgcn_readfirstlane(nneed < left ? nneed : left);
+            const uint32_t rank = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(need >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(need), 0u));
+            if (!active && rank < take) {
+                const RoundEntry r = ring[(next + rank) & 127u];
+                y = r.y;
+                s = r.s;
+                rounds = r.rounds;
+                pm = r.pm;
+                par = 0;
+                sid = next + rank;
+                if (rounds == 0) {
+                    // no draws: the checksum is 0 and the state its start
+                    *reinterpret_cast<uint64_t*>(cbase + (sid << 3)) = 0ull;
+                    if (STORE_STATE) P.state[lo + sid] = y;
+                } else {
+                    active = true;
+                }
+            }
+            next = __builtin_amdgcn_readfirstlane(next + take);
+            if (filled - next < 64u && filled < nw) {
+                const uint32_t j = filled + lane;
+                uint64_t x0;
+                if (MODE == SEED_STRIDE) {
+                    x0 = affine_apply(sl.g, sl.c, P.lcg.mask, sbase);
+                    sbase = affine_apply(sl.g64, sl.c64, P.lcg.mask, sbase);
+                } else {
+                    x0 = (j < nw) ? lane_start<MODE>(P, lo + filled, lane, lane_m) : 0ull;
+                }
+                ring[j & 127u] = round_entry<D>(s_align, x0, c_next);   // the one wait on vector memory per 64 streams
+                const uint32_t jn = j + 64u;
+                c_next = (jn < nw) ? P.count[lo + jn] : 0u;
+                filled += 64u;
+            }
+        }
+        if (__builtin_amdgcn_ballot_w64(active) == 0) break;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            y = g * y + c;
+            s += y;
+            if (TOPBIT) bits = __builtin_amdgcn_alignbit(bits, static_cast<uint32_t>(y >> 32), 31u);
+        }
+        if (TOPBIT) {
+            par = static_cast<uint32_t>(__builtin_popcount(bits & pm)) + par;
+            pm = kFull;
+        }
+        rounds -= 1u;
+    }
+}
+
+template <int MODE, int D>
+static hipError_t launch_draw_t(const DrawParams& p, hipStream_t st, int blocks) {
+    const bool rounds = p.align != nullptr;
+    const bool top = p.lcg.m == 63;
+    if (p.state != nullptr) {
+        if (!rounds)
+            hipLaunchKernelGGL((k_draw<MODE, D, true>), dim3(blocks), dim3(256), 0, st, p);
+        else if (top)
+            hipLaunchKernelGGL((k_draw_rounds<MODE, D, true, true>), dim3(blocks), dim3(256), 0, st, p);
+        else
+            hipLaunchKernelGGL((k_draw_rounds<MODE, D, true, false>), dim3(blocks), dim3(256), 0, st, p);
+    } else {
+        if (!rounds)
+            hipLaunchKernelGGL((k_draw<MODE, D, false>), dim3(blocks), dim3(256), 0, st, p);
+        else if (top)
+            hipLaunchKernelGGL((k_draw_rounds<MODE, D, false, true>), dim3(blocks), dim3(256), 0, st, p);
+        else
+            hipLaunchKernelGGL((k_draw_rounds<MODE, D, false, false>), dim3(blocks), dim3(256), 0, st, p);
+    }
+    return hipGetLastError();
 }
 
 template <int MODE>
 static hipError_t launch_draw_m(const DrawParams& p, hipStream_t st, int blocks, int d) {
-    const bool m63c1 = p.lcg.m == 63 && p.lcg.c == 1;
-    return m63c1 ? launch_draw_d<MODE, true>(p, st, blocks, d) : launch_draw_d<MODE, false>(p, st, blocks, d);
+    switch (d) {
+        case 8: return launch_draw_t<MODE, 8>(p, st, blocks);
+        case 16: return launch_draw_t<MODE, 16>(p, st, blocks);
+        case 24: return launch_draw_t<MODE, 24>(p, st, blocks);
+        case 32: return launch_draw_t<MODE, 32>(p, st, blocks);
+        default: return launch_draw_t<MODE, 20>(p, st, blocks);
+    }
 }
 
 hipError_t launch_draw(const DrawParams& p, int seed_mode, hipStream_t st, int blocks_per_cu, int round) {

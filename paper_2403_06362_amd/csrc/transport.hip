@@ -54,24 +54,14 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t st) 
     return hipGetLastError();
 }
 
-__device__ __forceinline__ void end_history(LaneCounters& cnt, int end, uint32_t hdraws, uint64_t stride_q) {
-    cnt.histories++;
-    cnt.draws += hdraws;
-    if (hdraws > cnt.max_draws) cnt.max_draws = hdraws;
-    if (stride_q != 0 && hdraws > stride_q) cnt.over_stride++;
-    cnt.leak_left += (end == END_LEAK_LEFT);
-    cnt.leak_right += (end == END_LEAK_RIGHT);
-    cnt.absorbed += (end == END_ABSORBED);
-    cnt.census += (end == END_CENSUS);
-}
-
-// LDS layout: [tally: copies x max_slice x 2 u64][edges][sig][scat f64][bin i32][tedges]
+// LDS layout: [tally: copies x max_slice x 2 u64][edges][sig][rsig][scat f64][bin i32][tedges]
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~static_cast<size_t>(15); }
 
 size_t transport_lds_bytes(const TransportParams& p, int f32) {
     const size_t rs = f32 ? sizeof(float) : sizeof(double);
     size_t b = align16(static_cast<size_t>(p.tally_copies) * p.max_slice * 2 * sizeof(uint64_t));
     b += align16((p.max_cells + 1) * rs);
+    b += align16(p.max_cells * rs);
     b += align16(p.max_cells * rs);
     b += align16(p.max_cells * sizeof(double));
     b += align16(p.max_cells * sizeof(int32_t));
@@ -82,6 +72,18 @@ size_t transport_lds_bytes(const TransportParams& p, int f32) {
 size_t transport_static_lds_bytes(int block) {
     return static_cast<size_t>(kStrideDigits) * kStrideRadix * 2 * sizeof(uint64_t) +
            static_cast<size_t>(block / 64) * 128 * sizeof(uint64_t) + 256;
+}
+
+// Phase of a lane's history slot.
+enum : int {
+    PH_EMPTY = 0,   // no history: refilled at the next collision pass
+    PH_GEOM = 1,    // has a flight: takes geometry steps
+    PH_COLL = 2,    // stands at a collision site
+    PH_NEW = 3      // a new history or a scattered particle: samples its next flight
+};
+
+__device__ __forceinline__ uint32_t wave_count(bool c) {
+    return static_cast<uint32_t>(__popcll(__builtin_amdgcn_ballot_w64(c)));
 }
 
 template <bool F32, bool TIMED, int H, int BLOCK>
@@ -100,13 +102,14 @@ __global__ void __launch_bounds__(BLOCK) k_transport(TransportParams P) {
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63u;
     const uint32_t wid = tid >> 6;
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
     uint64_t* tally_all = reinterpret_cast<uint64_t*>(smem);
     size_t off = align16(static_cast<size_t>(P.tally_copies) * P.max_slice * 2 * sizeof(uint64_t));
     R* l_edge = reinterpret_cast<R*>(smem + off);
     off += align16((P.max_cells + 1) * sizeof(R));
     R* l_sig = reinterpret_cast<R*>(smem + off);
+    off += align16(P.max_cells * sizeof(R));
+    R* l_rsig = reinterpret_cast<R*>(smem + off);
     off += align16(P.max_cells * sizeof(R));
     double* l_scat = reinterpret_cast<double*>(smem + off);
     off += align16(P.max_cells * sizeof(double));
@@ -149,7 +152,9 @@ __global__ void __launch_bounds__(BLOCK) k_transport(TransportParams P) {
         if (static_cast<int32_t>(U.problem) != cur_problem) {
             for (uint32_t i = tid; i <= PR.n_cells; i += BLOCK) l_edge[i] = g_edge[PR.edge_off + i];
             for (uint32_t i = tid; i < PR.n_cells; i += BLOCK) {
-                l_sig[i] = g_sig[PR.cell_off + i];
+                const R sg = g_sig[PR.cell_off + i];
+                l_sig[i] = sg;
+                l_rsig[i] = recip_refined(sg);
                 l_scat[i] = P.scat64[PR.cell_off + i];
                 l_bin[i] = P.cbin[PR.cell_off + i];
             }
@@ -164,6 +169,7 @@ __global__ void __launch_bounds__(BLOCK) k_transport(TransportParams P) {
         CellsLds<F32> C;
         C.edge = l_edge;
         C.sig = l_sig;
+        C.rsig = l_rsig;
         C.scat = l_scat;
         C.bin = l_bin;
         C.tedge = l_tedge;
@@ -177,112 +183,137 @@ __global__ void __launch_bounds__(BLOCK) k_transport(TransportParams P) {
         S.first_index = PR.first_index;
         S.table = s_skip;
         uint64_t* tally = tally_all + static_cast<size_t>(copy) * P.max_slice * 2;
+        const uint64_t stride_q = PR.stride_q;
 
-        LaneCounters cnt;
         Particle<F32> p[H];
-        bool alive[H], pend[H], pcoll[H];
+        int ph[H];
 #pragma unroll
-        for (int h = 0; h < H; ++h) alive[h] = pend[h] = pcoll[h] = false;
+        for (int h = 0; h < H; ++h) ph[h] = PH_EMPTY;
+        // wave-uniform counts of the unit (scalar registers)
+        uint64_t w_events = 0, w_colls = 0;
+        uint32_t w_ll = 0, w_lr = 0, w_abs = 0, w_cen = 0;
+        // per lane, over the histories this lane ended (their total draws
+        // follow from the wave counts: one for each history's first flight,
+        // one per collision for the absorption test and two more per scatter)
+        uint32_t l_maxd = 0, l_over = 0;
         bool exhausted = false;   // wave-uniform: no history of the unit left for this wave
         // the wave's ring of seeded histories (positions & 127): [r_next, r_filled)
         uint64_t* ring = s_ring[__builtin_amdgcn_readfirstlane(wid)];
         uint32_t r_next = 0, r_filled = 0;   // wave-uniform
         bool unit_taken = false;             // wave-uniform: s_next has passed the unit's end
 
-        // Each iteration: refill idle lanes; geometry step for the lanes not
-        // waiting on a collision; then, once enough lanes wait (or none can
-        // move), the collision phase for all waiting lanes together
-        // (collision draws and the next flight, the expensive, rarer part).
-        // Every particle still runs its own operations in its own order.
+        // Each iteration: one geometry step for every lane with a flight;
+        // then, once enough lanes wait at a collision site (or stand empty
+        // while histories remain), or none can move, the collision pass:
+        // empty lanes take new histories, and every waiting particle runs its
+        // collision draws and samples its next flight.  Every particle still
+        // runs its own operations in its own order.
         for (;;) {
 #pragma unroll
             for (int h = 0; h < H; ++h) {
-                if (!exhausted) {
-                    const uint64_t need = __ballot(!alive[h]);
-                    if (need != 0) {
-                        const uint32_t nneed = static_cast<uint32_t>(__popcll(need));
-                        if (r_filled - r_next < nneed && !unit_taken) {
-                            // seed the next 64 histories of the unit at once
-                            // (one per lane), so that a refill is an LDS read
-                            uint32_t base = 0;
-                            if (lane == 0) base = atomicAdd(&s_next, 64u);
-                            base = __shfl(base, 0);
-                            if (base + 64u >= U.count) unit_taken = true;
-                            const uint32_t got = base < U.count ? (U.count - base < 64u ? U.count - base : 64u) : 0u;
-                            if (lane < got) ring[(r_filled + lane) & 127u] = stream_start(P.lcg, S, U.j0 + base + lane);
-                            r_filled += got;
-                            __builtin_amdgcn_wave_barrier();
-                        }
-                        const uint32_t avail = r_filled - r_next;
-                        const uint32_t take = avail < nneed ? avail : nneed;
-                        if (!alive[h]) {
-                            const uint32_t rank = static_cast<uint32_t>(__popcll(need & lt_mask));
-                            if (rank < take) {
-                                init_particle_at<F32, TIMED>(p[h], C, ring[(r_next + rank) & 127u]);
-                                alive[h] = true;
-                                pend[h] = true;     // waits for its first flight
-                                pcoll[h] = false;
-                            }
-                        }
-                        r_next += take;
-                        if (unit_taken && r_next == r_filled) exhausted = true;
-                        __builtin_amdgcn_wave_barrier();
-                    }
-                }
-            }
-            bool any = false;
-#pragma unroll
-            for (int h = 0; h < H; ++h) any = any || alive[h];
-            if (__ballot(any) == 0) break;
-#pragma unroll
-            for (int h = 0; h < H; ++h) {
-                if (alive[h] && !pend[h]) {
-                    const int r = geom_step<F32, TIMED>(p[h], C, tally, cnt);
+                const bool g = ph[h] == PH_GEOM;
+                w_events += wave_count(g);
+                int r = END_NONE;
+                if (g) {
+                    r = geom_step<F32, TIMED>(p[h], C, tally);
                     if (r == STEP_COLLIDE) {
-                        pend[h] = true;
-                        pcoll[h] = true;
+                        ph[h] = PH_COLL;
                     } else if (r != END_NONE) {
-                        end_history(cnt, r, p[h].hdraws, PR.stride_q);
-                        alive[h] = false;
+                        ph[h] = PH_EMPTY;
+                        const uint32_t d = p[h].hdraws;
+                        l_maxd = d > l_maxd ? d : l_maxd;
+                        if (stride_q != 0 && d > stride_q) l_over++;
                     }
                 }
+                if (__builtin_amdgcn_ballot_w64(r > END_NONE) != 0) {
+                    w_ll += wave_count(r == END_LEAK_LEFT);
+                    w_lr += wave_count(r == END_LEAK_RIGHT);
+                    if (TIMED) w_cen += wave_count(r == END_CENSUS);
+                }
             }
-            uint32_t npend = 0, nfree = 0;
+            uint32_t nwait = 0, ngeom = 0;
 #pragma unroll
             for (int h = 0; h < H; ++h) {
-                npend += static_cast<uint32_t>(__popcll(__ballot(alive[h] && pend[h])));
-                nfree += static_cast<uint32_t>(__popcll(__ballot(alive[h] && !pend[h])));
+                nwait += wave_count(ph[h] == PH_COLL || (ph[h] == PH_EMPTY && !exhausted));
+                ngeom += wave_count(ph[h] == PH_GEOM);
             }
-            if (npend > 0 && (npend >= P.coll_batch || nfree == 0)) {
+            if (nwait < P.coll_batch && ngeom != 0) continue;
+
+            // collision pass: refill the empty lanes first
 #pragma unroll
-                for (int h = 0; h < H; ++h) {
-                    if (alive[h] && pend[h]) {
-                        int r = END_NONE;
-                        if (pcoll[h]) r = collide<F32>(p[h], C, P.lcg, cnt);
-                        if (r != END_NONE) {
-                            end_history(cnt, r, p[h].hdraws, PR.stride_q);
-                            alive[h] = false;
-                        } else {
-                            sample_tau<F32>(p[h], P.lcg);
-                        }
-                        pend[h] = false;
-                        pcoll[h] = false;
+            for (int h = 0; h < H; ++h) {
+                if (exhausted) continue;
+                const uint64_t need = __builtin_amdgcn_ballot_w64(ph[h] == PH_EMPTY);
+                if (need == 0) continue;
+                const uint32_t nneed = static_cast<uint32_t>(__popcll(need));
+                if (r_filled - r_next < nneed && !unit_taken) {
+                    // seed the next 64 histories of the unit at once (one per
+                    // lane), so that a refill is an LDS read
+                    uint32_t base = 0;
+                    if (lane == 0) base = atomicAdd(&s_next, 64u);
+                    base = __shfl(base, 0);
+                    if (base + 64u >= U.count) unit_taken = true;
+                    const uint32_t got = base < U.count ? (U.count - base < 64u ? U.count - base : 64u) : 0u;
+                    if (lane < got) ring[(r_filled + lane) & 127u] = stream_start(P.lcg, S, U.j0 + base + lane);
+                    r_filled += got;
+                    __builtin_amdgcn_wave_barrier();
+                }
+                const uint32_t avail = r_filled - r_next;
+                const uint32_t take = avail < nneed ? avail : nneed;
+                if (ph[h] == PH_EMPTY) {
+                    const uint32_t rank = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(need >> 32),
+                                                                    __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(need), 0u));
+                    if (rank < take) {
+                        init_particle_at<F32, TIMED>(p[h], C, ring[(r_next + rank) & 127u]);
+                        ph[h] = PH_NEW;
                     }
+                }
+                r_next += take;
+                if (unit_taken && r_next == r_filled) exhausted = true;
+                __builtin_amdgcn_wave_barrier();
+            }
+            uint32_t nlive = 0;
+#pragma unroll
+            for (int h = 0; h < H; ++h) nlive += wave_count(ph[h] != PH_EMPTY);
+            if (nlive == 0) break;
+#pragma unroll
+            for (int h = 0; h < H; ++h) {
+                const bool cl = ph[h] == PH_COLL;
+                w_colls += wave_count(cl);
+                bool absorbed = false;
+                if (cl) {
+                    if (collide<F32>(p[h], C, P.lcg) != END_NONE) {
+                        absorbed = true;
+                        ph[h] = PH_EMPTY;
+                        const uint32_t d = p[h].hdraws;
+                        l_maxd = d > l_maxd ? d : l_maxd;
+                        if (stride_q != 0 && d > stride_q) l_over++;
+                    } else {
+                        ph[h] = PH_NEW;
+                    }
+                }
+                w_abs += wave_count(absorbed);
+                if (ph[h] == PH_NEW) {
+                    sample_tau<F32>(p[h], P.lcg);
+                    ph[h] = PH_GEOM;
                 }
             }
         }
 
-        // unit diagnostics: per-lane counters into LDS
-        atomicAdd(&s_diag[D_HISTORIES], static_cast<unsigned long long>(cnt.histories));
-        atomicAdd(&s_diag[D_LEAK_LEFT], static_cast<unsigned long long>(cnt.leak_left));
-        atomicAdd(&s_diag[D_LEAK_RIGHT], static_cast<unsigned long long>(cnt.leak_right));
-        atomicAdd(&s_diag[D_ABSORBED], static_cast<unsigned long long>(cnt.absorbed));
-        atomicAdd(&s_diag[D_CENSUS], static_cast<unsigned long long>(cnt.census));
-        atomicAdd(&s_diag[D_EVENTS], static_cast<unsigned long long>(cnt.events));
-        atomicAdd(&s_diag[D_COLLISIONS], static_cast<unsigned long long>(cnt.collisions));
-        atomicAdd(&s_diag[D_DRAWS], static_cast<unsigned long long>(cnt.draws));
-        atomicMax(&s_diag[D_MAX_DRAWS], static_cast<unsigned long long>(cnt.max_draws));
-        atomicAdd(&s_diag[D_OVER_STRIDE], static_cast<unsigned long long>(cnt.over_stride));
+        // unit diagnostics: the wave's counts and the lanes' into LDS
+        if (lane == 0) {
+            const unsigned long long ends = static_cast<unsigned long long>(w_ll) + w_lr + w_abs + w_cen;
+            atomicAdd(&s_diag[D_HISTORIES], ends);
+            atomicAdd(&s_diag[D_LEAK_LEFT], static_cast<unsigned long long>(w_ll));
+            atomicAdd(&s_diag[D_LEAK_RIGHT], static_cast<unsigned long long>(w_lr));
+            atomicAdd(&s_diag[D_ABSORBED], static_cast<unsigned long long>(w_abs));
+            atomicAdd(&s_diag[D_CENSUS], static_cast<unsigned long long>(w_cen));
+            atomicAdd(&s_diag[D_EVENTS], static_cast<unsigned long long>(w_events));
+            atomicAdd(&s_diag[D_COLLISIONS], static_cast<unsigned long long>(w_colls));
+            atomicAdd(&s_diag[D_DRAWS], ends + 3ull * w_colls - 2ull * w_abs);
+        }
+        atomicMax(&s_diag[D_MAX_DRAWS], static_cast<unsigned long long>(l_maxd));
+        atomicAdd(&s_diag[D_OVER_STRIDE], static_cast<unsigned long long>(l_over));
         __syncthreads();
 
         uint64_t* dst = P.partial + U.slot;

@@ -89,19 +89,25 @@ def test_draw_parity(M, orc, mode, n):
     assert np.array_equal(u64_np(chk)[:n], ref)
 
 
-@pytest.mark.parametrize("rnd", [8, 16, 20, 32])
-def test_draw_round_lengths(M, orc, monkeypatch, rnd):
-    """Every round length of the draw kernel (MCRNG_DRAW_ROUND), with counts
-    on either side of its multiples, a long stream, both seedings, with and
-    without final states (two kernel bodies), and the 48-bit generator with
-    c = 3 (the generic step): every checksum and state is the oracle's."""
+@pytest.mark.parametrize("generic", [0, 1])
+@pytest.mark.parametrize("rnd", [8, 16, 20, 24, 32])
+def test_draw_round_lengths(M, orc, monkeypatch, rnd, generic):
+    """Every round length of the draw kernels (MCRNG_DRAW_ROUND), the
+    round-aligned kernel of m = 63 and the generic one (MCRNG_DRAW_GENERIC),
+    with counts on either side of the round's multiples (the aligned kernel's
+    rewind of h = 0 .. D-1 steps), a long stream, both seedings, with and
+    without final states, and the 48-bit generator with c = 3 (always the
+    generic kernel): every checksum and state is the oracle's."""
     import torch
     monkeypatch.setenv("MCRNG_DRAW_ROUND", str(rnd))
+    monkeypatch.setenv("MCRNG_DRAW_GENERIC", str(generic))
     edge = [0, 1, 2, 7, 8, 9, 15, 16, 17, 19, 20, 21, 31, 32, 33, 63, 64, 65, 96, 97, 1 << 16, 3_000_001]
     counts = np.concatenate([np.array(edge, dtype=np.uint32), W.draw_counts(20_000, seed=rnd)])
     n = len(counts)
     m48 = W.Lcg(W.G_MCNP % (1 << 48), 3, 48)
-    for lcg, sd in ((LCG, W.hash_seeding()), (LCG, W.stride_seeding()), (m48, W.Seeding("stride", 5, 1000003, 0))):
+    m64 = W.Lcg(W.G_MCNP, 7, 64)   # the aligned kernel without the top-bit parity
+    for lcg, sd in ((LCG, W.hash_seeding()), (LCG, W.stride_seeding()), (m48, W.Seeding("stride", 5, 1000003, 0)),
+                    (m64, W.hash_seeding())):
         ref = orc.seed_and_draw(lcg, sd, counts, threads=8)
         states = orc.init_streams(lcg, sd, n)
         orc.seed_and_draw(lcg, None, counts, states=states)
