@@ -50,11 +50,10 @@ Also reported, each timed separately after the headline loop:
                 long-chain and the multi-region slabs (bounded samples), and
                 samples of the pulse problems (the only part of the
                 benchmark that uses the oracle)
-With --full, the slower extras are added (the pulse event-based schedule on
-few sources; nothing the headline or the rooflines depend on).
+--only selects legs after the draw legs (for profiling one kernel's workload).
 
-Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 10] [--full] [--no-cpu]
-                       [--no-transport] [--no-pulse] [--no-autotune] [--copy-probe]
+Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 10] [--no-cpu] [--no-transport]
+                       [--no-slab] [--no-pulse] [--only LEGS] [--no-autotune] [--copy-probe]
 """
 from __future__ import annotations
 
@@ -332,11 +331,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--full", action="store_true", help="add the slower extras (few-source event-based pulse runs)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-transport", action="store_true", help="headline draw workload only (no slab or pulse legs)")
     ap.add_argument("--no-pulse", action="store_true", help="skip the pulse-problem legs")
     ap.add_argument("--no-slab", action="store_true", help="skip the slab legs (long chain, batched, multi-region)")
+    ap.add_argument("--only", default="",
+                    help="comma-separated subset of the legs after the draw legs: long_chain, batched, "
+                         "multi_region, pulse (schedules), study (the normality study), pulse_pc")
     ap.add_argument("--no-autotune", action="store_true",
                     help="long-chain legs with the default launch options (no autotuner runs)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -346,6 +347,12 @@ def main():
         print("bench.py runs on exactly one GPU (--gpus 1); several GPUs are not supported "
               "(the path would shard histories by first_index and all-reduce the integer "
               "tallies).", file=sys.stderr)
+        sys.exit(2)
+
+    only = set(x for x in args.only.split(",") if x)
+    unknown = only - {"long_chain", "batched", "multi_region", "pulse", "study", "pulse_pc"}
+    if unknown:
+        print("bench.py: unknown legs %s" % ",".join(sorted(unknown)), file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -430,9 +437,14 @@ def main():
         "roofline": roofline,
     }
 
+    def want(leg, slab):
+        if args.no_transport or (slab and args.no_slab) or (not slab and args.no_pulse):
+            return False
+        return not only or leg in only
+
     if not args.no_transport:
         ctx = M.Context(0)
-    if not args.no_transport and not args.no_slab:
+    if want("long_chain", True):
         prob = W.long_chain()
         # launch options from the library's autotuner, once per precision on
         # the hash-seeded problem (the stride leg reuses the FP64 choice)
@@ -467,10 +479,13 @@ def main():
                                             {k: d32[k] for k in ("histories", "events", "collisions", "absorbed")})
         out["histories_per_s"] = legs["hash_fp64"]["histories_per_s"]
         out["transport"] = tr
+    if want("batched", True):
         out["batched"] = batched_leg(M, W, torch, lcg, ctx, args.no_autotune)
+    if want("multi_region", True):
         out["multi_region"] = multi_region_leg(M, W, torch, lcg, ctx)
-    if not args.no_transport and not args.no_pulse:
-        out["pulse"] = pulse_leg(M, W, torch, lcg, ctx, args.full)
+    if want("pulse", False) or want("study", False):
+        out["pulse"] = pulse_leg(M, W, torch, lcg, ctx, schedules=want("pulse", False), study=want("study", False))
+    if want("pulse_pc", False):
         out["pulse_population_control"] = pulse_pc_leg(M, W, torch, lcg, ctx)
     if not args.no_transport:
         ctx.close()
@@ -637,21 +652,20 @@ def pulse_pc_leg(M, W, torch, lcg, ctx):
     return out
 
 
-def pulse_leg(M, W, torch, lcg, ctx, full=False):
+def pulse_leg(M, W, torch, lcg, ctx, schedules=True, study=True):
     """The paper's test problem: a pulse in an infinite medium (c = 0.4,
     nu = 2.75, census t = 20), 1000 batches x 1000 sources; secondaries
     seeded on demand by hashing (eq. 5) or drawing from their source's
     stride stream.  Then the paper's normality study at full size: 30
     repetitions x 1000 batches, Shapiro-Wilk on each of the 20 center-flux
     time points (600 tests per seeding)."""
-    from scipy import stats
     out = {"workload": "pulse at x=t=0 in an infinite medium: sigma_t=1, c=0.4, nu=2.75, census t=20, "
                        "collision estimator on x in [-1,1], 20 unit time bins, 1000 batches x 1000 sources",
            "few_sources_workload": "the same medium, one batch of 4096 sources run to t=60 "
                                    "(60 unit time bins, population about 400-fold)"}
     p = W.pulse(W.hash_seeding())
     few = W.pulse_few_sources()
-    for tag, base in (("", p), ("few_sources_", few)):
+    for tag, base in ((("", p), ("few_sources_", few)) if schedules else ()):
         for name, prob, sched in (("hash_bank", base, M.PULSE_BANK), ("hash_event", base, M.PULSE_EVENT),
                                   ("hash_family", base, M.PULSE_FAMILY),
                                   ("stride_family", base.with_(seeding=W.stride_seeding()), M.PULSE_FAMILY)):
@@ -662,6 +676,9 @@ def pulse_leg(M, W, torch, lcg, ctx, full=False):
                                "collisions_per_s": d["collisions"] / (ms * 1e-3),
                                "draws_per_s": d["draws"] / (ms * 1e-3),
                                "collisions_per_source": d["collisions"] / d["sources"], "max_draws": d["max_draws"]}
+    if not schedules:
+        out["normality_study"] = _study(M, W, torch, lcg, ctx, out) if study else {}
+        return out
     out["hash_bank_over_stride_family"] = out["stride_family"]["ms"] / out["hash_bank"]["ms"]
     out["few_sources_hash_bank_over_stride_family"] = (out["few_sources_stride_family"]["ms"] /
                                                        out["few_sources_hash_bank"]["ms"])
@@ -670,6 +687,17 @@ def pulse_leg(M, W, torch, lcg, ctx, full=False):
     out["few_sources_hash_event_over_stride_family"] = (out["few_sources_stride_family"]["ms"] /
                                                         out["few_sources_hash_event"]["ms"])
 
+    if study:
+        out["normality_study"] = _study(M, W, torch, lcg, ctx, out)
+    return out
+
+
+def _study(M, W, torch, lcg, ctx, out):
+    """The paper's normality study at full size: 30 repetitions x 1000
+    batches x 1000 sources per seeding, Shapiro-Wilk on each of the 20
+    center-flux time points (600 tests per seeding); the hash run's counts
+    give the pulse roofline."""
+    from scipy import stats
     study = {}
     for kind in ("hash", "stride"):
         sd = W.hash_seeding() if kind == "hash" else W.stride_seeding()
@@ -690,8 +718,7 @@ def pulse_leg(M, W, torch, lcg, ctx, full=False):
                                             {"flights": flights, "collisions": d["collisions"],
                                              "scatters": d["scatters"], "secondaries": d["secondaries"]})
     study["paper_fails_of_600"] = {"stride": 369, "hash": 339}
-    out["normality_study"] = study
-    return out
+    return study
 
 
 def _rate(fn, units):
@@ -746,7 +773,7 @@ def cpu_baseline(oracle, W, lcg, counts, chk_hash, chk_stride, out):
                         "all_threads_histories_per_s": ha, "threads": threads,
                         "all_threads_sample": "first %d histories" % nall, "gpu_over_all_threads": gpu / ha}
         res["transport"] = tr
-    if "pulse" in out:
+    if "pulse" in out and "hash_bank" in out["pulse"]:
         sample = W.pulse(W.hash_seeding(), n_batches=64)
         log("cpu baseline: oracle pulse problem, 64 batches")
         rate, _ = _rate(lambda: oracle.pulse(sample, lcg, threads=threads), sample.n_sources)
@@ -757,7 +784,8 @@ def cpu_baseline(oracle, W, lcg, counts, chk_hash, chk_stride, out):
         rate, _ = _rate(lambda: oracle.pulse_pc(sample, lcg, threads=threads), sample.n_sources)
         res["pulse_population_control"] = {
             "sources_per_s": rate, "threads": threads, "sample": "64 batches x 1000 sources, census every 5",
-            "gpu_over_cpu": out["pulse_population_control"]["sources_per_s"] / rate}
+            "gpu_over_cpu": out["pulse_population_control"]["sources_per_s"] / rate} \
+            if "pulse_population_control" in out else None
     return res
 
 

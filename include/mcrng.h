@@ -307,7 +307,7 @@ float mcrng_last_run_ms(mcrng_ctx *ctx);
  * Host array: time_edges, n_time_bins + 1 values, finite, >= 0, strictly
  * increasing. */
 typedef struct {
-    double sigma_t;              /* > 0 */
+    double sigma_t;              /* in [2^-64, 2^64] */
     double scatter;              /* in [0, 1] */
     double multiplicity;         /* nu in [0, 14] */
     double x_lo, x_hi;           /* finite, x_lo < x_hi */

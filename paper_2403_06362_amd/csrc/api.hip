@@ -313,7 +313,7 @@ extern "C" int mcrng_draw(const mcrng_lcg* lcg, const mcrng_seeding* seeding, ui
         if (rc < 0) return rc;
         mode = p.seed.kind;
     }
-    int bpc = 16, round = 20, generic = 0;
+    int bpc = 12, round = 20, generic = 0;
     if (const char* env = getenv("MCRNG_DRAW_BLOCKS_PER_CU")) bpc = atoi(env);
     if (const char* env = getenv("MCRNG_DRAW_ROUND")) round = atoi(env);
     if (const char* env = getenv("MCRNG_DRAW_GENERIC")) generic = atoi(env);
@@ -1243,7 +1243,8 @@ extern "C" int mcrng_uniforms(const mcrng_lcg* lcg, const mcrng_seeding* seeding
 
 static int validate_pulse(const mcrng_pulse_problem* P) {
     if (!P) return fail(MCRNG_EINVAL, "problem is NULL");
-    if (!(P->sigma_t > 0.0) || !std::isfinite(P->sigma_t)) return fail(MCRNG_EINVAL, "sigma_t must be finite and > 0");
+    if (!(P->sigma_t >= kMinSigma && P->sigma_t <= kMaxSigma))
+        return fail(MCRNG_EINVAL, "sigma_t must lie within [2^-64, 2^64]");
     if (!(P->scatter >= 0.0 && P->scatter <= 1.0)) return fail(MCRNG_EINVAL, "scatter must be in [0, 1]");
     if (!(P->multiplicity >= 0.0 && P->multiplicity <= 14.0))
         return fail(MCRNG_EINVAL, "multiplicity must be in [0, 14]");

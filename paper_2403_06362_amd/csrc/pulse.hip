@@ -86,14 +86,14 @@ __device__ __forceinline__ uint32_t pulse_flight(const PulseParams& P, PParticle
     if (DIR && p.has_mu) {
         mu = p.mu;
     } else {
-        p.X = lcg_next(L, p.X);
+        p.X = lcg_next_wide(L, p.X);
         mu = 2.0 * to_uniform(L, p.X) - 1.0;
         *draws += 1;
     }
-    p.X = lcg_next(L, p.X);
+    p.X = lcg_next_wide(L, p.X);
     const double tau = -fixed_log(to_uniform(L, p.X));
     *draws += 1;
-    const double s = tau / P.sigma_t;
+    const double s = quot(tau, P.sigma_t, recip_refined(P.sigma_t));   // the reciprocal is loop-invariant
     const double tn = p.t + s;
     if (!(tn < P.t_end)) {
         if (DIR) p.mu = mu;
@@ -108,10 +108,10 @@ __device__ __forceinline__ uint32_t pulse_flight(const PulseParams& P, PParticle
         *tally = static_cast<int64_t>(p.batch) * P.n_time_bins + p.tb;
         c.tallied++;
     }
-    p.X = lcg_next(L, p.X);
+    p.X = lcg_next_wide(L, p.X);
     *draws += 1;
     if (!(to_uniform(L, p.X) < P.scatter)) return PULSE_ABSORBED;
-    p.X = lcg_next(L, p.X);
+    p.X = lcg_next_wide(L, p.X);
     *draws += 1;
     *n = P.n_floor + (to_uniform(L, p.X) < P.nu_frac ? 1u : 0u);
     return PULSE_SCATTERED;

@@ -25,8 +25,8 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 def test_help_lists_the_flags():
     r = _run("--help")
     assert r.returncode == 0
-    for flag in ("--gpus", "--steps", "--warmup", "--full", "--no-cpu", "--no-transport", "--no-pulse",
-                 "--no-autotune", "--copy-probe"):
+    for flag in ("--gpus", "--steps", "--warmup", "--no-cpu", "--no-transport", "--no-slab", "--no-pulse",
+                 "--only", "--no-autotune", "--copy-probe"):
         assert flag in r.stdout, flag
 
 
@@ -35,6 +35,11 @@ def bench_module():
     sys.path.insert(0, ROOT)
     import bench
     return bench
+
+
+def test_unknown_leg_is_refused():
+    r = _run("--only", "long_chain,nonsense")
+    assert r.returncode == 2 and "nonsense" in r.stderr
 
 
 def test_traffic_is_reported_only_for_the_measured_source(bench_module):
