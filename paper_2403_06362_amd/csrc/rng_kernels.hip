@@ -315,30 +315,36 @@ __global__ void __launch_bounds__(256) k_draw_rounds(DrawParams P) {
         if (jn < nw) c_next = P.count[lo + jn];
     }
 
+    // a lane's stream is live while rounds > 0.  A lane whose stream ended
+    // has rounds == 0 at the top of the loop, stores its checksum there and
+    // then counts on downwards (idle lanes have rounds < 0 from the next
+    // round on; a stream of no draws is stored when it is taken and leaves
+    // the lane idle).  The wave ends once no lane is live and every stream
+    // of its range has been taken: a take that hands out only streams of no
+    // draws leaves no lane live, but streams may remain.
     uint64_t y = 0, s = 0;
-    uint32_t sid = 0, rounds = 0, pm = 0, par = 0, bits = 0;
-    bool active = false;
+    uint32_t sid = 0, pm = 0, par = 0, bits = 0;
+    int32_t rounds = -1;
     for (;;) {
-        if (active && rounds == 0) {
+        if (rounds == 0) {
             uint64_t chk = s;
             if (TOPBIT) chk += static_cast<uint64_t>(par & 1u) << 63;
             *reinterpret_cast<uint64_t*>(cbase + (sid << 3)) = chk;
             if (STORE_STATE) P.state[lo + sid] = y & P.lcg.mask;
-            active = false;
         }
         next = __builtin_amdgcn_readfirstlane(next);
-        const uint64_t need = __builtin_amdgcn_ballot_w64(!active);
+        const uint64_t need = __builtin_amdgcn_ballot_w64(rounds <= 0);
         const uint32_t left = nw - next;
         if (need != 0 && left != 0) {
             const uint32_t nneed = static_cast<uint32_t>(__popcll(need));
             const uint32_t take = __builtin_amdgcn_readfirstlane(nneed < left ? nneed : left);
             const uint32_t rank = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(need >> 32),
                                                             __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(need), 0u));
-            if (!active && rank < take) {
+            if (rounds <= 0 && rank < take) {
                 const RoundEntry r = ring[(next + rank) & 127u];
                 y = r.y;
                 s = r.s;
-                rounds = r.rounds;
+                rounds = static_cast<int32_t>(r.rounds);
                 pm = r.pm;
                 par = 0;
                 sid = next + rank;
@@ -346,8 +352,7 @@ __global__ void __launch_bounds__(256) k_draw_rounds(DrawParams P) {
                     // no draws: the checksum is 0 and the state its start
                     *reinterpret_cast<uint64_t*>(cbase + (sid << 3)) = 0ull;
                     if (STORE_STATE) P.state[lo + sid] = y;
-                } else {
-                    active = true;
+                    rounds = -1;
                 }
             }
             next = __builtin_amdgcn_readfirstlane(next + take);
@@ -366,7 +371,10 @@ __global__ void __launch_bounds__(256) k_draw_rounds(DrawParams P) {
                 filled += 64u;
             }
         }
-        if (__builtin_amdgcn_ballot_w64(active) == 0) break;
+        if (__builtin_amdgcn_ballot_w64(rounds > 0) == 0) {
+            if (next >= nw) break;
+            continue;
+        }
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             y = g * y + c;
@@ -377,7 +385,7 @@ __global__ void __launch_bounds__(256) k_draw_rounds(DrawParams P) {
             par = static_cast<uint32_t>(__builtin_popcount(bits & pm)) + par;
             pm = kFull;
         }
-        rounds -= 1u;
+        rounds -= 1;
     }
 }
 

@@ -122,6 +122,35 @@ def test_draw_round_lengths(M, orc, monkeypatch, rnd, generic):
                 assert np.array_equal(u64_np(st)[:n], states), (rnd, lcg.m, sd.kind)
 
 
+@pytest.mark.parametrize("pattern", ["zero_runs", "all_zero"])
+@pytest.mark.parametrize("kind", ["hash", "stride"])
+def test_draw_takes_of_only_empty_streams(M, orc, kind, pattern):
+    """A wave whose idle lanes are all handed streams of no draws, with no
+    lane live, still goes on to the rest of its range: 2^20 streams (waves of
+    more than 64 streams) in runs of 200 streams of no draws between single
+    streams of 3 draws, or no draws at all.  Checksums (0 for an empty
+    stream) and final states (its start) are the oracle's."""
+    import torch
+    n = 1 << 20
+    counts = np.zeros(n, dtype=np.uint32)
+    if pattern == "zero_runs":
+        counts[200::201] = 3
+    sd = W.hash_seeding() if kind == "hash" else W.stride_seeding()
+    ref = orc.seed_and_draw(LCG, sd, counts, threads=8)
+    states = orc.init_streams(LCG, sd, n)
+    orc.seed_and_draw(LCG, None, counts, states=states)
+    for with_state in (False, True):
+        say("draw of empty streams", kind, pattern, with_state)
+        chk = _empty_u64(n)
+        chk.view(torch.int64).fill_(0xFFFF)   # no stale zeros pass for a stream left unwritten
+        st = _empty_u64(n) if with_state else None
+        M.draw(LCG, sd, to_dev_u32(counts), chk, d_state=st)
+        torch.cuda.synchronize()
+        assert np.array_equal(u64_np(chk)[:n], ref), (kind, pattern, with_state)
+        if with_state:
+            assert np.array_equal(u64_np(st)[:n], states), (kind, pattern)
+
+
 def test_hash_draw_keys_wrap_at_2_64(M, orc):
     """Hash seeding keys stream i by first_index + i + 1 modulo 2^64: with the
     largest first_index the API accepts, the last stream's key wraps to 0.
