@@ -208,11 +208,17 @@ def uniforms_leg(M, W, torch, dev, lcg, n, k, warmup, reps):
     return out
 
 
-def traffic_from_profiles(kernel_src_sha):
+def source_sha(*names):
+    """sha256 of the named kernel sources (paper_2403_06362_amd/csrc), in order."""
+    src = b"".join(open(os.path.join(ROOT, "paper_2403_06362_amd", "csrc", n), "rb").read() for n in names)
+    return hashlib.sha256(src).hexdigest()
+
+
+def traffic_from_profiles(kernel_src_sha, summary="k_draw_hash_2p26_traffic.txt"):
     """HBM bytes per launch measured with rocprofv3 --pmc (FETCH_SIZE, then
     WRITE_SIZE), scaled by a copy kernel of known size; None if absent or
     taken on a different kernel source."""
-    path = os.path.join(ROOT, "profiles", "k_draw_hash_2p26_traffic.txt")
+    path = os.path.join(ROOT, "profiles", summary)
     if not os.path.exists(path):
         return None
     vals = {}
@@ -408,11 +414,7 @@ def main():
     ops_hash = OPS_PER_DRAW * total_draws + OPS_PER_HASH_SEED * n
     ops_stride = OPS_PER_DRAW * total_draws + OPS_PER_STRIDE_SEED * n
     achieved = ops_hash / (hsh["kernel_ms"] * 1e-3)
-    src = open(os.path.join(ROOT, "paper_2403_06362_amd", "csrc", "rng_kernels.hip"), "rb").read()
-    src += open(os.path.join(ROOT, "paper_2403_06362_amd", "csrc", "device_rng.hpp"), "rb").read()
-    src += open(os.path.join(ROOT, "paper_2403_06362_amd", "csrc", "internal.hpp"), "rb").read()
-    sha = hashlib.sha256(src).hexdigest()
-    traffic = traffic_from_profiles(sha)
+    traffic = traffic_from_profiles(source_sha("rng_kernels.hip", "device_rng.hpp", "internal.hpp"))
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": INT_VALU_PEAK / 1e12,
                 "unit": "Tera int32 VALU lane-ops/s", "frac": achieved / INT_VALU_PEAK,
                 "traffic": traffic, "kernel": "k_draw<hash>",
@@ -717,6 +719,8 @@ def _study(M, W, torch, lcg, ctx, out):
             out["roofline"] = valu_roofline(ops, ms, "k_pulse_family (3e7-source study, hash)",
                                             {"flights": flights, "collisions": d["collisions"],
                                              "scatters": d["scatters"], "secondaries": d["secondaries"]})
+            out["roofline"]["traffic"] = traffic_from_profiles(
+                source_sha("pulse.hip", "pulse.hpp", "device_rng.hpp"), "k_pulse_family_study_traffic.txt")
     study["paper_fails_of_600"] = {"stride": 369, "hash": 339}
     return study
 

@@ -27,11 +27,11 @@
 //       (the event-based schedule) every scattering banks all n particles:
 //       each launch advances every live particle by one flight.
 //   k_pulse_family            one source family per lane (sources taken 64
-//       per wave and atomic), walked depth first with a per-lane stack in
-//       HBM; a stack entry holds the siblings still to start of one
-//       scattering (stride: a count; hash: X_p and the next key), so the
-//       depth is at most the number of scatterings on the current line of
-//       descent.  With bank items (hash seeding) the same kernel finishes
+//       per wave and atomic), walked depth first with a per-lane stack (its
+//       top entry in registers, the rest in HBM planes, one per depth); a
+//       stack entry holds the siblings still to start of one scattering
+//       (stride: a count; hash: X_p and the next key), so the depth is at
+//       most the number of scatterings on the current line of descent.  With bank items (hash seeding) the same kernel finishes
 //       a bank schedule's tail: up to a budget of particles per item, the
 //       rest banked for the next launch.
 // Counts are integers added with 64-bit atomics (into a per-block LDS copy
@@ -50,6 +50,8 @@
 // integers, and copy k starts the stream hash(k, X) (eq. 5).  All
 // particles of a batch share the epoch's weight, so counts stay integers
 // and the flux applies the weights.
+#include <cstdlib>
+
 #include "pulse.hpp"
 
 namespace mcrng {
@@ -511,7 +513,18 @@ __device__ __forceinline__ void spill(const PulseParams& P, double x, double t, 
 // banks at most `budget` census arrivals per input particle.
 constexpr uint32_t kFamilyChunk = 64;   // items a wave of the family kernel takes per atomic
 
-template <bool HASH, int ITEMS, bool PC, int BLOCK>
+// Banks a lane's whole stack, bottom entry first: the sp entries in HBM,
+// then the top entry.
+__device__ __forceinline__ void spill_stack(const PulseParams& P, const PulseStackEntry* stack, uint64_t sstride,
+                                            uint32_t sp, const PulseStackEntry& top, bool has_top, uint32_t batch) {
+    for (uint32_t i = 0; i < sp; ++i) {
+        const PulseStackEntry& e = stack[static_cast<uint64_t>(i) * sstride];
+        spill(P, e.x, e.t, e.tb, batch, e.key, e.next, e.n);
+    }
+    if (has_top) spill(P, top.x, top.t, top.tb, batch, top.key, top.next, top.n);
+}
+
+template <bool HASH, int ITEMS, bool PC, int BLOCK, bool DEEP>
 __global__ void __launch_bounds__(BLOCK) k_pulse_family(PulseParams P) {
     constexpr bool SOURCES = ITEMS == PULSE_ITEMS_SOURCES;
     constexpr bool SPILL = !SOURCES;
@@ -522,10 +535,21 @@ __global__ void __launch_bounds__(BLOCK) k_pulse_family(PulseParams P) {
     PulseLane c;
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t gl = static_cast<uint64_t>(blockIdx.x) * BLOCK + threadIdx.x;
-    PulseStackEntry* stack = P.stack + gl * P.stack_depth;
+    // The lane's stack.  DEEP (many families per lane): its top entry in
+    // registers (top, valid if has_top), the entries below it in HBM, entry d
+    // of every lane of the launch in one plane (stack[d * sstride]), so that
+    // a wave's lanes at one depth share lines and the planes in use are a few
+    // dense regions.  Otherwise every entry in HBM, the lane's own entries
+    // contiguous (stack[d]), the top updated in place: a lane that runs alone
+    // on its SIMD waits for each entry anyway, and the registers the top
+    // would take cost occupancy.
+    PulseStackEntry* const stack = DEEP ? P.stack + gl : P.stack + gl * P.stack_depth;
+    const uint64_t sstride = DEEP ? static_cast<uint64_t>(gridDim.x) * BLOCK : 1ull;
     CensusStage& CS = cstage[PC ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0];
     uint32_t cstaged = 0;      // wave-uniform: entries in CS
-    uint32_t sp = 0;
+    uint32_t sp = 0;           // entries in HBM (DEEP: below the top)
+    PulseStackEntry top{};
+    bool has_top = false;
     const uint64_t n_items = SOURCES ? P.src_end - P.src_begin : P.n_in;
 
     PParticle p;
@@ -574,6 +598,7 @@ __global__ void __launch_bounds__(BLOCK) k_pulse_family(PulseParams P) {
                 }
                 pdraws = 0;
                 sp = 0;
+                has_top = false;
                 budget = P.lane_budget;
                 active = true;
             }
@@ -594,7 +619,7 @@ __global__ void __launch_bounds__(BLOCK) k_pulse_family(PulseParams P) {
         if (SPILL) budget--;
         if (n > 0) {
             if (n > 1) {
-                if (sp == P.stack_depth) {
+                if (sp + (has_top ? 1u : 0u) == P.stack_depth) {   // has_top is false unless DEEP
                     if (SPILL) {
                         spill(P, p.x, p.t, p.tb, p.batch, p.X, 2, n);
                     } else {
@@ -603,23 +628,28 @@ __global__ void __launch_bounds__(BLOCK) k_pulse_family(PulseParams P) {
                         continue;
                     }
                 } else {
-                    PulseStackEntry& e = stack[sp++];
+                    PulseStackEntry e;
                     e.x = p.x;
                     e.t = p.t;
                     e.key = p.X;
                     e.tb = p.tb;
                     e.next = 2;
-                    e.n = n;
+                    e.n = static_cast<uint16_t>(n);
+                    if (DEEP) {
+                        if (has_top) stack[static_cast<uint64_t>(sp++) * sstride] = top;
+                        top = e;
+                        has_top = true;
+                    } else {
+                        stack[sp++] = e;
+                    }
                 }
             }
             if (SPILL && budget == 0) {
                 // out of budget: the first emerging particle and the stack go to the bank
                 spill(P, p.x, p.t, p.tb, p.batch, p.X, 1, 1);
-                for (uint32_t i = 0; i < sp; ++i) {
-                    const PulseStackEntry& e = stack[i];
-                    spill(P, e.x, e.t, e.tb, p.batch, e.key, e.next, e.n);
-                }
+                spill_stack(P, stack, sstride, sp, top, has_top, p.batch);
                 sp = 0;
+                has_top = false;
                 active = false;
                 continue;
             }
@@ -627,30 +657,35 @@ __global__ void __launch_bounds__(BLOCK) k_pulse_family(PulseParams P) {
             p.has_mu = false;
             continue;   // the first emerging particle starts at once
         }
-        if (sp == 0) {
+        if (DEEP ? !has_top : sp == 0) {
             if (!HASH) note_stream(P, c, pdraws);
             active = false;
             continue;
         }
         if (SPILL && budget == 0) {
-            for (uint32_t i = 0; i < sp; ++i) {
-                const PulseStackEntry& e = stack[i];
-                spill(P, e.x, e.t, e.tb, p.batch, e.key, e.next, e.n);
-            }
+            spill_stack(P, stack, sstride, sp, top, has_top, p.batch);
             sp = 0;
+            has_top = false;
             active = false;
             continue;
         }
-        PulseStackEntry& e = stack[sp - 1];
+        PulseStackEntry& e = DEEP ? top : stack[sp - 1];
         p.x = e.x;
         p.t = e.t;
         p.tb = e.tb;
         p.has_mu = false;
         if (HASH) p.X = murmur_hash(e.next, e.key) & P.lcg.mask;
-        if (e.next == e.n)
-            --sp;
-        else
+        if (e.next != e.n) {
             e.next++;
+        } else if (!DEEP) {
+            --sp;
+        } else if (sp > 0) {
+            // the entry's last sibling: the entry below becomes the top (its
+            // load is in flight while this sibling's line runs)
+            top = stack[static_cast<uint64_t>(--sp) * sstride];
+        } else {
+            has_top = false;
+        }
     }
     if (PC && cstaged != 0) census_flush(P, CS, cstaged, lane);
     tally_lds_end<BLOCK>(P, lds_counts);
@@ -896,8 +931,16 @@ hipError_t launch_pulse_split(const PulseParams& p, uint64_t n_arrivals, hipStre
 
 template <bool HASH, int BLOCK>
 static hipError_t launch_family_b(const PulseParams& p, uint32_t grid, hipStream_t st) {
-    hipLaunchKernelGGL((k_pulse_family<HASH, PULSE_ITEMS_SOURCES, false, BLOCK>), dim3(grid), dim3(BLOCK),
-                       pulse_tally_lds_bytes(p), st, p);
+    // the register-top stack once every lane has many families to run
+    // (MCRNG_PULSE_DEEP = 0 or 1 forces one form: both give the same counts)
+    bool deep = p.src_end - p.src_begin >= 16ull * grid * BLOCK;
+    if (const char* env = getenv("MCRNG_PULSE_DEEP")) deep = atoi(env) != 0;
+    if (deep)
+        hipLaunchKernelGGL((k_pulse_family<HASH, PULSE_ITEMS_SOURCES, false, BLOCK, true>), dim3(grid), dim3(BLOCK),
+                           pulse_tally_lds_bytes(p), st, p);
+    else
+        hipLaunchKernelGGL((k_pulse_family<HASH, PULSE_ITEMS_SOURCES, false, BLOCK, false>), dim3(grid), dim3(BLOCK),
+                           pulse_tally_lds_bytes(p), st, p);
     return hipGetLastError();
 }
 
@@ -912,16 +955,17 @@ uint32_t pulse_finish_grid(uint64_t items) {
 hipError_t launch_pulse_finish(const PulseParams& p, bool pc, uint32_t grid, hipStream_t st) {
     if (p.n_in == 0) return hipSuccess;
     if (pc)
-        hipLaunchKernelGGL((k_pulse_family<true, PULSE_ITEMS_BANK, true, 256>), dim3(grid), dim3(256),
+        hipLaunchKernelGGL((k_pulse_family<true, PULSE_ITEMS_BANK, true, 256, false>), dim3(grid), dim3(256),
                            pulse_tally_lds_bytes(p), st, p);
     else
-        hipLaunchKernelGGL((k_pulse_family<true, PULSE_ITEMS_BANK, false, 256>), dim3(grid), dim3(256),
+        hipLaunchKernelGGL((k_pulse_family<true, PULSE_ITEMS_BANK, false, 256, false>), dim3(grid), dim3(256),
                            pulse_tally_lds_bytes(p), st, p);
     return hipGetLastError();
 }
 
 uint32_t pulse_family_grid(int block) {
-    // persistent lanes: 2048 per CU (the stack buffer is sized from this)
+    // persistent lanes: 2048 per CU (the stack buffer is sized from this);
+    // a run of few sources has its waves spread over the whole chip
     return static_cast<uint32_t>(device_cus()) * static_cast<uint32_t>(2048 / block);
 }
 

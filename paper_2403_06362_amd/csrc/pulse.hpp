@@ -67,7 +67,8 @@ struct PulseParams {
     uint64_t cont_budget;    // bank schedule: appends of continuing lines stay within this
     uint32_t* overflow;      // set if an append or a stack push found no room
     uint64_t* family_counter;
-    PulseStackEntry* stack;  // family schedule: stack_depth entries per lane
+    PulseStackEntry* stack;  // family schedule: stack_depth entries per lane of the launch,
+                             // depth-major (entry d of lane l at d * lanes + l)
     // population control (t_end is then the census time of the epoch)
     PulseCensusEntry* cen;   // census arrivals of the epoch
     uint64_t* cen_count;

@@ -181,6 +181,53 @@ def test_stack_overflow_is_reported(M, ctx):
     assert d["sources"] == 5
 
 
+def _smallest_stack_depth(M, ctx, prob):
+    """The smallest opts.stack_depth that holds every family of prob (one
+    less is reported as MCRNG_ERANGE)."""
+    lo, hi = 1, 128      # hi holds the families, lo does not
+    with pytest.raises(M.McrngError):
+        run(M, ctx, prob, schedule=M.PULSE_FAMILY, stack_depth=lo)
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        try:
+            run(M, ctx, prob, schedule=M.PULSE_FAMILY, stack_depth=mid)
+            hi = mid
+        except M.McrngError as e:
+            assert e.code == -4
+            lo = mid
+    return hi
+
+
+def test_family_stack_forms_bit_identical(M, ctx, orc, monkeypatch):
+    """Both forms of the family kernel's stack (MCRNG_PULSE_DEEP: every entry
+    in HBM, or the top entry in registers over depth-major planes, which runs
+    by itself only from 16 families per resident lane): the oracle's counts
+    for both seedings and every block size, deep families (256 sources to
+    t = 40), and the same smallest stack depth that holds them."""
+    for kind in ("hash", "stride"):
+        sd = W.hash_seeding() if kind == "hash" else W.stride_seeding()
+        p = W.pulse(sd, n_batches=17, per_batch=333, first_batch=4)
+        ref = orc.pulse(p, LCG, threads=8)
+        few = W.pulse_few_sources(n_sources=256, t_end=40).with_(seeding=sd)
+        ref_few = orc.pulse(few, LCG, threads=8)
+        depth = {}
+        for deep in ("0", "1"):
+            monkeypatch.setenv("MCRNG_PULSE_DEEP", deep)
+            for block in (64, 256, 1024):
+                say("family stack", deep, kind, block)
+                c, _, d = run(M, ctx, p, schedule=M.PULSE_FAMILY, block=block, stack_depth=40)
+                assert np.array_equal(c, ref.counts), (deep, kind, block)
+                assert d == ref.diag
+            say("family stack deep families", deep, kind)
+            c, _, d = run(M, ctx, few, schedule=M.PULSE_FAMILY)
+            assert np.array_equal(c, ref_few.counts) and d == ref_few.diag, (deep, kind)
+            depth[deep] = _smallest_stack_depth(M, ctx, few)
+            say("family stack smallest depth", deep, kind, depth[deep])
+            c, _, d = run(M, ctx, few, schedule=M.PULSE_FAMILY, stack_depth=depth[deep])
+            assert np.array_equal(c, ref_few.counts) and d == ref_few.diag, (deep, kind)
+        assert depth["0"] == depth["1"], (kind, depth)
+
+
 @pytest.mark.parametrize("kind", ["hash", "stride"])
 def test_full_study_whole(M, ctx, orc, kind):
     """The paper's normality study at full size: 30 repetitions x 1000
