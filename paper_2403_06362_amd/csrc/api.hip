@@ -313,7 +313,7 @@ extern "C" int mcrng_draw(const mcrng_lcg* lcg, const mcrng_seeding* seeding, ui
         if (rc < 0) return rc;
         mode = p.seed.kind;
     }
-    int bpc = 12, round = 20, generic = 0;
+    int bpc = 16, round = 20, generic = 0;
     if (const char* env = getenv("MCRNG_DRAW_BLOCKS_PER_CU")) bpc = atoi(env);
     if (const char* env = getenv("MCRNG_DRAW_ROUND")) round = atoi(env);
     if (const char* env = getenv("MCRNG_DRAW_GENERIC")) generic = atoi(env);

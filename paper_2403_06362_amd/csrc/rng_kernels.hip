@@ -371,21 +371,21 @@ __global__ void __launch_bounds__(256) k_draw_rounds(DrawParams P) {
                 filled += 64u;
             }
         }
-        if (__builtin_amdgcn_ballot_w64(rounds > 0) == 0) {
-            if (next >= nw) break;
-            continue;
-        }
+        const bool live = __builtin_amdgcn_ballot_w64(rounds > 0) != 0;
+        if (!live && next >= nw) break;
+        if (live) {
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-            y = g * y + c;
-            s += y;
-            if (TOPBIT) bits = __builtin_amdgcn_alignbit(bits, static_cast<uint32_t>(y >> 32), 31u);
+            for (int d = 0; d < D; ++d) {
+                y = g * y + c;
+                s += y;
+                if (TOPBIT) bits = __builtin_amdgcn_alignbit(bits, static_cast<uint32_t>(y >> 32), 31u);
+            }
+            if (TOPBIT) {
+                par = static_cast<uint32_t>(__builtin_popcount(bits & pm)) + par;
+                pm = kFull;
+            }
+            rounds -= 1;
         }
-        if (TOPBIT) {
-            par = static_cast<uint32_t>(__builtin_popcount(bits & pm)) + par;
-            pm = kFull;
-        }
-        rounds -= 1;
     }
 }
 
