@@ -74,17 +74,17 @@ METRIC = "particle histories/sec and RNG draws/sec (hash vs stride seeding), % i
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz = one full-rate 32-bit
 # VALU lane-operation per lane per clock.
 INT_VALU_PEAK = 256 * 4 * 16 * 2.4e9
-# Algorithmic integer lane-ops: a draw is the 63-bit multiply-add on 32-bit
-# halves (64-bit low product with the increment, two cross products, one
-# three-way add, the mask) plus the 64-bit checksum add = 6; a hash seed is
+# Algorithmic integer lane-ops: a draw is the LCG step on 32-bit halves
+# (64-bit low product with the increment, two cross products, one three-way
+# add), the reduction to m bits (a mask, or for m = 63 the top bit's
+# bookkeeping) and the 64-bit checksum add = 6; a hash seed is
 # Listing 1 on a 64-bit key = 16; a stride seed of consecutive streams is
 # one k-step affine map from the previous batch base (64-bit multiply-add
 # with a 64-bit increment, the mask) = 6.
 OPS_PER_DRAW = 6
 OPS_PER_HASH_SEED = 16
 OPS_PER_STRIDE_SEED = 6
-# Slab transport, algorithmic VALU lane-operations (the derivation, operation
-# by operation, is in the design notes' kernel table):
+# Slab transport, algorithmic VALU lane-operations, operation by operation:
 #   per geometry step (event), FP64, steady: collision distance through the
 #     cell's refined reciprocal 3, edge choice by direction 3, numerator 1,
 #     edge distance through the flight's reciprocal 3, strict choice 4,
