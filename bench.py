@@ -343,7 +343,8 @@ def main():
     ap.add_argument("--no-slab", action="store_true", help="skip the slab legs (long chain, batched, multi-region)")
     ap.add_argument("--only", default="",
                     help="comma-separated subset of the legs after the draw legs: long_chain, batched, "
-                         "multi_region, pulse (schedules), study (the normality study), pulse_pc")
+                         "multi_region, pulse (schedules), study (the normality study), pulse_pc, "
+                         "pulse_bank (the hash-seeded generation banks on 1000 x 1000 alone)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="long-chain legs with the default launch options (no autotuner runs)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -356,7 +357,7 @@ def main():
         sys.exit(2)
 
     only = set(x for x in args.only.split(",") if x)
-    unknown = only - {"long_chain", "batched", "multi_region", "pulse", "study", "pulse_pc"}
+    unknown = only - {"long_chain", "batched", "multi_region", "pulse", "study", "pulse_pc", "pulse_bank"}
     if unknown:
         print("bench.py: unknown legs %s" % ",".join(sorted(unknown)), file=sys.stderr)
         sys.exit(2)
@@ -489,6 +490,8 @@ def main():
         out["pulse"] = pulse_leg(M, W, torch, lcg, ctx, schedules=want("pulse", False), study=want("study", False))
     if want("pulse_pc", False):
         out["pulse_population_control"] = pulse_pc_leg(M, W, torch, lcg, ctx)
+    if only and "pulse_bank" in only:
+        out["pulse_bank"] = pulse_bank_leg(M, W, torch, lcg, ctx)
     if not args.no_transport:
         ctx.close()
 
@@ -694,6 +697,29 @@ def pulse_leg(M, W, torch, lcg, ctx, schedules=True, study=True):
     return out
 
 
+def pulse_ops(d):
+    """Algorithmic VALU lane-operations of a pulse run, from its diagnostics."""
+    flights = d["sources"] + d["secondaries"]
+    return (OPS_FLIGHT * flights + OPS_PULSE_COLLISION * d["collisions"] + OPS_PULSE_SCATTER * d["scatters"]
+            + OPS_SECONDARY_HASH * d["secondaries"] + OPS_PER_HASH_SEED * d["sources"]), flights
+
+
+def pulse_bank_leg(M, W, torch, lcg, ctx, reps=3):
+    """The hash-seeded generation banks alone on the paper's 1000 x 1000
+    problem (for profiling the bank kernel): run time and the algorithmic
+    work per flight over it (the run is a chain of launches with a size
+    read-back between generations, so this is a bound on the kernels' rate)."""
+    p = W.pulse(W.hash_seeding())
+    ms, _, d = pulse_run(M, torch, lcg, ctx, p, M.PULSE_BANK, reps)
+    ops, flights = pulse_ops(d)
+    out = {"workload": "pulse 1000 x 1000, hash seeding, generation banks", "runs": reps, "ms": ms,
+           "sources_per_s": p.n_sources / (ms * 1e-3), "flights": flights}
+    out["roofline_over_run_time"] = valu_roofline(ops, ms, "k_pulse_bank + finish (whole run)",
+                                                  {"flights": flights, "collisions": d["collisions"],
+                                                   "scatters": d["scatters"], "secondaries": d["secondaries"]})
+    return out
+
+
 def _study(M, W, torch, lcg, ctx, out):
     """The paper's normality study at full size: 30 repetitions x 1000
     batches x 1000 sources per seeding, Shapiro-Wilk on each of the 20
@@ -713,9 +739,7 @@ def _study(M, W, torch, lcg, ctx, out):
                        "median_p_per_time_bin": [float(v) for v in np.median(pv, axis=0)],
                        "over_stride_families": d["over_stride"], "max_draws": d["max_draws"]}
         if kind == "hash":
-            flights = d["sources"] + d["secondaries"]
-            ops = (OPS_FLIGHT * flights + OPS_PULSE_COLLISION * d["collisions"] + OPS_PULSE_SCATTER * d["scatters"]
-                   + OPS_SECONDARY_HASH * d["secondaries"] + OPS_PER_HASH_SEED * d["sources"])
+            ops, flights = pulse_ops(d)
             out["roofline"] = valu_roofline(ops, ms, "k_pulse_family (3e7-source study, hash)",
                                             {"flights": flights, "collisions": d["collisions"],
                                              "scatters": d["scatters"], "secondaries": d["secondaries"]})
