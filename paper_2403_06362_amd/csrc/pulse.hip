@@ -513,6 +513,13 @@ __device__ __forceinline__ void spill(const PulseParams& P, double x, double t, 
 // banks at most `budget` census arrivals per input particle.
 constexpr uint32_t kFamilyChunk = 64;   // items a wave of the family kernel takes per atomic
 
+// A source of the family schedule, seeded when its wave takes the chunk.
+struct __align__(16) FamilySource {
+    uint64_t X;
+    uint32_t batch;
+    uint32_t pad;
+};
+
 // Banks a lane's whole stack, bottom entry first: the sp entries in HBM,
 // then the top entry.
 __device__ __forceinline__ void spill_stack(const PulseParams& P, const PulseStackEntry* stack, uint64_t sstride,
@@ -545,6 +552,11 @@ __global__ void __launch_bounds__(BLOCK) k_pulse_family(PulseParams P) {
     // would take cost occupancy.
     PulseStackEntry* const stack = DEEP ? P.stack + gl : P.stack + gl * P.stack_depth;
     const uint64_t sstride = DEEP ? static_cast<uint64_t>(gridDim.x) * BLOCK : 1ull;
+    // sources: the wave's current chunk, seeded at once (one per lane) when
+    // the chunk is taken, so that a lane taking a source reads it from LDS
+    __shared__ FamilySource s_src[SOURCES ? BLOCK / 64 : 1][SOURCES ? kFamilyChunk : 1];
+    FamilySource* const ring = s_src[SOURCES ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0];
+    uint64_t cbase = 0;        // wave-uniform: the item of ring[0]
     CensusStage& CS = cstage[PC ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0];
     uint32_t cstaged = 0;      // wave-uniform: entries in CS
     uint32_t sp = 0;           // entries in HBM (DEEP: below the top)
@@ -577,6 +589,17 @@ __global__ void __launch_bounds__(BLOCK) k_pulse_family(PulseParams P) {
             if (b + kFamilyChunk >= n_items) exhausted = true;
             wnext = b < n_items ? b : n_items;
             wend = b + kFamilyChunk < n_items ? b + kFamilyChunk : n_items;
+            if (SOURCES) {
+                const uint64_t j = wnext + lane;
+                if (j < wend) {
+                    FamilySource e;
+                    e.X = pulse_source_state(P, P.src_begin + j, &e.batch);
+                    e.pad = 0;
+                    ring[lane] = e;
+                }
+                cbase = wnext;
+                __builtin_amdgcn_wave_barrier();
+            }
         }
         if (need != 0 && wnext != wend) {
             const uint64_t avail = wend - wnext;
@@ -588,7 +611,9 @@ __global__ void __launch_bounds__(BLOCK) k_pulse_family(PulseParams P) {
             if (!active && rank < take) {
                 const uint64_t j = wbase + rank;
                 if (SOURCES) {
-                    p.X = pulse_source_state(P, P.src_begin + j, &p.batch);
+                    const FamilySource e = ring[j - cbase];
+                    p.X = e.X;
+                    p.batch = e.batch;
                     p.x = 0.0;
                     p.t = 0.0;
                     p.tb = P.tb0;
