@@ -520,6 +520,14 @@ struct __align__(16) FamilySource {
     uint32_t pad;
 };
 
+// A family of a chunk with a tally slot has ended: the lane whose end leaves
+// the chunk with no family marks the slot for its wave's flush.
+__device__ __forceinline__ void family_ended(uint32_t* slot_alive, int32_t& lsl) {
+    if (lsl < 0) return;
+    const int32_t s = lsl >> 16;
+    lsl = atomicSub(slot_alive + s, 1u) == 1u ? -2 - s : -1;
+}
+
 // Banks a lane's whole stack, bottom entry first: the sp entries in HBM,
 // then the top entry.
 __device__ __forceinline__ void spill_stack(const PulseParams& P, const PulseStackEntry* stack, uint64_t sstride,
@@ -531,7 +539,7 @@ __device__ __forceinline__ void spill_stack(const PulseParams& P, const PulseSta
     if (has_top) spill(P, top.x, top.t, top.tb, batch, top.key, top.next, top.n);
 }
 
-template <bool HASH, int ITEMS, bool PC, int BLOCK, bool DEEP>
+template <bool HASH, int ITEMS, bool PC, int BLOCK, bool DEEP, bool SLOTS>
 __global__ void __launch_bounds__(BLOCK) k_pulse_family(PulseParams P) {
     constexpr bool SOURCES = ITEMS == PULSE_ITEMS_SOURCES;
     constexpr bool SPILL = !SOURCES;
@@ -557,6 +565,29 @@ __global__ void __launch_bounds__(BLOCK) k_pulse_family(PulseParams P) {
     __shared__ FamilySource s_src[SOURCES ? BLOCK / 64 : 1][SOURCES ? kFamilyChunk : 1];
     FamilySource* const ring = s_src[SOURCES ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0];
     uint64_t cbase = 0;        // wave-uniform: the item of ring[0]
+    // Tally slots (SLOTS: sources, counters that do not fit one LDS copy per
+    // block): each chunk of sources the wave takes gets a slot of
+    // 2 x n_time_bins counters in LDS (its sources span at most two batches);
+    // its families count there, and the slot goes to HBM once the chunk's
+    // last family has ended.  With no slot free the chunk counts straight
+    // into HBM.
+    constexpr bool SL = SOURCES && SLOTS;
+    const uint32_t nslots = SL ? P.tally_slots : 0u;
+    const uint32_t nt = P.n_time_bins;
+    __shared__ uint32_t s_slot[SL ? BLOCK / 64 : 1][SL ? 2 * kPulseTallySlots : 1];
+    uint32_t* const slot_alive = s_slot[SL ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0];
+    uint32_t* const slot_b0 = slot_alive + (SL ? kPulseTallySlots : 0);   // first batch of the slot's chunk
+    unsigned long long* const wslots =
+        lds_counts + static_cast<size_t>(__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) * nslots * 2u * nt;
+    if (SL)
+        for (uint32_t i = lane; i < nslots * 2u * nt; i += 64u) wslots[i] = 0ull;
+    uint32_t free_mask = nslots >= 32 ? 0xffffffffu : (1u << nslots) - 1u;   // wave-uniform
+    int32_t cur_slot = -1;     // wave-uniform: the current chunk's slot
+    uint32_t cur_b0 = 0;       // wave-uniform: the current chunk's first batch
+    // the lane's family: slot s and the counter of its batch's time bin 0
+    // in wslots as (s << 16) | base; -1: counts go to HBM; -2 - s: the lane
+    // ended the last family of slot s's chunk (flushed at the next top)
+    int32_t lsl = -1;
     CensusStage& CS = cstage[PC ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0];
     uint32_t cstaged = 0;      // wave-uniform: entries in CS
     uint32_t sp = 0;           // entries in HBM (DEEP: below the top)
@@ -578,6 +609,26 @@ __global__ void __launch_bounds__(BLOCK) k_pulse_family(PulseParams P) {
     uint32_t budget = 0;       // finish: particles the current item may still start
 
     for (;;) {
+        if (SL) {
+            // slots whose chunk has no family left: add them to HBM, clear, free
+            uint64_t fm = __ballot(lsl <= -2);
+            while (fm != 0) {
+                const int leader = __ffsll(static_cast<long long>(fm)) - 1;
+                const uint32_t s = static_cast<uint32_t>(-2 - __builtin_amdgcn_readlane(lsl, leader));
+                const uint64_t c0 = static_cast<uint64_t>(slot_b0[s]) * nt;
+                unsigned long long* const sc = wslots + static_cast<size_t>(s) * 2u * nt;
+                for (uint32_t i = lane; i < 2u * nt; i += 64u) {
+                    const unsigned long long v = sc[i];
+                    if (v != 0ull) {
+                        if (c0 + i < P.n_counters) atomicAdd(reinterpret_cast<unsigned long long*>(P.counts) + c0 + i, v);
+                        sc[i] = 0ull;
+                    }
+                }
+                free_mask |= 1u << s;
+                fm &= fm - 1ull;
+            }
+            if (lsl <= -2) lsl = -1;
+        }
         // lanes without a family take the next items from the wave's chunk
         // (one atomic per kFamilyChunk items: the counter is one address
         // for the whole GPU)
@@ -599,6 +650,17 @@ __global__ void __launch_bounds__(BLOCK) k_pulse_family(PulseParams P) {
                 }
                 cbase = wnext;
                 __builtin_amdgcn_wave_barrier();
+                cur_slot = -1;
+                if (SL && nslots != 0 && free_mask != 0 && wend > wnext) {
+                    cur_slot = __builtin_ctz(free_mask);
+                    free_mask &= free_mask - 1u;
+                    cur_b0 = ring[0].batch;
+                    if (lane == 0) {
+                        slot_alive[cur_slot] = static_cast<uint32_t>(wend - wnext);
+                        slot_b0[cur_slot] = cur_b0;
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                }
             }
         }
         if (need != 0 && wnext != wend) {
@@ -614,6 +676,10 @@ __global__ void __launch_bounds__(BLOCK) k_pulse_family(PulseParams P) {
                     const FamilySource e = ring[j - cbase];
                     p.X = e.X;
                     p.batch = e.batch;
+                    if (SL)
+                        lsl = cur_slot >= 0 ? (cur_slot << 16) | static_cast<int32_t>(static_cast<uint32_t>(cur_slot) * 2u * nt +
+                                                                                    (e.batch - cur_b0) * nt)
+                                            : -1;
                     p.x = 0.0;
                     p.t = 0.0;
                     p.tb = P.tb0;
@@ -633,7 +699,13 @@ __global__ void __launch_bounds__(BLOCK) k_pulse_family(PulseParams P) {
         int64_t tally = -1;
         bool at_census = false;
         if (active) n = pulse_particle<DIR>(P, p, c, &pdraws, &tally, &at_census);
-        wave_tally(P, tally, lane, lds_counts);
+        if (SL) {
+            if (tally >= 0 && lsl >= 0)
+                atomicAdd(wslots + (lsl & 0xffff) + static_cast<uint32_t>(tally - static_cast<int64_t>(p.batch) * nt), 1ull);
+            wave_tally(P, lsl >= 0 ? -1 : tally, lane, lds_counts);   // chunks without a slot
+        } else {
+            wave_tally(P, tally, lane, lds_counts);
+        }
         if (PC) census_stage(P, CS, cstaged, at_census, p, lane);
         if (!active) continue;
         if (HASH) {
@@ -650,6 +722,7 @@ __global__ void __launch_bounds__(BLOCK) k_pulse_family(PulseParams P) {
                     } else {
                         atomicOr(P.overflow, 1u);
                         active = false;   // the family is abandoned; the run reports an error
+                        if (SL) family_ended(slot_alive, lsl);
                         continue;
                     }
                 } else {
@@ -685,6 +758,7 @@ __global__ void __launch_bounds__(BLOCK) k_pulse_family(PulseParams P) {
         if (DEEP ? !has_top : sp == 0) {
             if (!HASH) note_stream(P, c, pdraws);
             active = false;
+            if (SL) family_ended(slot_alive, lsl);
             continue;
         }
         if (SPILL && budget == 0) {
@@ -954,18 +1028,47 @@ hipError_t launch_pulse_split(const PulseParams& p, uint64_t n_arrivals, hipStre
     return hipGetLastError();
 }
 
+// Tally slots per wave of the family kernel over sources: when the counters
+// do not fit one LDS copy per block, a chunk of 64 sources spans at most two
+// batches (at least 64 sources per batch) and the slots of a block fit in
+// 32 KiB.  MCRNG_PULSE_SLOTS sets the number (0: per-wave HBM atomics).
+template <int BLOCK>
+static uint32_t family_tally_slots(const PulseParams& p) {
+    if (p.lds_tally || p.per_batch < kFamilyChunk || p.n_time_bins > 64) return 0;
+    uint32_t k = kPulseTallySlots;
+    if (const char* env = getenv("MCRNG_PULSE_SLOTS")) k = static_cast<uint32_t>(atoi(env));
+    if (k > kPulseTallySlots) k = kPulseTallySlots;
+    while (k > 0 && static_cast<size_t>(BLOCK / 64) * k * 2u * p.n_time_bins * 8u > 32768u) k /= 2;
+    return k;
+}
+
 template <bool HASH, int BLOCK>
-static hipError_t launch_family_b(const PulseParams& p, uint32_t grid, hipStream_t st) {
+static hipError_t launch_family_b(const PulseParams& p_in, uint32_t grid, hipStream_t st) {
+    PulseParams p = p_in;
+    p.tally_slots = family_tally_slots<BLOCK>(p);
+    const size_t lds = static_cast<size_t>(BLOCK / 64) * p.tally_slots * 2u * p.n_time_bins * 8u;
     // the register-top stack once every lane has many families to run
     // (MCRNG_PULSE_DEEP = 0 or 1 forces one form: both give the same counts)
     bool deep = p.src_end - p.src_begin >= 16ull * grid * BLOCK;
     if (const char* env = getenv("MCRNG_PULSE_DEEP")) deep = atoi(env) != 0;
-    if (deep)
-        hipLaunchKernelGGL((k_pulse_family<HASH, PULSE_ITEMS_SOURCES, false, BLOCK, true>), dim3(grid), dim3(BLOCK),
-                           pulse_tally_lds_bytes(p), st, p);
-    else
-        hipLaunchKernelGGL((k_pulse_family<HASH, PULSE_ITEMS_SOURCES, false, BLOCK, false>), dim3(grid), dim3(BLOCK),
-                           pulse_tally_lds_bytes(p), st, p);
+    // the slot form only for the default block (other blocks count into HBM)
+    constexpr bool kSlots = BLOCK == 256;
+    if (!kSlots) p.tally_slots = 0;
+    if (p.tally_slots != 0) {
+        if (deep)
+            hipLaunchKernelGGL((k_pulse_family<HASH, PULSE_ITEMS_SOURCES, false, BLOCK, true, kSlots>), dim3(grid),
+                               dim3(BLOCK), lds, st, p);
+        else
+            hipLaunchKernelGGL((k_pulse_family<HASH, PULSE_ITEMS_SOURCES, false, BLOCK, false, kSlots>), dim3(grid),
+                               dim3(BLOCK), lds, st, p);
+    } else {
+        if (deep)
+            hipLaunchKernelGGL((k_pulse_family<HASH, PULSE_ITEMS_SOURCES, false, BLOCK, true, false>), dim3(grid),
+                               dim3(BLOCK), pulse_tally_lds_bytes(p), st, p);
+        else
+            hipLaunchKernelGGL((k_pulse_family<HASH, PULSE_ITEMS_SOURCES, false, BLOCK, false, false>), dim3(grid),
+                               dim3(BLOCK), pulse_tally_lds_bytes(p), st, p);
+    }
     return hipGetLastError();
 }
 
@@ -980,10 +1083,10 @@ uint32_t pulse_finish_grid(uint64_t items) {
 hipError_t launch_pulse_finish(const PulseParams& p, bool pc, uint32_t grid, hipStream_t st) {
     if (p.n_in == 0) return hipSuccess;
     if (pc)
-        hipLaunchKernelGGL((k_pulse_family<true, PULSE_ITEMS_BANK, true, 256, false>), dim3(grid), dim3(256),
+        hipLaunchKernelGGL((k_pulse_family<true, PULSE_ITEMS_BANK, true, 256, false, false>), dim3(grid), dim3(256),
                            pulse_tally_lds_bytes(p), st, p);
     else
-        hipLaunchKernelGGL((k_pulse_family<true, PULSE_ITEMS_BANK, false, 256, false>), dim3(grid), dim3(256),
+        hipLaunchKernelGGL((k_pulse_family<true, PULSE_ITEMS_BANK, false, 256, false, false>), dim3(grid), dim3(256),
                            pulse_tally_lds_bytes(p), st, p);
     return hipGetLastError();
 }

@@ -55,6 +55,8 @@ struct PulseParams {
     uint64_t* counts;        // n_batches x n_time_bins
     uint32_t n_counters;     // n_batches x n_time_bins
     uint32_t lds_tally;      // 1: each block counts into an LDS copy of all counters
+    uint32_t tally_slots;    // family schedule over sources, counters not in LDS: per-wave LDS
+                             // slots, one per chunk of sources in flight (0: HBM atomics)
     uint64_t* diag;          // kNDiag words (PD_*)
     uint64_t stride_q;       // stride: Q (over-stride count)
     uint64_t src_begin, src_end;   // sources of this launch (0-based over the run)
@@ -98,6 +100,7 @@ constexpr uint32_t kPulsePcChunkBatches = 4096;   // batches per chunk of a popu
 // population control (arrivals are banked in p.cen).
 uint32_t pulse_bank_grid(const PulseParams& p, int items_kind, bool pc, int block, uint64_t items);
 constexpr uint32_t kPulseLdsCounters = 2048;   // block-local tally copies up to this many counters (16 KiB)
+constexpr uint32_t kPulseTallySlots = 16;      // most tally slots per wave of the family kernel
 // Entries of a wave's LDS stage of appends in k_pulse_bank (output slack).
 uint32_t pulse_bank_stage(int block);
 hipError_t launch_pulse_bank(const PulseParams& p, int items_kind, bool pc, int block, uint32_t grid,

@@ -228,6 +228,31 @@ def test_family_stack_forms_bit_identical(M, ctx, orc, monkeypatch):
         assert depth["0"] == depth["1"], (kind, depth)
 
 
+def test_family_tally_slots_bit_identical(M, ctx, orc, monkeypatch):
+    """Family runs whose counters do not fit one LDS copy per block count
+    each chunk of sources in a per-wave LDS slot, added to HBM when the
+    chunk's last family ends; with no slot free a chunk counts straight into
+    HBM.  Forced slot counts (MCRNG_PULSE_SLOTS: 0, 1, 16), both stack forms
+    and both seedings give the oracle's counts, with 1000 sources per batch
+    and with 63, 64 and 65 (a chunk of 64 sources then straddles two batches,
+    or the slots are off)."""
+    for per_batch, n_batches in ((1000, 120), (64, 3000), (65, 3000), (63, 3000)):
+        for kind in ("hash", "stride"):
+            sd = W.hash_seeding() if kind == "hash" else W.stride_seeding()
+            p = W.pulse(sd, n_batches=n_batches, per_batch=per_batch, first_batch=3)
+            assert n_batches * 20 > 2048   # the counters do not fit one LDS copy
+            ref = orc.pulse(p, LCG, threads=8)
+            for slots in ("0", "1", "16"):
+                for deep in ("0", "1"):
+                    monkeypatch.setenv("MCRNG_PULSE_SLOTS", slots)
+                    monkeypatch.setenv("MCRNG_PULSE_DEEP", deep)
+                    say("tally slots", per_batch, kind, slots, deep)
+                    c, f, d = run(M, ctx, p, schedule=M.PULSE_FAMILY)
+                    assert np.array_equal(c, ref.counts), (per_batch, kind, slots, deep)
+                    assert d == ref.diag
+            assert np.array_equal(f, orc.pulse_flux(p, LCG, ref.counts))
+
+
 @pytest.mark.parametrize("kind", ["hash", "stride"])
 def test_full_study_whole(M, ctx, orc, kind):
     """The paper's normality study at full size: 30 repetitions x 1000
