@@ -215,7 +215,7 @@ static int get_align_table(const LcgDev& L, int D, const AlignEntry** out) {
     }
     uint64_t gi = L.g;   // g^-1 modulo 2^64 by Newton's iteration (3 correct bits, doubling)
     for (int k = 0; k < 5; ++k) gi *= 2ull - L.g * gi;
-    std::vector<AlignEntry> h(kMaxRound);
+    std::vector<AlignEntry> h(kMaxRound + kSkipMaps);
     uint64_t a = 1, b = 0, sa = 0, sb = 0;   // rewind of h steps, and the sums of the first h of them
     for (int k = 0; k < kMaxRound; ++k) {
         h[k] = AlignEntry{a, b, 0ull - sa, 0ull - sb};
@@ -223,6 +223,17 @@ static int get_align_table(const LcgDev& L, int D, const AlignEntry** out) {
         sb += b;
         a = gi * a;
         b = gi * b - gi * L.c;
+    }
+    // skip-ahead by 2^e rounds: one round (D steps), then doubling
+    uint64_t G = 1, C = 0;
+    for (int k = 0; k < D; ++k) {
+        C = L.g * C + L.c;
+        G = L.g * G;
+    }
+    for (int e = 0; e < kSkipMaps; ++e) {
+        h[kMaxRound + e] = AlignEntry{G, C, 0ull, 0ull};
+        C = G * C + C;
+        G = G * G;
     }
     AlignEntry* d_tab = nullptr;
     HIP_TRY(hipMalloc(&d_tab, h.size() * sizeof(AlignEntry)));
@@ -313,7 +324,7 @@ extern "C" int mcrng_draw(const mcrng_lcg* lcg, const mcrng_seeding* seeding, ui
         if (rc < 0) return rc;
         mode = p.seed.kind;
     }
-    int bpc = 16, round = 20, generic = 0;
+    int bpc = 32, round = 20, generic = 0;
     if (const char* env = getenv("MCRNG_DRAW_BLOCKS_PER_CU")) bpc = atoi(env);
     if (const char* env = getenv("MCRNG_DRAW_ROUND")) round = atoi(env);
     if (const char* env = getenv("MCRNG_DRAW_GENERIC")) generic = atoi(env);

@@ -58,6 +58,10 @@ struct __align__(16) AlignEntry {
 };
 
 constexpr int kMaxRound = 32;
+// The table holds kMaxRound alignment entries, then kSkipMaps skip-ahead
+// maps: entry kMaxRound + e has (a, b) = the map of 2^e rounds (2^e D steps,
+// modulo 2^64), Y -> a Y + b; na and nb are 0.
+constexpr int kSkipMaps = 32;
 
 struct DrawParams {
     LcgDev lcg;
@@ -66,7 +70,7 @@ struct DrawParams {
     const uint32_t* count;
     uint64_t* state;      // SEED_LOAD: in/out; else optional out (may be null)
     uint64_t* checksum;
-    const AlignEntry* align;   // round alignment for the round length (null: the generic kernel)
+    const AlignEntry* align;   // round alignment and skip maps for the round length (null: the generic kernel)
 };
 
 hipError_t launch_init_streams(const LcgDev& L, const SeedDev& S, uint64_t n, uint64_t* out,

@@ -272,9 +272,17 @@ __device__ __forceinline__ RoundEntry round_entry(const AlignEntry* al, uint64_t
 // entries are computed when a batch of 64 streams is seeded (all lanes).
 template <int MODE, int D, bool STORE_STATE, bool TOPBIT>
 __global__ void __launch_bounds__(256) k_draw_rounds(DrawParams P) {
+    // splitting the last streams between lanes (below) leaves a stream's
+    // final state in whichever lane ran its last part: not with final states
+    constexpr bool SPLIT = !STORE_STATE;
     __shared__ RoundEntry s_ring[4][128];
     __shared__ AlignEntry s_align[kMaxRound];
+    __shared__ uint64_t s_skip[SPLIT ? kSkipMaps : 1][2];
     if (threadIdx.x < static_cast<uint32_t>(D)) s_align[threadIdx.x] = P.align[threadIdx.x];
+    if (SPLIT && threadIdx.x < static_cast<uint32_t>(kSkipMaps)) {
+        s_skip[threadIdx.x][0] = P.align[kMaxRound + threadIdx.x].a;
+        s_skip[threadIdx.x][1] = P.align[kMaxRound + threadIdx.x].b;
+    }
     __syncthreads();
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -322,15 +330,31 @@ __global__ void __launch_bounds__(256) k_draw_rounds(DrawParams P) {
     // the lane idle).  The wave ends once no lane is live and every stream
     // of its range has been taken: a take that hands out only streams of no
     // draws leaves no lane live, but streams may remain.
+    // The wave's tail: once every stream of its range is taken, a lane with
+    // two or more rounds left hands its last rounds to an idle lane (the
+    // idle lane starts 2^e rounds ahead through a skip map; the parts' sums
+    // and parities add).  The parts of a split stream add their checksums
+    // into a record, ring[r] (s: the sum, rounds: the parts still running),
+    // r the lane that first split it; the last part stores the total.  The
+    // ring holds no untaken stream by then: records use ring[0..63], the
+    // hand-over ring[64..127].
     uint64_t y = 0, s = 0;
     uint32_t sid = 0, pm = 0, par = 0, bits = 0;
     int32_t rounds = -1;
+    int32_t rec = -1;          // SPLIT: the record of the stream's parts (-1: the stream is whole here)
     for (;;) {
         if (rounds == 0) {
             uint64_t chk = s;
             if (TOPBIT) chk += static_cast<uint64_t>(par & 1u) << 63;
-            *reinterpret_cast<uint64_t*>(cbase + (sid << 3)) = chk;
-            if (STORE_STATE) P.state[lo + sid] = y & P.lcg.mask;
+            if (SPLIT && rec >= 0) {
+                RoundEntry* const r = ring + rec;
+                atomicAdd(reinterpret_cast<unsigned long long*>(&r->s), static_cast<unsigned long long>(chk));
+                if (atomicSub(&r->rounds, 1u) == 1u) *reinterpret_cast<uint64_t*>(cbase + (sid << 3)) = r->s;
+                rec = -1;
+            } else {
+                *reinterpret_cast<uint64_t*>(cbase + (sid << 3)) = chk;
+                if (STORE_STATE) P.state[lo + sid] = y & P.lcg.mask;
+            }
         }
         next = __builtin_amdgcn_readfirstlane(next);
         const uint64_t need = __builtin_amdgcn_ballot_w64(rounds <= 0);
@@ -369,6 +393,54 @@ __global__ void __launch_bounds__(256) k_draw_rounds(DrawParams P) {
                 const uint32_t jn = j + 64u;
                 c_next = (jn < nw) ? P.count[lo + jn] : 0u;
                 filled += 64u;
+            }
+        }
+        if (SPLIT && next >= nw) {
+            const uint64_t idle = __builtin_amdgcn_ballot_w64(rounds <= 0);
+            const uint64_t cand = __builtin_amdgcn_ballot_w64(rounds >= 2);
+            if (idle != 0 && cand != 0) {
+                const uint32_t ni = static_cast<uint32_t>(__popcll(idle));
+                const uint32_t nc = static_cast<uint32_t>(__popcll(cand));
+                const uint32_t np = ni < nc ? ni : nc;
+                if (rounds >= 2) {
+                    const uint32_t cr = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(cand >> 32),
+                                                                  __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(cand), 0u));
+                    if (cr < np) {
+                        // keep the first 2^e rounds, 2^e <= rounds / 2; hand over the rest
+                        const uint32_t e = 31u - static_cast<uint32_t>(__builtin_clz(static_cast<uint32_t>(rounds) >> 1));
+                        const int32_t keep = 1 << e;
+                        if (rec < 0) {
+                            rec = static_cast<int32_t>(lane);
+                            ring[lane].s = 0ull;
+                            ring[lane].rounds = 2u;
+                        } else {
+                            atomicAdd(&ring[rec].rounds, 1u);
+                        }
+                        RoundEntry h;
+                        h.y = s_skip[e][0] * y + s_skip[e][1];
+                        h.s = (static_cast<uint64_t>(sid) << 32) | static_cast<uint32_t>(rec);
+                        h.rounds = static_cast<uint32_t>(rounds - keep);
+                        h.pm = kFull;
+                        h.pad = 0;
+                        ring[64u + cr] = h;
+                        rounds = keep;
+                    }
+                }
+                __builtin_amdgcn_wave_barrier();
+                if (rounds <= 0) {
+                    const uint32_t ir = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(idle >> 32),
+                                                                  __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(idle), 0u));
+                    if (ir < np) {
+                        const RoundEntry h = ring[64u + ir];
+                        y = h.y;
+                        sid = static_cast<uint32_t>(h.s >> 32);
+                        rec = static_cast<int32_t>(static_cast<uint32_t>(h.s));
+                        rounds = static_cast<int32_t>(h.rounds);
+                        pm = h.pm;
+                        s = 0ull;
+                        par = 0u;
+                    }
+                }
             }
         }
         const bool live = __builtin_amdgcn_ballot_w64(rounds > 0) != 0;
@@ -429,7 +501,7 @@ hipError_t launch_draw(const DrawParams& p, int seed_mode, hipStream_t st, int b
     if (e != hipSuccess) return e;
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    if (blocks_per_cu <= 0) blocks_per_cu = 16;
+    if (blocks_per_cu <= 0) blocks_per_cu = 32;
     uint64_t blocks = static_cast<uint64_t>(cus) * blocks_per_cu;
     // at least one queue of streams per wave on average
     const uint64_t max_blocks = (p.n + 255) / 256;

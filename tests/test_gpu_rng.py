@@ -151,6 +151,31 @@ def test_draw_takes_of_only_empty_streams(M, orc, kind, pattern):
             assert np.array_equal(u64_np(st)[:n], states), (kind, pattern)
 
 
+@pytest.mark.parametrize("kind", ["hash", "stride"])
+def test_draw_tail_splits(M, orc, kind):
+    """The end of a wave's range: lanes whose stream has two or more rounds
+    left hand their last rounds to idle lanes (a skip-ahead of 2^e rounds)
+    and the parts' checksums add.  Streams of 1 draw with one of 40,000 to
+    100,000 draws every 997 streams (so most waves end on a few long
+    streams, split again and again), 2^20 streams, every checksum the
+    oracle's; with final states (no splitting) as well."""
+    import torch
+    n = 1 << 20
+    counts = np.ones(n, dtype=np.uint32)
+    rng = np.random.default_rng(11)
+    counts[::997] = rng.integers(40_000, 100_001, counts[::997].size)
+    sd = W.hash_seeding() if kind == "hash" else W.stride_seeding()
+    ref = orc.seed_and_draw(LCG, sd, counts, threads=host_threads())
+    for with_state in (False, True):
+        say("draw tail splits", kind, with_state)
+        chk = _empty_u64(n)
+        st = _empty_u64(n) if with_state else None
+        M.draw(LCG, sd, to_dev_u32(counts), chk, d_state=st)
+        torch.cuda.synchronize()
+        bad = np.flatnonzero(u64_np(chk)[:n] != ref)
+        assert bad.size == 0, (kind, with_state, bad[:8])
+
+
 def test_hash_draw_keys_wrap_at_2_64(M, orc):
     """Hash seeding keys stream i by first_index + i + 1 modulo 2^64: with the
     largest first_index the API accepts, the last stream's key wraps to 0.
