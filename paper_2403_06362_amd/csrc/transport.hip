@@ -86,11 +86,11 @@ __device__ __forceinline__ uint32_t wave_count(bool c) {
     return static_cast<uint32_t>(__popcll(__builtin_amdgcn_ballot_w64(c)));
 }
 
-// One history per lane: six waves per SIMD in FP64 (80 VGPRs) and seven in
-// FP32 (72), each with a few registers spilled, measured faster than five
-// and six without spills.
+// One history per lane: seven waves per SIMD (72 VGPRs, a few spilled)
+// measured faster than five (FP64) or six (FP32) without spills, except
+// FP64 with time bins, where six (80 VGPRs) is best.
 template <bool F32, bool TIMED, int H, int BLOCK>
-__global__ void __launch_bounds__(BLOCK, (H == 1) ? (F32 ? 7 : 6) : 1) k_transport(TransportParams P) {
+__global__ void __launch_bounds__(BLOCK, (H == 1) ? ((F32 || !TIMED) ? 7 : 6) : 1) k_transport(TransportParams P) {
     using R = typename Particle<F32>::R;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t s_unit;
