@@ -477,6 +477,9 @@ def main():
         d64 = legs["hash_fp64"]["diag"]
         tr["roofline"] = valu_roofline(transport_ops(d64), legs["hash_fp64"]["ms"], "k_transport<fp64> (history)",
                                        {k: d64[k] for k in ("histories", "events", "collisions", "absorbed")})
+        tr["roofline"]["traffic"] = traffic_from_profiles(
+            source_sha("transport.hip", "particle.hpp", "device_rng.hpp", "internal.hpp"),
+            "k_transport_long_chain_fp64_traffic.txt")
         d32 = legs["hash_fp32"]["diag"]
         tr["roofline_fp32"] = valu_roofline(transport_ops(d32), legs["hash_fp32"]["ms"], "k_transport<fp32> (history)",
                                             {k: d32[k] for k in ("histories", "events", "collisions", "absorbed")})
