@@ -91,7 +91,11 @@ int mcrng_init_streams(const mcrng_lcg *lcg, const mcrng_seeding *seeding, uint6
  *                    d_state may be NULL, else it receives the final states.
  *   seeding == NULL: start states are read from d_state, which receives the
  *                    final states (in place).
- * d_count: n uint32; d_checksum: n uint64.  n = 0 is a no-op. */
+ * d_count: n uint32; d_checksum: n uint64.  n = 0 is a no-op.
+ * Launch-shape overrides read from the environment (results never change):
+ * MCRNG_DRAW_ROUND (8, 16, 20, 24 or 32 steps per round; default 20),
+ * MCRNG_DRAW_BLOCKS_PER_CU (default 32), MCRNG_DRAW_GENERIC=1 (the masked
+ * kernel instead of the round-aligned one). */
 int mcrng_draw(const mcrng_lcg *lcg, const mcrng_seeding *seeding, uint64_t n,
                const uint32_t *d_count, uint64_t *d_state, uint64_t *d_checksum, void *stream);
 
@@ -379,7 +383,12 @@ enum {
  * MCRNG_EINVAL (arguments), MCRNG_ERANGE (a family outgrew
  * opts.stack_depth; the outputs are then incomplete), MCRNG_ENOMEM.
  * Returns MCRNG_WSTRIDE_WRAP when the stride allocation passes 2^m states.
- * The run's time (first to last launch of the run) is mcrng_last_run_ms. */
+ * The run's time (first to last launch of the run) is mcrng_last_run_ms.
+ * Family-kernel overrides read from the environment (counts never change):
+ * MCRNG_PULSE_DEEP = 0 or 1 (the lane-major stack, or the register-held top
+ * over depth-major planes; by default the latter from 16 families per lane),
+ * MCRNG_PULSE_SLOTS = 0..16 (per-wave LDS tally slots when the counters do
+ * not fit one LDS copy per block; default 16, 0 counts into HBM). */
 int mcrng_run_pulse(mcrng_ctx *ctx, const mcrng_lcg *lcg, const mcrng_pulse_problem *problem,
                     const mcrng_pulse_opts *opts, uint64_t *d_counts, double *d_flux,
                     uint64_t *d_diag, void *stream);
