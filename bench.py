@@ -251,7 +251,7 @@ def transport_leg(M, W, torch, lcg, ctx, prob, opts, reps=2):
     d = diag.view(torch.int64).cpu().numpy().view(np.uint64)[0]
     dd = dict(zip(P.DIAG_NAMES, (int(v) for v in d)))
     ms = float(np.median(times))
-    return {"ms": ms, "histories_per_s": prob.n_histories / (ms * 1e-3),
+    return {"ms": ms, "kernel": ctx.last_run_kernel(), "histories_per_s": prob.n_histories / (ms * 1e-3),
             "draws_per_s": dd["draws"] / (ms * 1e-3), "events_per_s": dd["events"] / (ms * 1e-3),
             "draws_per_history": dd["draws"] / max(1, dd["histories"]),
             "events_per_history": dd["events"] / max(1, dd["histories"]),
@@ -475,13 +475,13 @@ def main():
         tr["fp32_speedup"] = legs["hash_fp64"]["ms"] / legs["hash_fp32"]["ms"]
         tr["hash_over_stride"] = legs["stride_fp64"]["ms"] / legs["hash_fp64"]["ms"]
         d64 = legs["hash_fp64"]["diag"]
-        tr["roofline"] = valu_roofline(transport_ops(d64), legs["hash_fp64"]["ms"], "k_transport<fp64> (history)",
+        tr["roofline"] = valu_roofline(transport_ops(d64), legs["hash_fp64"]["ms"], "%s<fp64>" % legs["hash_fp64"]["kernel"],
                                        {k: d64[k] for k in ("histories", "events", "collisions", "absorbed")})
         tr["roofline"]["traffic"] = traffic_from_profiles(
             source_sha("transport.hip", "particle.hpp", "device_rng.hpp", "internal.hpp"),
             "k_transport_long_chain_fp64_traffic.txt")
         d32 = legs["hash_fp32"]["diag"]
-        tr["roofline_fp32"] = valu_roofline(transport_ops(d32), legs["hash_fp32"]["ms"], "k_transport<fp32> (history)",
+        tr["roofline_fp32"] = valu_roofline(transport_ops(d32), legs["hash_fp32"]["ms"], "%s<fp32>" % legs["hash_fp32"]["kernel"],
                                             {k: d32[k] for k in ("histories", "events", "collisions", "absorbed")})
         out["histories_per_s"] = legs["hash_fp64"]["histories_per_s"]
         out["transport"] = tr
@@ -585,7 +585,7 @@ def multi_region_leg(M, W, torch, lcg, ctx):
     res["fp32_speedup"] = res["history_fp64"]["ms"] / res["history_fp32"]["ms"]
     d = diag["history_fp64"]
     res["roofline"] = valu_roofline(transport_ops(d, timed=True), res["history_fp64"]["ms"],
-                                    "k_transport<fp64, timed> (history)",
+                                    "%s<fp64, timed>" % res["history_fp64"]["kernel"],
                                     {k: d[k] for k in ("histories", "events", "collisions", "absorbed")})
     return res
 

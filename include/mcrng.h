@@ -156,13 +156,26 @@ enum { MCRNG_SCHED_HISTORY = 0, MCRNG_SCHED_EVENT = 1 };
  *   block           threads per block: 64, 128, 256, 512 or 1024
  *   hist_per_lane   histories each lane carries at once: 1, 2 or 4
  *   unit_histories  histories per work unit (the scheduling grain), at most
- *                   2^18 (0 = automatic, at most 2^16).  A unit's partial
+ *                   2^18 (0 = automatic, at most 2^16: total / 4096, or
+ *                   total / 10240 when that takes the chained kernel
+ *                   below).  A unit's partial
  *                   tally is exact while fewer than 2^32 of its scores fall
  *                   in one bin (2^14 per history on average at 2^18
  *                   histories); the event schedule's slots that collect a
  *                   whole slice carry and have no such limit.
  *   grid            persistent blocks (0 = fill the device)
  *   tally_copies    LDS tally copies per block: 1, or one per wave (= 2)
+ *                   A set of one problem with one history per lane, one
+ *                   tally copy and units of at least 20 x block histories
+ *                   runs on the chained kernel, where a block holds two
+ *                   units (two LDS tally slices) and starts its next unit
+ *                   while the last histories of the current one finish, if
+ *                   the second slice costs no blocks per CU.  Environment
+ *                   override MCRNG_TRANSPORT_CHAIN: 0 = never, 2 = for
+ *                   every run of one problem with one history per lane and
+ *                   one tally copy, whatever its units and even where it
+ *                   costs blocks per CU (any other history-schedule run
+ *                   fails with MCRNG_EINVAL); read at every run.
  *   use_graph       1 = capture the launches of a run in a hipGraph once
  *                   per (problem set, options) and replay it
  *   bank_size       event schedule: particles per bank slice
@@ -277,6 +290,12 @@ int mcrng_autotune(mcrng_ctx *ctx, const mcrng_lcg *lcg, const mcrng_problem *pr
  * its stream), in milliseconds, once that stream has reached the end of the
  * run; negative if unavailable. */
 float mcrng_last_run_ms(mcrng_ctx *ctx);
+
+/* Name of the transport kernel the last run_histories of `ctx` launched:
+ * "k_transport_chain" (one problem, two units in flight per block),
+ * "k_transport" (per-unit) or "k_event_step" (event schedule); "" before
+ * any run or for a NULL ctx.  A static string; host-only. */
+const char *mcrng_last_run_kernel(const mcrng_ctx *ctx);
 
 /* ------------------------------------------------------------------ */
 /* Pulse in an infinite multiplying medium, with secondary particles   */

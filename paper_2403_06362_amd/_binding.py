@@ -31,7 +31,7 @@ PULSE_DIAG_NAMES = ("sources", "collisions", "tallied", "scatters", "absorbed", 
 EXPORTS = ("mcrng_init_streams", "mcrng_draw", "mcrng_ctx_create", "mcrng_ctx_destroy",
            "mcrng_tally_bins", "mcrng_run_histories", "mcrng_reduce_tallies", "mcrng_autotune",
            "mcrng_last_run_ms", "mcrng_last_error", "mcrng_version", "mcrng_run_pulse", "mcrng_uniforms",
-           "mcrng_run_pulse_pc", "mcrng_run_histories_noalloc")
+           "mcrng_run_pulse_pc", "mcrng_run_histories_noalloc", "mcrng_last_run_kernel")
 
 
 class McrngError(RuntimeError):
@@ -108,6 +108,8 @@ def lib():
         L.mcrng_autotune.argtypes = [vp, P(Lcg), P(Problem), u32, P(RunOpts), P(RunOpts), P(C.c_float), vp]
         L.mcrng_last_run_ms.argtypes = [vp]
         L.mcrng_last_run_ms.restype = C.c_float
+        L.mcrng_last_run_kernel.argtypes = [vp]
+        L.mcrng_last_run_kernel.restype = C.c_char_p
         L.mcrng_last_error.argtypes = []
         L.mcrng_last_error.restype = C.c_char_p
         L.mcrng_version.argtypes = []
@@ -116,7 +118,7 @@ def lib():
         L.mcrng_run_pulse_pc.argtypes = [vp, P(Lcg), P(PulseProblem), P(PulsePc), P(PulseOpts), vp, vp, vp, vp, vp]
         L.mcrng_run_histories_noalloc.argtypes = [P(Lcg), P(Problem), u32, P(RunOpts), vp, vp, vp, vp]
         for name in EXPORTS:
-            if name not in ("mcrng_tally_bins", "mcrng_last_run_ms", "mcrng_last_error"):
+            if name not in ("mcrng_tally_bins", "mcrng_last_run_ms", "mcrng_last_error", "mcrng_last_run_kernel"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -359,3 +361,6 @@ class Context:
 
     def last_run_ms(self):
         return float(lib().mcrng_last_run_ms(self._h))
+
+    def last_run_kernel(self):
+        return lib().mcrng_last_run_kernel(self._h).decode()

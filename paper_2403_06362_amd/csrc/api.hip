@@ -351,6 +351,8 @@ struct mcrng_ctx {
     hipStream_t capture_stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool timing_valid = false;
+    const char* last_kernel = "";                        // transport kernel of the last run
+    std::map<uint64_t, const char*> graph_kernel;        // ... of each cached graph
 
     DevBuf problems, edges64, sig64, scat64, cbin, edges32, sig32, tedges64, tedges32;
     DevBuf units, order, partial, unit_diag, counter, groups, dx, dt, pu_begin;
@@ -419,6 +421,7 @@ static int upload(DevBuf& b, const std::vector<T>& h, hipStream_t st) {
 static void clear_graphs(mcrng_ctx* ctx) {
     for (auto& kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
     ctx->graphs.clear();
+    ctx->graph_kernel.clear();
 }
 
 extern "C" int mcrng_ctx_create(int device, mcrng_ctx** out) {
@@ -557,10 +560,62 @@ static uint64_t signature(const mcrng_lcg* lcg, const mcrng_problem* P, uint32_t
     return h;
 }
 
-static uint32_t default_unit_histories(const mcrng_problem* P, uint32_t n) {
+// Work units of a chained run by default (total histories / kChainUnits).
+constexpr uint64_t kChainUnits = 10240;
+// The chained kernel holds two units per block, so the block waits whenever
+// a unit is handed out before the one before it has ended; on the long-chain
+// slab (heavy-tailed history lengths) that costs little from about 20
+// histories per lane per unit up (block 256: 34.5-35.2 ms at 5425-12207
+// histories per unit, 44 ms at 3051, 67 ms at 1525; the per-unit kernel
+// 38.1 ms).  Smaller units run on the per-unit kernel.
+constexpr uint32_t kChainMinPerLane = 20;
+
+// MCRNG_TRANSPORT_CHAIN: 0 keeps one-problem runs on the per-unit kernel;
+// 2 takes the chained kernel for every run of one problem with one history
+// per lane and one tally copy, whatever its units and even where it costs
+// blocks per CU (other history-schedule runs fail); otherwise it is taken
+// for units of at least kChainMinPerLane histories per lane where it costs
+// no blocks per CU.
+static int chain_mode() {
+    const char* env = getenv("MCRNG_TRANSPORT_CHAIN");
+    const int m = env ? atoi(env) : 1;
+    return (m == 0 || m == 2) ? m : 1;
+}
+static bool chain_enabled() { return chain_mode() != 0; }
+
+// Whether a run of these problems with these options will take the chained
+// kernel (estimated from the problem's sizes: the merged cells are at most
+// regions + bins; the launch decides on the exact tables).
+static bool chain_planned(const mcrng_problem* P, uint32_t n, const mcrng_run_opts& o) {
+    if (n != 1 || o.schedule != MCRNG_SCHED_HISTORY || o.hist_per_lane != 1 || o.tally_copies != 1 ||
+        !chain_enabled())
+        return false;
+    const uint64_t unit = o.unit_histories ? o.unit_histories : P[0].n_histories / kChainUnits;
+    if (chain_mode() != 2 && unit < static_cast<uint64_t>(kChainMinPerLane) * o.block) return false;
+    TransportParams a{};
+    a.max_slice = std::max<uint32_t>(P[0].n_time_bins, 1) * P[0].n_space_bins;
+    a.max_cells = P[0].n_regions + P[0].n_space_bins;
+    a.max_tedges = P[0].n_time_bins ? P[0].n_time_bins + 1 : 0;
+    a.tally_copies = 1;
+    TransportParams b = a;
+    b.tally_copies = 2;
+    LaunchShape s{};
+    s.block = static_cast<int>(o.block);
+    s.hist_per_lane = 1;
+    s.f32 = o.precision == MCRNG_FP32;
+    s.timed = P[0].n_time_bins > 0;
+    bool fits = false;
+    return transport_chain_fits(a, b, s, &fits) == hipSuccess && fits;
+}
+
+// Histories per work unit.  The per-unit kernel pays a pause at the end of
+// each unit, so its units are few (a few per resident block); the chained
+// kernel pauses only at the end of the launch, where small units even out
+// the blocks' finishing times.
+static uint32_t default_unit_histories(const mcrng_problem* P, uint32_t n, bool chained) {
     uint64_t total = 0;
     for (uint32_t i = 0; i < n; ++i) total += P[i].n_histories;
-    uint64_t u = total / 4096;   // a few units per resident block of the device
+    uint64_t u = total / (chained ? kChainUnits : 4096);
     u = std::max<uint64_t>(u, 512);
     u = std::min<uint64_t>(u, 65536);
     return static_cast<uint32_t>(u);
@@ -839,7 +894,8 @@ extern "C" int mcrng_run_histories(mcrng_ctx* ctx, const mcrng_lcg* lcg, const m
         if ((rc = validate_problem(problems[i], i)) < 0) return rc;
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const uint32_t unit_hist = o.unit_histories ? o.unit_histories : default_unit_histories(problems, n_problems);
+    const uint32_t unit_hist =
+        o.unit_histories ? o.unit_histories : default_unit_histories(problems, n_problems, chain_planned(problems, n_problems, o));
     o.unit_histories = unit_hist;
     const uint64_t sig = signature(lcg, problems, n_problems, unit_hist);
     int warn = MCRNG_OK;
@@ -871,12 +927,33 @@ static int enqueue_run(mcrng_ctx* ctx, const LcgDev& L, const mcrng_run_opts& o,
     sh.grid = static_cast<int>(o.grid);
     sh.f32 = o.precision == MCRNG_FP32;
     sh.timed = ctx->any_timed;
+    sh.chain = 0;
+    // one problem, one history per lane, one tally copy, units of at least
+    // kChainMinPerLane histories per lane: the chained kernel, if its second
+    // tally slice costs no blocks per CU
+    const bool big_units = o.unit_histories >= kChainMinPerLane * o.block;
+    if (ctx->h_problems.size() == 1 && o.hist_per_lane == 1 && o.tally_copies == 1 &&
+        (chain_mode() == 2 || (chain_mode() == 1 && big_units))) {
+        TransportParams t2 = tp;
+        t2.tally_copies = 2;
+        bool fits = chain_mode() == 2;
+        if (!fits) HIP_TRY(transport_chain_fits(tp, t2, sh, &fits));
+        if (fits) {
+            tp = t2;
+            sh.chain = 1;
+        }
+    }
+    if (!sh.chain && chain_mode() == 2)
+        return fail(MCRNG_EINVAL, "MCRNG_TRANSPORT_CHAIN=2 and the chained kernel does not take this run");
     int dev_lds = 0;
     HIP_TRY(hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
     const size_t lds_need = transport_lds_bytes(tp, sh.f32) + transport_static_lds_bytes(sh.block);
     if (lds_need > static_cast<size_t>(dev_lds))
         return fail(MCRNG_EINVAL, "LDS needed (%zu bytes) exceeds the device's %d", lds_need, dev_lds);
+    ctx->last_kernel = sh.chain ? "k_transport_chain" : "k_transport";
     HIP_TRY(launch_fill_u32(tp.unit_counter, 16, 0u, st));
+    // the chained kernel writes each block's diagnostics to one of its units
+    if (sh.chain) HIP_TRY(launch_fill_u64(tp.unit_diag, static_cast<uint64_t>(tp.n_units) * kNDiag, 0ull, st));
     HIP_TRY(launch_transport(tp, sh, st, nullptr));
     return MCRNG_OK;
 }
@@ -994,6 +1071,7 @@ static uint64_t opts_key(uint64_t tables_sig, const mcrng_run_opts& o) {
 static int run_prepared(mcrng_ctx* ctx, const LcgDev& L, const mcrng_run_opts& o, hipStream_t st) {
     HIP_TRY(hipEventRecord(ctx->ev0, st));
     if (o.schedule == MCRNG_SCHED_EVENT) {
+        ctx->last_kernel = "k_event_step";
         int rc = run_event_schedule(ctx, L, o, st);
         if (rc < 0) return rc;
     } else if (o.use_graph) {
@@ -1016,7 +1094,9 @@ static int run_prepared(mcrng_ctx* ctx, const LcgDev& L, const mcrng_run_opts& o
             (void)hipGraphDestroy(g);
             if (e != hipSuccess) return fail(MCRNG_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
             it = ctx->graphs.emplace(key, ex).first;
+            ctx->graph_kernel[key] = ctx->last_kernel;
         }
+        ctx->last_kernel = ctx->graph_kernel[key];
         HIP_TRY(hipGraphLaunch(it->second, st));
     } else {
         int rc = enqueue_run(ctx, L, o, st);
@@ -1026,6 +1106,8 @@ static int run_prepared(mcrng_ctx* ctx, const LcgDev& L, const mcrng_run_opts& o
     ctx->timing_valid = true;
     return MCRNG_OK;
 }
+
+extern "C" const char* mcrng_last_run_kernel(const mcrng_ctx* ctx) { return ctx ? ctx->last_kernel : ""; }
 
 extern "C" float mcrng_last_run_ms(mcrng_ctx* ctx) {
     if (!ctx || !ctx->timing_valid) return -1.0f;
@@ -1143,7 +1225,8 @@ extern "C" int mcrng_run_histories_noalloc(const mcrng_lcg* lcg, const mcrng_pro
         b->cap = 0;
     }
     hipStream_t st = static_cast<hipStream_t>(stream);
-    o.unit_histories = o.unit_histories ? o.unit_histories : default_unit_histories(problems, n_problems);
+    if (!o.unit_histories)
+        o.unit_histories = default_unit_histories(problems, n_problems, chain_planned(problems, n_problems, o));
     int warn = MCRNG_OK;
     if ((rc = build_tables(ctx, L, problems, n_problems, o.unit_histories, st, &warn)) < 0) return rc;
     if ((rc = enqueue_run(ctx, L, o, st)) < 0) return rc;
@@ -1216,7 +1299,7 @@ extern "C" int mcrng_autotune(mcrng_ctx* ctx, const mcrng_lcg* lcg, const mcrng_
     if ((rc = try_field(&mcrng_run_opts::tally_copies, {1, 2})) < 0) return rc;
     if (cur.schedule == MCRNG_SCHED_HISTORY)
         if ((rc = try_field(&mcrng_run_opts::coll_batch, {1, 16, 24, 32, 36, 40, 48})) < 0) return rc;
-    const uint32_t u0 = default_unit_histories(problems, n_problems);
+    const uint32_t u0 = default_unit_histories(problems, n_problems, chain_planned(problems, n_problems, cur));
     if ((rc = try_field(&mcrng_run_opts::unit_histories, {u0 / 4 > 256 ? u0 / 4 : 256, u0, u0 * 4})) < 0) return rc;
     if (cur.unit_histories == 0) cur.unit_histories = u0;
     cur.use_graph = b0.use_graph;

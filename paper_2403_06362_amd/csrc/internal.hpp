@@ -135,12 +135,18 @@ struct LaunchShape {
     int grid;            // 0 = fill the device
     int f32;             // 1 = FP32 flight mode
     int timed;           // 1 = time-dependent problems present
+    int chain;           // 1 = k_transport_chain (one problem, one history per lane, two tally slices)
 };
 
 size_t transport_lds_bytes(const TransportParams& p, int f32);
 // LDS k_transport declares statically for a block size (skip table, the
 // waves' rings of seeded histories, block words).
 size_t transport_static_lds_bytes(int block);
+// Whether k_transport_chain (with `chained`, whose tally_copies is 2: the
+// block's two unit slices) keeps at least k_transport's blocks per CU with
+// `single` (one history per lane).
+hipError_t transport_chain_fits(const TransportParams& single, const TransportParams& chained, const LaunchShape& s,
+                                bool* fits);
 hipError_t launch_transport(const TransportParams& p, const LaunchShape& s, hipStream_t st,
                             int* grid_used);
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st);

@@ -70,8 +70,9 @@ size_t transport_lds_bytes(const TransportParams& p, int f32) {
 }
 
 size_t transport_static_lds_bytes(int block) {
+    // skip table, rings, ring slice tags (k_transport_chain), block words
     return static_cast<size_t>(kStrideDigits) * kStrideRadix * 2 * sizeof(uint64_t) +
-           static_cast<size_t>(block / 64) * 128 * sizeof(uint64_t) + 256;
+           static_cast<size_t>(block / 64) * 128 * (sizeof(uint64_t) + 1) + 512;
 }
 
 // Phase of a lane's history slot.
@@ -254,7 +255,7 @@ __global__ void __launch_bounds__(BLOCK, (H == 1) ? ((F32 || !TIMED) ? 7 : 6) : 
                     // lane), so that a refill is an LDS read
                     uint32_t base = 0;
                     if (lane == 0) base = atomicAdd(&s_next, 64u);
-                    base = __shfl(base, 0);
+                    base = __builtin_amdgcn_readfirstlane(base);
                     if (base + 64u >= U.count) unit_taken = true;
                     const uint32_t got = base < U.count ? (U.count - base < 64u ? U.count - base : 64u) : 0u;
                     if (lane < got) ring[(r_filled + lane) & 127u] = stream_start(P.lcg, S, U.j0 + base + lane);
@@ -336,6 +337,372 @@ __global__ void __launch_bounds__(BLOCK, (H == 1) ? ((F32 || !TIMED) ? 7 : 6) : 
     }
 }
 
+// Chained units (a set of one problem, one history per lane).  In k_transport
+// a block's lanes fall idle while the slowest histories of its unit finish
+// (history lengths are heavy-tailed: the long-chain slab has a median of 23
+// events and a longest of about 1750), and every block waits for its last
+// unit at the end of the launch.  Here a block holds two units at once, each
+// with its own LDS tally slice: once every history of the feeding unit has
+// been handed out, the block takes its next unit into the other slice and
+// the lanes go on without a pause.  A unit's slice is written to the unit's
+// HBM slot by the wave that ends its last history, and the slice is then free
+// for the block's next unit.  Each particle still runs its own operations in
+// its own order and the counts are integer sums, so every output equals
+// k_transport's.  The problem's diagnostics are summed over the block's
+// units and written to the block's last unit (the per-unit words start at
+// zero; the reduction sums a problem's units).
+//
+// Block state in LDS (only the lane-0 of a wave touches it, with
+// workgroup-scope atomics):
+//   s_w     bit s (s = 0, 1): slice s holds a unit; kWant: the feeding unit
+//           has been handed out and the block wants its next unit; kNoMore:
+//           the launch's counter has passed its last unit
+//   s_feed  (claim number << 1) | slice of the unit handed out now, or kNone
+//   s_cs[s] the unit in slice s: its histories, first index, HBM slot, the
+//           histories not yet ended, and (claim number << 32) | handed out
+// Claims are serial: kWant is set once per unit, by the wave that hands out
+// its last histories, and cleared by the compare-exchange that takes a free
+// slice, so exactly one wave claims; that wave is the one that finds both
+// conditions (kWant set, a slice free), whichever of the two came last.
+namespace chain {
+constexpr uint32_t kWant = 4u, kNoMore = 8u, kNone = 0xffffffffu;
+struct Slot {
+    uint64_t j0;
+    uint64_t hslot;
+    uint64_t next;     // (claim number << 32) | histories handed out
+    uint32_t count;
+    uint32_t alive;
+};
+}  // namespace chain
+
+#define CH_ACQ_REL(op, p, v) __hip_atomic_##op((p), (v), __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP)
+
+template <bool F32, bool TIMED, int BLOCK>
+__global__ void __launch_bounds__(BLOCK, (F32 || !TIMED) ? 7 : 6) k_transport_chain(TransportParams P) {
+    using R = typename Particle<F32>::R;
+    using chain::kNone;
+    using chain::kNoMore;
+    using chain::kWant;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ uint64_t s_skip[kStrideDigits * kStrideRadix * 2];
+    __shared__ uint64_t s_ring[BLOCK / 64][128];
+    __shared__ uint8_t s_rslice[BLOCK / 64][128];   // the slice of each ring entry's unit
+    __shared__ chain::Slot s_cs[2];
+    __shared__ uint32_t s_w, s_feed, s_seq, s_last_ui;
+    __shared__ unsigned long long s_diag[kNDiag];
+
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & 63u;
+    const uint32_t wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+
+    uint64_t* tally_all = reinterpret_cast<uint64_t*>(smem);
+    size_t off = align16(static_cast<size_t>(P.tally_copies) * P.max_slice * 2 * sizeof(uint64_t));
+    R* l_edge = reinterpret_cast<R*>(smem + off);
+    off += align16((P.max_cells + 1) * sizeof(R));
+    R* l_sig = reinterpret_cast<R*>(smem + off);
+    off += align16(P.max_cells * sizeof(R));
+    R* l_rsig = reinterpret_cast<R*>(smem + off);
+    off += align16(P.max_cells * sizeof(R));
+    double* l_scat = reinterpret_cast<double*>(smem + off);
+    off += align16(P.max_cells * sizeof(double));
+    int32_t* l_bin = reinterpret_cast<int32_t*>(smem + off);
+    off += align16(P.max_cells * sizeof(int32_t));
+    R* l_tedge = reinterpret_cast<R*>(smem + off);
+
+    const R* g_edge;
+    const R* g_sig;
+    const R* g_tedge;
+    if constexpr (F32) {
+        g_edge = P.edges32;
+        g_sig = P.sig32;
+        g_tedge = P.tedges32;
+    } else {
+        g_edge = P.edges64;
+        g_sig = P.sig64;
+        g_tedge = P.tedges64;
+    }
+
+    const DevProblem PR = P.problems[0];
+    const uint32_t slice = PR.slice_bins;
+    uint64_t* const tsl0 = tally_all;
+    uint64_t* const tsl1 = tally_all + static_cast<size_t>(P.max_slice) * 2;
+    for (uint32_t i = tid; i <= PR.n_cells; i += BLOCK) l_edge[i] = g_edge[PR.edge_off + i];
+    for (uint32_t i = tid; i < PR.n_cells; i += BLOCK) {
+        const R sg = g_sig[PR.cell_off + i];
+        l_sig[i] = sg;
+        l_rsig[i] = recip_refined(sg);
+        l_scat[i] = P.scat64[PR.cell_off + i];
+        l_bin[i] = P.cbin[PR.cell_off + i];
+    }
+    if (TIMED)
+        for (uint32_t i = tid; i <= PR.n_time_bins; i += BLOCK) l_tedge[i] = g_tedge[PR.tedge_off + i];
+    if (PR.seed_kind == SEED_STRIDE)
+        for (uint32_t i = tid; i < PR.stride_digits * kStrideRadix * 2u; i += BLOCK) s_skip[i] = PR.table[i];
+    for (uint32_t i = tid; i < 2u * slice; i += BLOCK) {
+        tsl0[i] = 0ull;
+        tsl1[i] = 0ull;
+    }
+    if (tid < kNDiag) s_diag[tid] = 0;
+
+    // lane 0 of a wave: puts the launch's next unit into free slice f
+    auto take_unit = [&](uint32_t f) {
+        const uint32_t pos = atomicAdd(P.unit_counter, 1u);
+        if (pos >= P.n_units) {
+            CH_ACQ_REL(fetch_or, &s_w, kNoMore);
+            CH_ACQ_REL(fetch_and, &s_w, ~(1u << f));
+            return;
+        }
+        const uint32_t ui = P.order[pos];
+        const WorkUnit U = P.units[ui];
+        const uint32_t seq = s_seq + 1u;
+        s_seq = seq;
+        s_last_ui = ui;
+        s_cs[f].j0 = U.j0;
+        s_cs[f].hslot = U.slot;
+        s_cs[f].count = U.count;
+        s_cs[f].alive = U.count;
+        s_cs[f].next = static_cast<uint64_t>(seq) << 32;
+        __hip_atomic_store(&s_feed, (seq << 1) | f, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
+    // lane 0 of a wave: claims a free slice if the block wants a unit
+    auto try_claim = [&]() {
+        uint32_t old = __hip_atomic_load(&s_w, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        for (;;) {
+            if (!(old & kWant) || (old & kNoMore)) return;
+            const int f = !(old & 1u) ? 0 : (!(old & 2u) ? 1 : -1);
+            if (f < 0) return;
+            if (__hip_atomic_compare_exchange_strong(&s_w, &old, (old & ~kWant) | (1u << f), __ATOMIC_ACQ_REL,
+                                                     __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+                take_unit(static_cast<uint32_t>(f));
+                return;
+            }
+        }
+    };
+    if (tid == 0) {
+        s_w = 1u;
+        s_seq = 0;
+        s_last_ui = kNone;
+        s_feed = kNone;
+        take_unit(0);
+    }
+    __syncthreads();
+
+    CellsLds<F32> C;
+    C.edge = l_edge;
+    C.sig = l_sig;
+    C.rsig = l_rsig;
+    C.scat = l_scat;
+    C.bin = l_bin;
+    C.tedge = l_tedge;
+    C.n_cells = static_cast<int32_t>(PR.n_cells);
+    C.n_time_bins = static_cast<int32_t>(PR.n_time_bins);
+    C.n_space_bins = static_cast<int32_t>(PR.n_space_bins);
+    SeedDev S;
+    S.kind = static_cast<int>(PR.seed_kind);
+    S.stride_digits = PR.stride_digits;
+    S.base = PR.seed_base;
+    S.first_index = PR.first_index;
+    S.table = s_skip;
+    const uint64_t stride_q = PR.stride_q;
+    uint64_t* const ring = s_ring[wid];
+    uint8_t* const rsl = s_rslice[wid];
+
+    // The lanes in `ended` have ended their histories.  A wave counts its
+    // ended histories per slice and subtracts them from the unit's live
+    // count once none of its lanes runs a history of that slice (so about
+    // once per unit and wave, not at every end); the wave whose subtraction
+    // reaches zero writes the unit's slice to HBM, clears it and frees it.
+    uint64_t live = 0;     // wave-uniform: lanes running a history
+    uint64_t s1mask = 0;   // wave-uniform: lanes whose history is in slice 1
+    uint32_t acc0 = 0, acc1 = 0;
+    auto report = [&](uint32_t sl, uint32_t n) {
+        uint32_t old = 0;
+        if (lane == 0) old = CH_ACQ_REL(fetch_sub, &s_cs[sl].alive, n);
+        old = __builtin_amdgcn_readfirstlane(old);
+        if (old != n) return;
+        uint64_t* t = sl ? tsl1 : tsl0;
+        uint64_t* dst = P.partial + s_cs[sl].hslot;
+        for (uint32_t i = lane; i < 2u * slice; i += 64u) {
+            dst[i] = t[i];
+            t[i] = 0ull;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        if (lane == 0) {
+            CH_ACQ_REL(fetch_and, &s_w, ~(1u << sl));
+            try_claim();
+        }
+        __builtin_amdgcn_wave_barrier();
+    };
+    auto ends = [&](uint64_t ended) {
+        const uint32_t e1 = static_cast<uint32_t>(__popcll(ended & s1mask));
+        acc1 += e1;
+        acc0 += static_cast<uint32_t>(__popcll(ended)) - e1;
+        live &= ~ended;
+        s1mask &= ~ended;
+        if (acc0 != 0 && (live & ~s1mask) == 0) {
+            report(0, acc0);
+            acc0 = 0;
+        }
+        if (acc1 != 0 && (live & s1mask) == 0) {
+            report(1, acc1);
+            acc1 = 0;
+        }
+    };
+    // seeds up to 64 histories of the feeding unit into the ring; returns
+    // false when no unit is feeding or it has been handed out
+    uint32_t r_next = 0, r_filled = 0;   // wave-uniform: the ring holds [r_next, r_filled)
+    auto fetch = [&]() -> bool {
+        uint32_t fd = 0;
+        uint64_t old = 0;
+        if (lane == 0) {
+            fd = __hip_atomic_load(&s_feed, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (fd != kNone) old = CH_ACQ_REL(fetch_add, &s_cs[fd & 1u].next, 64ull);
+        }
+        fd = __builtin_amdgcn_readfirstlane(fd);
+        if (fd == kNone) return false;
+        const uint32_t gen = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(old >> 32));
+        if (gen != (fd >> 1)) return false;   // the unit was replaced
+        const uint32_t f = fd & 1u;
+        const uint32_t base = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(old));
+        const uint32_t cnt = __builtin_amdgcn_readfirstlane(s_cs[f].count);
+        if (base >= cnt) return false;
+        const uint32_t got = cnt - base < 64u ? cnt - base : 64u;
+        if (lane < got) {
+            ring[(r_filled + lane) & 127u] = stream_start(P.lcg, S, s_cs[f].j0 + base + lane);
+            rsl[(r_filled + lane) & 127u] = static_cast<uint8_t>(f);
+        }
+        r_filled += got;
+        if (base + 64u >= cnt && lane == 0) {
+            // this wave handed out the unit's last histories
+            __hip_atomic_store(&s_feed, kNone, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            CH_ACQ_REL(fetch_or, &s_w, kWant);
+            try_claim();
+        }
+        __builtin_amdgcn_wave_barrier();
+        return true;
+    };
+
+    Particle<F32> p;
+    int ph = PH_EMPTY;
+    uint64_t* tl = tsl0;   // the slice of the lane's history
+    uint64_t w_events = 0, w_colls = 0;
+    uint32_t w_ll = 0, w_lr = 0, w_abs = 0, w_cen = 0;
+    uint32_t l_maxd = 0, l_over = 0;
+    bool starved = false;   // wave-uniform: the last refill found no history to take
+
+    for (;;) {
+        {
+            const bool g = ph == PH_GEOM;
+            w_events += wave_count(g);
+            int r = END_NONE;
+            if (g) {
+                r = geom_step<F32, TIMED>(p, C, tl);
+                if (r == STEP_COLLIDE) {
+                    ph = PH_COLL;
+                } else if (r != END_NONE) {
+                    ph = PH_EMPTY;
+                    const uint32_t d = p.hdraws;
+                    l_maxd = d > l_maxd ? d : l_maxd;
+                    if (stride_q != 0 && d > stride_q) l_over++;
+                }
+            }
+            const uint64_t ended = __builtin_amdgcn_ballot_w64(r > END_NONE);
+            if (ended != 0) {
+                w_ll += wave_count(r == END_LEAK_LEFT);
+                w_lr += wave_count(r == END_LEAK_RIGHT);
+                if (TIMED) w_cen += wave_count(r == END_CENSUS);
+                ends(ended);
+            }
+        }
+        const uint32_t nwait = wave_count(ph == PH_COLL || (ph == PH_EMPTY && !starved));
+        const uint32_t ngeom = wave_count(ph == PH_GEOM);
+        if (nwait < P.coll_batch && ngeom != 0) continue;
+
+        // collision pass: refill the empty lanes first
+        const uint64_t need = __builtin_amdgcn_ballot_w64(ph == PH_EMPTY);
+        if (need != 0) {
+            const uint32_t nneed = static_cast<uint32_t>(__popcll(need));
+            starved = false;
+            while (r_filled - r_next < nneed) {
+                if (!fetch()) {
+                    starved = true;
+                    break;
+                }
+            }
+            const uint32_t avail = r_filled - r_next;
+            const uint32_t take = avail < nneed ? avail : nneed;
+            bool in1 = false;
+            if (ph == PH_EMPTY) {
+                const uint32_t rank = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(need >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(need), 0u));
+                if (rank < take) {
+                    const uint32_t e = (r_next + rank) & 127u;
+                    init_particle_at<F32, TIMED>(p, C, ring[e]);
+                    in1 = rsl[e] != 0;
+                    tl = in1 ? tsl1 : tsl0;
+                    ph = PH_NEW;
+                }
+            }
+            s1mask |= __builtin_amdgcn_ballot_w64(in1);
+            live = __builtin_amdgcn_ballot_w64(ph != PH_EMPTY);
+            r_next += take;
+            __builtin_amdgcn_wave_barrier();
+        }
+        if (live == 0) {
+            // nothing to run: done once the launch has no unit left, else
+            // wait for a unit (another wave frees a slice or is claiming)
+            uint32_t w = 0;
+            if (lane == 0) w = __hip_atomic_load(&s_w, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            w = __builtin_amdgcn_readfirstlane(w);
+            if ((w & kNoMore) && r_next == r_filled) break;
+            __builtin_amdgcn_s_sleep(4);
+        }
+        {
+            const bool cl = ph == PH_COLL;
+            w_colls += wave_count(cl);
+            bool absorbed = false;
+            if (cl) {
+                if (collide<F32>(p, C, P.lcg) != END_NONE) {
+                    absorbed = true;
+                    ph = PH_EMPTY;
+                    const uint32_t d = p.hdraws;
+                    l_maxd = d > l_maxd ? d : l_maxd;
+                    if (stride_q != 0 && d > stride_q) l_over++;
+                } else {
+                    ph = PH_NEW;
+                }
+            }
+            const uint64_t ab = __builtin_amdgcn_ballot_w64(absorbed);
+            if (ab != 0) {
+                w_abs += static_cast<uint32_t>(__popcll(ab));
+                ends(ab);
+            }
+            if (ph == PH_NEW) {
+                sample_tau<F32>(p, P.lcg);
+                ph = PH_GEOM;
+            }
+        }
+    }
+
+    // the problem's diagnostics: the block's sums, into its last unit's words
+    if (lane == 0) {
+        const unsigned long long nend = static_cast<unsigned long long>(w_ll) + w_lr + w_abs + w_cen;
+        atomicAdd(&s_diag[D_HISTORIES], nend);
+        atomicAdd(&s_diag[D_LEAK_LEFT], static_cast<unsigned long long>(w_ll));
+        atomicAdd(&s_diag[D_LEAK_RIGHT], static_cast<unsigned long long>(w_lr));
+        atomicAdd(&s_diag[D_ABSORBED], static_cast<unsigned long long>(w_abs));
+        atomicAdd(&s_diag[D_CENSUS], static_cast<unsigned long long>(w_cen));
+        atomicAdd(&s_diag[D_EVENTS], static_cast<unsigned long long>(w_events));
+        atomicAdd(&s_diag[D_COLLISIONS], static_cast<unsigned long long>(w_colls));
+        atomicAdd(&s_diag[D_DRAWS], nend + 3ull * w_colls - 2ull * w_abs);
+    }
+    atomicMax(&s_diag[D_MAX_DRAWS], static_cast<unsigned long long>(l_maxd));
+    atomicAdd(&s_diag[D_OVER_STRIDE], static_cast<unsigned long long>(l_over));
+    __syncthreads();
+    if (tid < kNDiag && s_last_ui != kNone) P.unit_diag[static_cast<size_t>(s_last_ui) * kNDiag + tid] = s_diag[tid];
+}
+#undef CH_ACQ_REL
+
 template <bool F32, bool TIMED, int H, int BLOCK>
 static hipError_t launch_t(const TransportParams& p, int grid, size_t lds, hipStream_t st, int* used) {
     auto kern = k_transport<F32, TIMED, H, BLOCK>;
@@ -382,9 +749,96 @@ static hipError_t launch_h(const TransportParams& p, const LaunchShape& s, size_
     }
 }
 
+// Blocks of `kern` that fit on one CU with `lds` bytes of dynamic LDS.
+static hipError_t blocks_per_cu(const void* kern, int block, size_t lds, int* out) {
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+        if (e != hipSuccess) return e;
+    }
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, kern, block, lds);
+}
+
+template <bool F32, bool TIMED, int BLOCK>
+static hipError_t launch_chain_t(const TransportParams& p, int grid, size_t lds, hipStream_t st, int* used) {
+    auto kern = k_transport_chain<F32, TIMED, BLOCK>;
+    if (grid <= 0) {
+        int dev = 0, cus = 0, per_cu = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        e = blocks_per_cu(reinterpret_cast<const void*>(kern), BLOCK, lds, &per_cu);
+        if (e != hipSuccess) return e;
+        if (per_cu < 1) per_cu = 1;
+        grid = cus * per_cu;
+    } else if (lds > 64 * 1024) {
+        int per_cu = 0;
+        hipError_t e = blocks_per_cu(reinterpret_cast<const void*>(kern), BLOCK, lds, &per_cu);
+        if (e != hipSuccess) return e;
+    }
+    if (static_cast<uint32_t>(grid) > p.n_units) grid = static_cast<int>(p.n_units);
+    if (grid < 1) grid = 1;
+    if (used) *used = grid;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(BLOCK), lds, st, p);
+    return hipGetLastError();
+}
+
+template <bool F32, bool TIMED>
+static hipError_t launch_chain_b(const TransportParams& p, const LaunchShape& s, size_t lds, hipStream_t st,
+                                 int* used) {
+    switch (s.block) {
+        case 64: return launch_chain_t<F32, TIMED, 64>(p, s.grid, lds, st, used);
+        case 128: return launch_chain_t<F32, TIMED, 128>(p, s.grid, lds, st, used);
+        case 512: return launch_chain_t<F32, TIMED, 512>(p, s.grid, lds, st, used);
+        case 1024: return launch_chain_t<F32, TIMED, 1024>(p, s.grid, lds, st, used);
+        default: return launch_chain_t<F32, TIMED, 256>(p, s.grid, lds, st, used);
+    }
+}
+
+template <bool F32, bool TIMED, int BLOCK>
+static hipError_t chain_fits_t(const TransportParams& a, const TransportParams& b, int f32, bool* fits) {
+    int na = 0, nb = 0;
+    hipError_t e = blocks_per_cu(reinterpret_cast<const void*>(k_transport<F32, TIMED, 1, BLOCK>), BLOCK,
+                                 transport_lds_bytes(a, f32), &na);
+    if (e != hipSuccess) return e;
+    e = blocks_per_cu(reinterpret_cast<const void*>(k_transport_chain<F32, TIMED, BLOCK>), BLOCK,
+                      transport_lds_bytes(b, f32), &nb);
+    if (e != hipSuccess) return e;
+    *fits = nb >= 1 && nb >= na;
+    return hipSuccess;
+}
+
+template <bool F32, bool TIMED>
+static hipError_t chain_fits_b(const TransportParams& a, const TransportParams& b, const LaunchShape& s, bool* fits) {
+    switch (s.block) {
+        case 64: return chain_fits_t<F32, TIMED, 64>(a, b, s.f32, fits);
+        case 128: return chain_fits_t<F32, TIMED, 128>(a, b, s.f32, fits);
+        case 512: return chain_fits_t<F32, TIMED, 512>(a, b, s.f32, fits);
+        case 1024: return chain_fits_t<F32, TIMED, 1024>(a, b, s.f32, fits);
+        default: return chain_fits_t<F32, TIMED, 256>(a, b, s.f32, fits);
+    }
+}
+
+hipError_t transport_chain_fits(const TransportParams& single, const TransportParams& chained, const LaunchShape& s,
+                                bool* fits) {
+    *fits = false;
+    if (s.f32)
+        return s.timed ? chain_fits_b<true, true>(single, chained, s, fits)
+                       : chain_fits_b<true, false>(single, chained, s, fits);
+    return s.timed ? chain_fits_b<false, true>(single, chained, s, fits)
+                   : chain_fits_b<false, false>(single, chained, s, fits);
+}
+
 hipError_t launch_transport(const TransportParams& p, const LaunchShape& s, hipStream_t st, int* grid_used) {
     if (p.n_units == 0) return hipSuccess;
     const size_t lds = transport_lds_bytes(p, s.f32);
+    if (s.chain) {
+        if (s.f32)
+            return s.timed ? launch_chain_b<true, true>(p, s, lds, st, grid_used)
+                           : launch_chain_b<true, false>(p, s, lds, st, grid_used);
+        return s.timed ? launch_chain_b<false, true>(p, s, lds, st, grid_used)
+                       : launch_chain_b<false, false>(p, s, lds, st, grid_used);
+    }
     if (s.f32) {
         return s.timed ? launch_h<true, true>(p, s, lds, st, grid_used)
                        : launch_h<true, false>(p, s, lds, st, grid_used);

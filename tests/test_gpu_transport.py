@@ -92,10 +92,61 @@ def test_launch_shapes_bit_identical(M, ctx, orc):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
+def test_chained_units_bit_identical(M, ctx, orc, precision, monkeypatch):
+    """One problem, one history per lane: the chained kernel (a block holds
+    two units and starts the next while the current one's last histories
+    finish) gives the oracle's bits and the per-unit kernel's, for units of
+    one history up to thousands, fewer units than blocks and many more,
+    blocks of one wave up to sixteen, steady and time-dependent slabs, hash
+    and stride seeding."""
+    cases = [
+        (W.homogeneous(10.0, 1.3, 0.95, 37, 20011, W.hash_seeding(), n_batches=3),
+         [(256, 0), (64, 1), (256, 7), (1024, 64), (256, 65), (128, 300)]),
+        (W.long_chain(W.stride_seeding(), n_histories=30_011, n_batches=5), [(256, 0), (512, 1000)]),
+        (W.multi_region(n_histories=20_011, n_space_bins=8, n_time_bins=4), [(256, 0), (256, 97)]),
+        (W.small_slab(n_histories=5), [(256, 0), (64, 1)]),
+    ]
+    for k, (p, shapes) in enumerate(cases):
+        ref = orc.transport(p, LCG, float_mode=bool(precision), threads=8)
+        for block, unit in shapes:
+            say("chained", k, precision, block, unit)
+            monkeypatch.setenv("MCRNG_TRANSPORT_CHAIN", "2")
+            raw, flux, diag = run(M, ctx, [p], precision=precision, block=block, unit_histories=unit)
+            assert ctx.last_run_kernel() == "k_transport_chain"
+            assert raw == ref.raw, (k, block, unit)
+            assert diag[0] == ref.diag, (k, block, unit)
+            assert np.array_equal(flux, orc.flux(p, ref))
+            monkeypatch.setenv("MCRNG_TRANSPORT_CHAIN", "0")
+            raw0, _, diag0 = run(M, ctx, [p], precision=precision, block=block, unit_histories=unit)
+            assert ctx.last_run_kernel() == "k_transport"
+            assert raw0 == raw and diag0 == diag
+    # graph replays of a chained run (the unit counter and the diagnostic
+    # words are cleared by fill kernels inside the graph)
+    import torch
+    p = cases[0][0]
+    monkeypatch.setenv("MCRNG_TRANSPORT_CHAIN", "2")
+    eager = run(M, ctx, [p], precision=precision, unit_histories=300)
+    for rep in range(3):
+        say("chained graph replay", precision, rep)
+        g = run(M, ctx, [p], precision=precision, unit_histories=300, use_graph=1)
+        assert g[0] == eager[0] and g[2] == eager[2]
+        x = torch.ones(1 << 20, device="cuda:0").sum()
+        torch.cuda.synchronize()
+        assert float(x) == float(1 << 20)
+    # two problems, or two histories per lane: not chained
+    monkeypatch.setenv("MCRNG_TRANSPORT_CHAIN", "2")
+    with pytest.raises(M.McrngError):
+        run(M, ctx, [W.small_slab(), W.small_slab()])
+    with pytest.raises(M.McrngError):
+        run(M, ctx, [W.small_slab()], hist_per_lane=2)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
 def test_long_chain_parity(M, ctx, orc, precision):
     p = W.long_chain(n_histories=200_003)
     say("long chain 2e5", precision)
     raw, flux, diag = run(M, ctx, [p], precision=precision)
+    assert ctx.last_run_kernel() == "k_transport"   # units of 512 histories: too small to chain
     check_parity(orc, [p], raw, flux, diag, float_mode=bool(precision))
 
 
@@ -260,6 +311,7 @@ def test_long_chain_full_size_whole(M, ctx, orc, precision):
     p = W.long_chain()
     say("long chain full", precision)
     raw, flux, diag = run(M, ctx, [p], precision=precision)
+    assert ctx.last_run_kernel() == "k_transport_chain"
     say("long chain full: oracle", precision, host_threads())
     ref = orc.transport(p, LCG, float_mode=bool(precision), threads=host_threads())
     bad = [i for i, (a, b) in enumerate(zip(raw, ref.raw)) if a != b]

@@ -64,8 +64,9 @@ def test_noalloc_equals_context_run_twice(M):
     big = (W.batched(seeding_kind="stride", scale=2e-3)[:40] + [W.multi_region(n_histories=50_003)] +
            W.batched(scale=1e-3)[40:60])
     small = [W.small_slab(W.hash_seeding(), n_histories=3001)]
+    chained = [W.long_chain(n_histories=2_000_003, n_batches=4)]   # units of 5200: the chained kernel
     cases = ((big, {}), (small, dict(block=128, hist_per_lane=2, precision=1)),
-             (big[:7], dict(unit_histories=700, tally_copies=2)))
+             (big[:7], dict(unit_histories=700, tally_copies=2)), (chained, dict(unit_histories=5200)))
     for i, (probs, opts) in enumerate(cases):
         say("noalloc call", i, len(probs), opts)
         got = _noalloc(M, probs, **opts)
