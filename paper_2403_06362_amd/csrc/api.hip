@@ -848,7 +848,6 @@ static TransportParams make_params(mcrng_ctx* ctx, const LcgDev& L, uint32_t cop
     return tp;
 }
 
-constexpr uint32_t kMaxUnitHistories = 1u << 18;
 
 static int normalise_opts(const mcrng_run_opts* in, mcrng_run_opts* o) {
     std::memset(o, 0, sizeof *o);

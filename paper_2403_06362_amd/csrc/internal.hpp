@@ -129,6 +129,11 @@ struct TransportParams {
     uint32_t* unit_counter;      // persistent scheduling counter (zeroed before launch)
 };
 
+// Largest work unit (histories): a unit's LDS tally words take plain 64-bit
+// adds of 32-bit halves, exact while fewer than 2^32 of its scores fall in
+// one bin.
+constexpr uint32_t kMaxUnitHistories = 1u << 18;
+
 struct LaunchShape {
     int block;           // threads per block
     int hist_per_lane;   // 1, 2 or 4

@@ -358,20 +358,30 @@ __global__ void __launch_bounds__(BLOCK, (H == 1) ? ((F32 || !TIMED) ? 7 : 6) : 
 //           has been handed out and the block wants its next unit; kNoMore:
 //           the launch's counter has passed its last unit
 //   s_feed  (claim number << 1) | slice of the unit handed out now, or kNone
-//   s_cs[s] the unit in slice s: its histories, first index, HBM slot, the
-//           histories not yet ended, and (claim number << 32) | handed out
+//   s_cs[s] the unit in slice s: first index, HBM slot, the histories not
+//           yet ended, and the hand-out word (claim number, size, handed
+//           out)
 // Claims are serial: kWant is set once per unit, by the wave that hands out
 // its last histories, and cleared by the compare-exchange that takes a free
 // slice, so exactly one wave claims; that wave is the one that finds both
 // conditions (kWant set, a slice free), whichever of the two came last.
 namespace chain {
 constexpr uint32_t kWant = 4u, kNoMore = 8u, kNone = 0xffffffffu;
+// A slice's hand-out word: claim number (24 bits, mod 2^24) | the unit's
+// histories (20 bits) | histories handed out (20 bits).  A wave takes
+// histories by compare-exchange on the whole word, so a wave that read a
+// stale feed word (its unit replaced in the meantime) fails the exchange and
+// changes nothing, and a unit's size is read with the word, never from a
+// field a new claim could have overwritten.
+constexpr int kWordCount = 20, kWordGen = 40;
+constexpr uint64_t kWordMask = (1ull << kWordCount) - 1ull;
+static_assert(kMaxUnitHistories + 64u < (1u << kWordCount), "a unit's size and hand-out count fit their fields");
 struct Slot {
     uint64_t j0;
     uint64_t hslot;
-    uint64_t next;     // (claim number << 32) | histories handed out
-    uint32_t count;
+    uint64_t word;
     uint32_t alive;
+    uint32_t pad;
 };
 }  // namespace chain
 
@@ -459,9 +469,11 @@ __global__ void __launch_bounds__(BLOCK, (F32 || !TIMED) ? 7 : 6) k_transport_ch
         s_last_ui = ui;
         s_cs[f].j0 = U.j0;
         s_cs[f].hslot = U.slot;
-        s_cs[f].count = U.count;
         s_cs[f].alive = U.count;
-        s_cs[f].next = static_cast<uint64_t>(seq) << 32;
+        __hip_atomic_store(&s_cs[f].word,
+                           (static_cast<uint64_t>(seq & 0xffffffu) << chain::kWordGen) |
+                               (static_cast<uint64_t>(U.count) << chain::kWordCount),
+                           __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
         __hip_atomic_store(&s_feed, (seq << 1) | f, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     };
     // lane 0 of a wave: claims a free slice if the block wants a unit
@@ -552,20 +564,35 @@ __global__ void __launch_bounds__(BLOCK, (F32 || !TIMED) ? 7 : 6) k_transport_ch
     // false when no unit is feeding or it has been handed out
     uint32_t r_next = 0, r_filled = 0;   // wave-uniform: the ring holds [r_next, r_filled)
     auto fetch = [&]() -> bool {
-        uint32_t fd = 0;
-        uint64_t old = 0;
+        // lane 0: takes up to 64 histories of the feeding unit, if it has any left
+        uint32_t fd = kNone, base = 0, cnt = 0;
         if (lane == 0) {
             fd = __hip_atomic_load(&s_feed, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (fd != kNone) old = CH_ACQ_REL(fetch_add, &s_cs[fd & 1u].next, 64ull);
+            if (fd != kNone) {
+                uint64_t* w = &s_cs[fd & 1u].word;
+                const uint64_t gen = (fd >> 1) & 0xffffffu;
+                uint64_t cur = __hip_atomic_load(w, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                for (;;) {
+                    const uint32_t c = static_cast<uint32_t>(cur >> chain::kWordCount) & chain::kWordMask;
+                    const uint32_t h = static_cast<uint32_t>(cur) & chain::kWordMask;
+                    if ((cur >> chain::kWordGen) != gen || h >= c) {   // replaced, or handed out
+                        fd = kNone;
+                        break;
+                    }
+                    if (__hip_atomic_compare_exchange_strong(w, &cur, cur + 64u, __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
+                                                             __HIP_MEMORY_SCOPE_WORKGROUP)) {
+                        base = h;
+                        cnt = c;
+                        break;
+                    }
+                }
+            }
         }
         fd = __builtin_amdgcn_readfirstlane(fd);
         if (fd == kNone) return false;
-        const uint32_t gen = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(old >> 32));
-        if (gen != (fd >> 1)) return false;   // the unit was replaced
         const uint32_t f = fd & 1u;
-        const uint32_t base = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(old));
-        const uint32_t cnt = __builtin_amdgcn_readfirstlane(s_cs[f].count);
-        if (base >= cnt) return false;
+        base = __builtin_amdgcn_readfirstlane(base);
+        cnt = __builtin_amdgcn_readfirstlane(cnt);
         const uint32_t got = cnt - base < 64u ? cnt - base : 64u;
         if (lane < got) {
             ring[(r_filled + lane) & 127u] = stream_start(P.lcg, S, s_cs[f].j0 + base + lane);
@@ -573,7 +600,7 @@ __global__ void __launch_bounds__(BLOCK, (F32 || !TIMED) ? 7 : 6) k_transport_ch
         }
         r_filled += got;
         if (base + 64u >= cnt && lane == 0) {
-            // this wave handed out the unit's last histories
+            // this wave took the unit's last histories
             __hip_atomic_store(&s_feed, kNone, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
             CH_ACQ_REL(fetch_or, &s_w, kWant);
             try_claim();
