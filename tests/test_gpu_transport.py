@@ -141,6 +141,24 @@ def test_chained_units_bit_identical(M, ctx, orc, precision, monkeypatch):
         run(M, ctx, [W.small_slab()], hist_per_lane=2)
 
 
+def test_stride_overrun_counted(M, ctx, orc, monkeypatch):
+    """Stride seeding with a short stride (Q = 40): many histories draw past
+    their Q numbers into the next history's stream (Sec. "Repetition and
+    State Space Exhaustion").  Both transport kernels give the oracle's raw
+    sums and diagnostics, the count of such histories and the largest draw
+    count included."""
+    p = W.long_chain(W.Seeding("stride", 7, 40, 3), n_histories=40_009, n_batches=3)
+    ref = orc.transport(p, LCG, threads=8)
+    assert ref.diag["over_stride"] > 1000 and ref.diag["max_draws"] > 40
+    for mode, kernel in (("2", "k_transport_chain"), ("0", "k_transport")):
+        monkeypatch.setenv("MCRNG_TRANSPORT_CHAIN", mode)
+        say("stride overrun", kernel)
+        raw, flux, diag = run(M, ctx, [p], unit_histories=1000)
+        assert ctx.last_run_kernel() == kernel
+        assert raw == ref.raw and diag[0] == ref.diag
+        assert np.array_equal(flux, orc.flux(p, ref))
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_long_chain_parity(M, ctx, orc, precision):
     p = W.long_chain(n_histories=200_003)
