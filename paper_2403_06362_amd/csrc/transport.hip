@@ -340,8 +340,8 @@ __global__ void __launch_bounds__(BLOCK, (H == 1) ? ((F32 || !TIMED) ? 7 : 6) : 
 // Chained units (a set of one problem, one history per lane).  In k_transport
 // a block's lanes fall idle while the slowest histories of its unit finish
 // (history lengths are heavy-tailed: the long-chain slab has a median of 23
-// events and a longest of about 1750), and every block waits for its last
-// unit at the end of the launch.  Here a block holds two units at once, each
+// events and a longest of about 1750), and the block's next unit starts only
+// after a barrier.  Here a block holds two units at once, each
 // with its own LDS tally slice: once every history of the feeding unit has
 // been handed out, the block takes its next unit into the other slice and
 // the lanes go on without a pause.  A unit's slice is written to the unit's
@@ -352,7 +352,7 @@ __global__ void __launch_bounds__(BLOCK, (H == 1) ? ((F32 || !TIMED) ? 7 : 6) : 
 // units and written to the block's last unit (the per-unit words start at
 // zero; the reduction sums a problem's units).
 //
-// Block state in LDS (only the lane-0 of a wave touches it, with
+// Block state in LDS (only lane 0 of a wave touches it, with
 // workgroup-scope atomics):
 //   s_w     bit s (s = 0, 1): slice s holds a unit; kWant: the feeding unit
 //           has been handed out and the block wants its next unit; kNoMore:
