@@ -128,6 +128,12 @@ def test_tally_bins_host_only(M):
     assert M.tally_bins(probs) == 20 + 64 * 200 + 20 * 50
 
 
+def test_last_run_kernel_without_a_context(M):
+    """The name of the last run's transport kernel: empty for a NULL context
+    (host-only, no device call)."""
+    assert M.lib().mcrng_last_run_kernel(None) == b""
+
+
 def test_pulse_host_validation_without_gpu(M):
     """mcrng_run_pulse checks the generator, the problem and the options
     before it touches a context or the GPU."""
