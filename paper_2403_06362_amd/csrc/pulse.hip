@@ -206,6 +206,15 @@ __device__ __forceinline__ uint32_t lane_prefix(uint64_t mask) {
 // otherwise one 64-bit HBM atomic per distinct counter of the wave.  Either
 // way same-address atomics from every wave of the GPU, which serialise, are
 // avoided.  Called by the whole wave.
+// Lane l's value of v as a wave-uniform (scalar) value: the compiler then
+// treats what depends on it (loop exits included) as uniform, where a lane
+// shuffle's result would count as divergent.
+__device__ __forceinline__ uint64_t lane_value(uint64_t v, int l) {
+    const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(v)), l));
+    const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(v >> 32)), l));
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
 __device__ __forceinline__ void wave_tally(const PulseParams& P, int64_t tally, uint32_t lane,
                                            unsigned long long* lds_counts) {
     if (P.lds_tally) {
@@ -216,7 +225,7 @@ __device__ __forceinline__ void wave_tally(const PulseParams& P, int64_t tally, 
     uint64_t pending = __ballot(tally >= 0);
     while (pending != 0) {
         const int leader = __ffsll(static_cast<long long>(pending)) - 1;
-        const int64_t key = __shfl(tally, leader);
+        const int64_t key = static_cast<int64_t>(lane_value(static_cast<uint64_t>(tally), leader));
         const uint64_t same = __ballot(tally == key);
         if (lane == static_cast<uint32_t>(leader))
             atomicAdd(reinterpret_cast<unsigned long long*>(P.counts) + key,
@@ -284,7 +293,7 @@ __device__ __forceinline__ uint64_t bank_flush(const PulseParams& P, Stage& S, u
     __builtin_amdgcn_wave_barrier();
     uint64_t base = 0;
     if (lane == 0) base = atomicAdd(reinterpret_cast<unsigned long long*>(P.out_count), count);
-    base = __shfl(base, 0);
+    base = lane_value(base, 0);
     for (uint32_t i = lane; i < count; i += 64) bank_store(P, base + i, S.x[i], S.t[i], S.X[i], S.batch[i], S.tb[i]);
     __builtin_amdgcn_wave_barrier();
     return base + count;
@@ -304,7 +313,7 @@ __device__ __forceinline__ void census_flush(const PulseParams& P, CensusStage& 
     __builtin_amdgcn_wave_barrier();
     uint64_t base = 0;
     if (lane == 0) base = atomicAdd(reinterpret_cast<unsigned long long*>(P.cen_count), count);
-    base = __shfl(base, 0);
+    base = lane_value(base, 0);
     for (uint32_t i = lane; i < count; i += 64) {
         const uint64_t o = base + i;
         if (o < P.cen_cap) {
@@ -404,7 +413,7 @@ __global__ void __launch_bounds__(BLOCK) k_pulse_bank(PulseParams P) {
         if (need != 0 && wnext == wend && !exhausted) {
             uint64_t b = 0;
             if (lane == 0) b = atomicAdd(reinterpret_cast<unsigned long long*>(P.item_counter), chunk);
-            b = __shfl(b, 0);
+            b = lane_value(b, 0);
             if (b + chunk >= n_items) exhausted = true;
             wnext = b < n_items ? b : n_items;
             wend = b + chunk < n_items ? b + chunk : n_items;
@@ -470,7 +479,7 @@ __global__ void __launch_bounds__(BLOCK) k_pulse_bank(PulseParams P) {
                 // more than the stage holds (large multiplicities): straight to the bank
                 uint64_t base = 0;
                 if (lane == 0) base = atomicAdd(reinterpret_cast<unsigned long long*>(P.out_count), total);
-                base = __shfl(base, 0);
+                base = lane_value(base, 0);
                 for (uint32_t k = k0; k <= n; ++k)
                     bank_store(P, base + off + (k - k0), p.x, p.t, murmur_hash(k, p.X) & P.lcg.mask, p.batch, p.tb);
                 seen = base + total;
@@ -636,7 +645,7 @@ __global__ void __launch_bounds__(BLOCK) k_pulse_family(PulseParams P) {
         if (need != 0 && wnext == wend && !exhausted) {
             uint64_t b = 0;
             if (lane == 0) b = atomicAdd(reinterpret_cast<unsigned long long*>(P.family_counter), kFamilyChunk);
-            b = __shfl(b, 0);
+            b = lane_value(b, 0);
             if (b + kFamilyChunk >= n_items) exhausted = true;
             wnext = b < n_items ? b : n_items;
             wend = b + kFamilyChunk < n_items ? b + kFamilyChunk : n_items;
