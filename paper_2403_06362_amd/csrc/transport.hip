@@ -365,6 +365,12 @@ __global__ void __launch_bounds__(BLOCK, (H == 1) ? ((F32 || !TIMED) ? 7 : 6) : 
 // its last histories, and cleared by the compare-exchange that takes a free
 // slice, so exactly one wave claims; that wave is the one that finds both
 // conditions (kWant set, a slice free), whichever of the two came last.
+// A wave with nothing to run waits only while no unit is being handed out
+// and the counter is not exhausted: then kWant is set and both slices are
+// busy (or a claim is under way), a busy slice's live histories run in other
+// waves' lanes, the last of them frees the slice and that wave claims.  So
+// every wave ends once the counter has passed the last unit and its own
+// lanes and ring are empty.
 namespace chain {
 constexpr uint32_t kWant = 4u, kNoMore = 8u, kNone = 0xffffffffu;
 // A slice's hand-out word: claim number (24 bits, mod 2^24) | the unit's
