@@ -240,6 +240,7 @@ def test_event_schedule_matches_oracle_and_history(M, ctx, orc, precision):
     for bank, unit in ((0, 0), (10_000, 3_001), (4_000, 4_096)):
         say("event schedule", precision, bank, unit)
         ev = run(M, ctx, [p], precision=precision, schedule=1, bank_size=bank, unit_histories=unit)
+        assert ctx.last_run_kernel() == "k_event_step"
         assert ev[0] == ref.raw, (bank, unit)
         assert ev[2][0] == ref.diag
         assert np.array_equal(ev[1], hist[1])
